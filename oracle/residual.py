@@ -183,8 +183,9 @@ class Setup:
         for i in range(self.S):
             expo = self.mu_hs[i] - self.vext[i] + E[i]
             G[i] = np.where(self.mask[i], self.rho_b[i] * np.exp(np.where(self.mask[i], expo, 0.0)), 0.0)
+        n3max = float(np.max(n[3])) if np.all(np.isfinite(n[3])) else math.inf
         return {"rho_hat": rho_hat, "n": n, "dphi": d, "c_hs": c_hs, "phi": phi, "c_sc": c_sc,
-                "E": E, "G": G, "n3max": float(np.max(n[3]))}
+                "E": E, "G": G, "n3max": n3max}
 
     def G(self, rho):
         return self.evaluate(rho)["G"]
@@ -193,9 +194,10 @@ class Setup:
     def sqnorm(self, u):
         """Squared weighted L2 norm over fluid nodes: sum_i sum_fluid (u_i / rho_b_i)^2."""
         tot = 0.0
-        for i in range(self.S):
-            tot += float(np.sum(np.where(self.mask[i], u[i] / self.rho_b[i], 0.0) ** 2))
-        return tot
+        with np.errstate(over="ignore", invalid="ignore"):
+            for i in range(self.S):
+                tot += float(np.sum(np.where(self.mask[i], u[i] / self.rho_b[i], 0.0) ** 2))
+        return tot if math.isfinite(tot) else math.inf   # a non-finite trial point is never accepted
 
     def residual_norm(self, sq):
         """r = sqrt(f / number of fluid nodes over all species)."""
