@@ -1,0 +1,211 @@
+/*
+ * dft.h -- C ABI of the MI355X FFT/Picard solver for three-dimensional classical
+ * density functional theory of charged hard spheres (Knepley, Karpeev, Davidovits,
+ * Eisenberg, Gillespie: "An Efficient Algorithm for Classical Density Functional
+ * Theory in Three Dimensions: Ionic Solutions").
+ *
+ * The library solves the Euler-Lagrange fixed point of the theory section,
+ *     rho_i(x) = rho_i^bath exp(beta mu_i^HS,bath - beta V_i(x) + E_i[rho](x)),
+ *     E_i = c_HS,i - beta mu_SC,i' - z_i beta e phi      (eqs. rhoEquation, excessChemicalPotential)
+ * on a periodic uniform grid.  c_HS comes from fundamental measure theory
+ * (eqs. nDef, omegaDef, muHS, Phi, conv; Appendix B spectra), the screening term from
+ * the bulk-fluid expansion (eqs. muESexpansion, CplusPsiFunc, CplusPsiHat) and phi
+ * from the finite-difference Poisson equation solved in Fourier space
+ * (eqs. Poisson, potentialSolution, potentialConstraint).  Iteration: Picard with a
+ * quadratic line search and the n3 <= 0.9 bound (nonlinear-solver section).
+ *
+ * Conventions
+ *   - Grid: n[3] = (nx, ny, nz) nodes, spacings h[3]; node (ix, iy, iz) sits at
+ *     (ix hx, iy hy, iz hz); the box is periodic with period n_d h_d.  Each n_d is
+ *     1 or 2^a 3^b with 2 <= n_d <= 1024.
+ *   - Fields are float64, laid out [species][z][y][x] (x fastest), and live in device
+ *     (HIP) memory owned by the caller.  Scalars marked "host" are host memory.
+ *   - Units: one caller length unit for h, radii and l_B; densities in unit^-3;
+ *     energies in kT (beta-scaled); charge densities in e per unit^3.
+ *   - Weighted densities are stacked as n0, n1, n2, n3, nV1(x,y,z), nV2(x,y,z).
+ *   - Every call returns a dft_status; nothing throws or aborts across the ABI.
+ *     Arguments are validated on the host before any HIP call, so the error paths
+ *     run without a GPU.  dft_last_error() gives a thread-local message.
+ *   - Work is enqueued on the stream given to dft_setup (dft_set_stream changes it).
+ *     Functions that return host scalars synchronize that stream.
+ *   - Ownership: the caller owns every device buffer (densities, potentials,
+ *     workspace, outputs); the library owns only the opaque host dft_ctx and the HIP
+ *     graph it captures.  dft_destroy never frees caller memory.
+ *   - Thread safety: one ctx per stream; distinct ctxs are independent.
+ */
+#ifndef DFT_H
+#define DFT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DFT_MAX_SPECIES 8
+#define DFT_NALPHA 10
+#define DFT_MAX_N 1024
+
+typedef struct dft_ctx dft_ctx;
+
+typedef enum dft_status {
+    DFT_OK = 0,
+    DFT_E_INVALID_ARG = 1,      /* null pointer, non-positive h or R, negative density, bad flag */
+    DFT_E_UNSUPPORTED_SIZE = 2, /* n_d not 1 or 2^a 3^b in [2, 1024], or too many species */
+    DFT_E_WORKSPACE = 3,        /* workspace missing or smaller than dft_workspace_size */
+    DFT_E_DEVICE = 4,           /* a HIP call failed */
+    DFT_E_NONFINITE = 5,        /* a non-finite value appeared in G or in the norms */
+    DFT_E_PACKING = 6,          /* max n3 >= eta_cap at the current iterate */
+    DFT_E_NOT_CONVERGED = 7,    /* max_iter reached with r > tol */
+    DFT_E_NOT_NEUTRAL = 8       /* bulk sum_k z_k rho_k not zero with electrostatics on */
+} dft_status;
+
+typedef enum dft_precision {
+    DFT_FP64 = 0,       /* every transform and product in float64 */
+    DFT_FP32_MIXED = 1  /* float32 transforms of differences from an FP64 reference state;
+                           FP64 pointwise FMT, exponent, norms and master density */
+} dft_precision;
+
+/* Flags for dft_params.flags */
+#define DFT_FLAG_ALLOW_NON_NEUTRAL 1   /* accept a non-neutral bulk (finite-difference probes) */
+#define DFT_FLAG_CUTOFF_LAMBDA     2   /* cut the screening kernel at lambda_i + lambda_j, not R_i + R_j */
+
+/*
+ * Problem statement (theory section; Appendix A for the bath).  Inline arrays keep
+ * the struct self-contained for foreign-function callers.
+ */
+typedef struct dft_params {
+    int32_t n[3];                         /* nodes along x, y, z */
+    double h[3];                          /* grid spacings, > 0 */
+    int32_t nspecies;                     /* 1 .. DFT_MAX_SPECIES */
+    double radius[DFT_MAX_SPECIES];       /* R_k = sigma_k / 2, > 0 */
+    double valence[DFT_MAX_SPECIES];      /* z_k */
+    double rho_bulk[DFT_MAX_SPECIES];     /* rho_k^bath >= 0, unit^-3 */
+    double bjerrum_length;                /* l_B = e^2 / (4 pi eps0 eps_r kT) in the length unit */
+    int32_t electrostatics;               /* 0: hard spheres only; 1: bulk-fluid screening + Poisson */
+    int32_t precision;                    /* dft_precision */
+    double eta_cap;                       /* bound on max n3 in the line search; 0 selects 0.9 */
+    int32_t flags;                        /* DFT_FLAG_* */
+} dft_params;
+
+/* Bath quantities of Appendix A, computed on the host in FP64. */
+typedef struct dft_bulk_info {
+    double mu_hs[DFT_MAX_SPECIES];   /* beta mu_k^HS,bath (eq. muHSBath) */
+    double beta_p;                   /* beta P^HS_bath (eq. HSPressure) */
+    double xi[4];                    /* xi_0 .. xi_3 */
+    double gamma;                    /* MSA Gamma (eq. Gamma), 0 without electrostatics */
+    double eta_msa;                  /* MSA eta at Gamma */
+    double omega;                    /* MSA Omega at Gamma */
+    double lambda[DFT_MAX_SPECIES];  /* lambda_k = R_k + 1/(2 Gamma) (bulk-fluid section) */
+    double mu_es[DFT_MAX_SPECIES];   /* beta mu_k^ES,bath (reporting only; cancels in G) */
+} dft_bulk_info;
+
+/* Counters kept by a ctx since dft_setup or the last dft_solve start. */
+typedef struct dft_stats {
+    int64_t iterations;      /* accepted Picard steps */
+    int64_t rejected;        /* line-search steps that did not lower the residual */
+    int64_t g_evals;         /* full residual evaluations */
+    int64_t n3_evals;        /* n3-only evaluations (step-cap path of the line search) */
+    int64_t fp64_refresh;    /* FP64 reference evaluations (FP32-mixed only) */
+    double residual;         /* r at the current iterate */
+    double alpha;            /* last accepted step */
+    double max_n3;           /* max n3 at the current iterate */
+    double step_cap;         /* current line-search step cap */
+} dft_stats;
+
+/* Message for the last non-OK status returned on this thread ("" if none). */
+const char *dft_last_error(void);
+
+/*
+ * Bath thermodynamics (Appendix A: eqs. muHSBath, HSPressure, Gamma) on the host.
+ * params: host, validated as in dft_setup.  out: host.  No GPU needed.
+ */
+dft_status dft_bulk(const dft_params *params, dft_bulk_info *out);
+
+/*
+ * Bytes of device workspace dft_setup needs for these parameters.  Host only.
+ */
+dft_status dft_workspace_size(const dft_params *params, size_t *bytes);
+
+/*
+ * Setup work done once per problem (discretization section: the bath and external
+ * potentials are computed once): validates the parameters, solves the bath (Appendix A),
+ * builds FFT plans and twiddle tables, and forms per species the fixed exponent
+ *     beta mu_k^HS,bath - beta V_k(x) - z_k beta e phi_fixed(x)
+ * (fixed charges enter the Poisson source only).
+ *   beta_vext     device [S][nz][ny][nx] float64: beta V_k; +inf marks an excluded centre.
+ *                 NULL means V = 0 everywhere.  Read during the call only.
+ *   fixed_charge  device [nz][ny][nx] float64, e / unit^3; NULL means none.  Read only.
+ *   workspace     device memory of at least dft_workspace_size bytes, 256-byte aligned,
+ *                 owned by the caller and used by the ctx until dft_destroy.
+ *   stream        hipStream_t as void* (NULL = default stream).
+ *   out           receives the new ctx (host).
+ * Errors: DFT_E_INVALID_ARG, DFT_E_UNSUPPORTED_SIZE, DFT_E_NOT_NEUTRAL, DFT_E_WORKSPACE
+ * before any HIP call; DFT_E_DEVICE if a HIP call fails.
+ */
+dft_status dft_setup(const dft_params *params, const double *beta_vext, const double *fixed_charge,
+                     void *workspace, size_t ws_bytes, void *stream, dft_ctx **out);
+
+/* Change the stream subsequent calls enqueue on. */
+dft_status dft_set_stream(dft_ctx *ctx, void *stream);
+
+/*
+ * One residual evaluation (eq. rhoEquation with eqs. conv, Phi, muHS, potentialSolution,
+ * muESexpansion): G(rho) and the norm r = sqrt(sum_k sum_fluid ((rho_k - G_k)/rho_k^b)^2 / N_fluid).
+ *   rho       device [S][N] float64 (read).
+ *   g_out     device [S][N] float64 (written; NULL to skip).
+ *   norm_out  host double (NULL to skip); if given, the stream is synchronized.
+ * Uses the ctx's precision: in FP32-mixed mode the FP32 transforms act on rho - rho_ref
+ * around the ctx's current reference state (set by dft_set_reference or dft_solve).
+ */
+dft_status dft_residual(dft_ctx *ctx, const double *rho, double *g_out, double *norm_out);
+
+/*
+ * The intermediate fields of one FP64 residual evaluation at rho, for inspection and
+ * parity tests (any output may be NULL):
+ *   n_out     device [10][N]: weighted densities n_alpha (eq. nDef via eq. conv)
+ *   dphi_out  device [10][N]: dPhi/dn_alpha (eq. Phi)
+ *   c_out     device [S][N]:  E_k = c_HS,k + c_SC,k - z_k beta e phi (the exponent's rho-dependent part)
+ *   phi_out   device [N]:     beta e phi from ions and fixed charges (eq. potentialSolution)
+ */
+dft_status dft_operators(dft_ctx *ctx, const double *rho, double *n_out, double *dphi_out,
+                         double *c_out, double *phi_out);
+
+/*
+ * FP32-mixed only: make rho the reference state (one FP64 evaluation at rho).  Later
+ * FP32 transforms act on differences from it.  No-op in FP64 mode.
+ */
+dft_status dft_set_reference(dft_ctx *ctx, const double *rho);
+
+/*
+ * One line-search Picard step (nonlinear-solver section) on rho_inout (device [S][N]),
+ * updated in place.  alpha_out: accepted step (0 if the step was rejected), host.
+ * norm_out: r at the new iterate, host.  Either may be NULL; the stream is synchronized.
+ * Consecutive calls with the same buffer reuse the Picard image of the previous step.
+ */
+dft_status dft_picard_step(dft_ctx *ctx, double *rho_inout, double *alpha_out, double *norm_out);
+
+/*
+ * Picard iteration until r <= tol or max_iter accepted steps, starting from rho_inout
+ * (device [S][N]) and leaving the last iterate there.  The step is a captured HIP graph
+ * launched in chunks; the host reads the status between chunks.  In FP32-mixed mode the
+ * FP64 reference is refreshed as the residual falls, and convergence is confirmed with
+ * an FP64 evaluation.  iters_out, norm_out: host, may be NULL.
+ * Returns DFT_E_NOT_CONVERGED, DFT_E_NONFINITE or DFT_E_PACKING on failure, leaving the
+ * last finite iterate in rho_inout.
+ */
+dft_status dft_solve(dft_ctx *ctx, double *rho_inout, double tol, int32_t max_iter,
+                     int32_t *iters_out, double *norm_out);
+
+/* Counters of the ctx (host out). */
+dft_status dft_get_stats(dft_ctx *ctx, dft_stats *out);
+
+/* Free the ctx and its graph; caller memory is untouched.  NULL is accepted. */
+dft_status dft_destroy(dft_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DFT_H */

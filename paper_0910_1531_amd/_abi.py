@@ -1,0 +1,89 @@
+"""ctypes mirror of include/dft.h.  Loading fails loudly when the HIP library is absent."""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdftpicard.so")
+
+MAX_SPECIES = 8
+NALPHA = 10
+
+DFT_OK = 0
+STATUS_NAMES = {0: "DFT_OK", 1: "DFT_E_INVALID_ARG", 2: "DFT_E_UNSUPPORTED_SIZE", 3: "DFT_E_WORKSPACE",
+                4: "DFT_E_DEVICE", 5: "DFT_E_NONFINITE", 6: "DFT_E_PACKING", 7: "DFT_E_NOT_CONVERGED",
+                8: "DFT_E_NOT_NEUTRAL"}
+DFT_FP64 = 0
+DFT_FP32_MIXED = 1
+FLAG_ALLOW_NON_NEUTRAL = 1
+FLAG_CUTOFF_LAMBDA = 2
+
+D8 = ctypes.c_double * MAX_SPECIES
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32 * 3), ("h", ctypes.c_double * 3), ("nspecies", ctypes.c_int32),
+                ("radius", D8), ("valence", D8), ("rho_bulk", D8), ("bjerrum_length", ctypes.c_double),
+                ("electrostatics", ctypes.c_int32), ("precision", ctypes.c_int32), ("eta_cap", ctypes.c_double),
+                ("flags", ctypes.c_int32)]
+
+
+class BulkInfo(ctypes.Structure):
+    _fields_ = [("mu_hs", D8), ("beta_p", ctypes.c_double), ("xi", ctypes.c_double * 4),
+                ("gamma", ctypes.c_double), ("eta_msa", ctypes.c_double), ("omega", ctypes.c_double),
+                ("lambda_", D8), ("mu_es", D8)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int64), ("rejected", ctypes.c_int64), ("g_evals", ctypes.c_int64),
+                ("n3_evals", ctypes.c_int64), ("fp64_refresh", ctypes.c_int64), ("residual", ctypes.c_double),
+                ("alpha", ctypes.c_double), ("max_n3", ctypes.c_double), ("step_cap", ctypes.c_double)]
+
+
+class DftError(RuntimeError):
+    def __init__(self, status, where, msg):
+        super().__init__(f"{where}: {STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+_vp = ctypes.c_void_p
+_dp = ctypes.POINTER(ctypes.c_double)
+# (name, argtypes) in the order of include/dft.h
+SIGNATURES = [
+    ("dft_last_error", []),
+    ("dft_bulk", [ctypes.POINTER(Params), ctypes.POINTER(BulkInfo)]),
+    ("dft_workspace_size", [ctypes.POINTER(Params), ctypes.POINTER(ctypes.c_size_t)]),
+    ("dft_setup", [ctypes.POINTER(Params), _vp, _vp, _vp, ctypes.c_size_t, _vp, ctypes.POINTER(_vp)]),
+    ("dft_set_stream", [_vp, _vp]),
+    ("dft_residual", [_vp, _vp, _vp, _dp]),
+    ("dft_operators", [_vp, _vp, _vp, _vp, _vp, _vp]),
+    ("dft_set_reference", [_vp, _vp]),
+    ("dft_picard_step", [_vp, _vp, _dp, _dp]),
+    ("dft_solve", [_vp, _vp, ctypes.c_double, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), _dp]),
+    ("dft_get_stats", [_vp, ctypes.POINTER(Stats)]),
+    ("dft_destroy", [_vp]),
+]
+
+_lib = None
+
+
+def load():
+    """Load libdftpicard.so (built by paper_0910_1531_amd.build); raise if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_0910_1531_amd.build`; "
+                          "there is no fallback path")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, args in SIGNATURES:
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_char_p if name == "dft_last_error" else ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def check(status, where):
+    if status != DFT_OK:
+        raise DftError(status, where, load().dft_last_error().decode())
+    return status

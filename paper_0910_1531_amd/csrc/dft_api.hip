@@ -1,0 +1,744 @@
+// C ABI of the solver (include/dft.h): context, workspace layout, the residual
+// evaluation sequence, the device-controlled line-search step, HIP graph capture and
+// the solve loop.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "dft_host.h"
+#include "dft_kernels.h"
+
+using namespace dft;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+dft_status fail(dft_status st, const std::string &msg) {
+    g_last_error = msg;
+    return st;
+}
+
+struct HipError : std::runtime_error {
+    using std::runtime_error::runtime_error;
+};
+
+#define HIPCHK(expr)                                                                              \
+    do {                                                                                          \
+        hipError_t e_ = (expr);                                                                   \
+        if (e_ != hipSuccess) throw HipError(std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// ------------------------------------------------------------------ workspace layout
+struct Layout {
+    size_t consts, state, tw64[3], tw32[3], fpart, mpart, fflag, mflag, specA, specB;
+    size_t base, rho0, g0, ga, gb, gs, rho_t, rho_ref, lp, nref, phi_fix, count_part;
+    size_t total;
+    int red_cap;
+    int count_blocks;
+};
+
+size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
+
+Layout make_layout(const dft_params *p) {
+    Layout L;
+    const long long N = (long long)p->n[0] * p->n[1] * p->n[2];
+    const long long Kx = p->n[0] / 2 + 1;
+    const long long NC = Kx * p->n[1] * p->n[2];
+    const int S = p->nspecies;
+    Geo g{};
+    g.nx = p->n[0];
+    g.ny = p->n[1];
+    g.nz = p->n[2];
+    g.S = S;
+    L.red_cap = std::max(x2_blocks(g), x3_blocks(g)) + 16;
+    L.count_blocks = (int)std::min<long long>((S * N + 255) / 256, 4096);
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
+    L.consts = take(sizeof(Consts));
+    L.state = take(sizeof(DevState));
+    for (int d = 0; d < 3; ++d) {
+        L.tw64[d] = take(2 * sizeof(double) * p->n[d]);
+        L.tw32[d] = take(2 * sizeof(float) * p->n[d]);
+    }
+    L.fpart = take(sizeof(double) * L.red_cap);
+    L.mpart = take(sizeof(double) * L.red_cap);
+    L.fflag = take(sizeof(int) * L.red_cap);
+    L.mflag = take(sizeof(int) * L.red_cap);
+    L.count_part = take(sizeof(double) * L.count_blocks);
+    L.specA = take(2 * sizeof(double) * NC * S);
+    L.specB = take(2 * sizeof(double) * NC * DFT_NALPHA);
+    const size_t F = sizeof(double) * (size_t)N * S;
+    L.base = take(F);
+    L.rho0 = take(F);
+    L.g0 = take(F);
+    L.ga = take(F);
+    L.gb = take(F);
+    L.gs = take(F);
+    L.rho_t = take(F);
+    L.phi_fix = take(sizeof(double) * (size_t)N);
+    if (p->precision == DFT_FP32_MIXED) {
+        L.rho_ref = take(F);
+        L.lp = take(F);
+        L.nref = take(sizeof(float) * (size_t)N * DFT_NALPHA);
+    } else {
+        L.rho_ref = L.lp = L.nref = 0;
+    }
+    L.total = off;
+    return L;
+}
+
+}  // namespace
+
+struct dft_ctx {
+    dft_params p;
+    dft_bulk_info bulk;
+    Consts hc;
+    Layout lay;
+    hipStream_t stream = nullptr;
+    hipStream_t cap_stream = nullptr;
+    char *ws = nullptr;
+    Geo geo{};
+    Consts *cs = nullptr;
+    DevState *st = nullptr;
+    void *specA = nullptr, *specB = nullptr;
+    double *base = nullptr, *rho0 = nullptr, *g0 = nullptr, *ga = nullptr, *gb = nullptr, *gs = nullptr;
+    double *rho_t = nullptr, *rho_ref = nullptr, *lp = nullptr, *phi_fix = nullptr;
+    float *nref = nullptr;
+    RedBufs red{};
+    int nf_parts = 0, nm_parts = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    const double *step_rho = nullptr;   // caller buffer whose iterate rho0 currently holds
+    long long refreshes = 0;
+    bool mixed = false;
+};
+
+namespace {
+
+template <typename T> int x3_parts(const Geo &g);
+
+int x_pairs_host(const Geo &g, int E) {
+    long long P = (256LL * E) / g.nx;
+    const long long npairs = ((long long)g.ny * g.nz + 1) / 2;
+    if (P > npairs) P = npairs;
+    if (P < 1) P = 1;
+    return (int)P;
+}
+
+int nparts_x3(const Geo &g, bool fp32) {
+    const int P = x_pairs_host(g, fp32 ? 16 : 8);
+    const long long npairs = ((long long)g.ny * g.nz + 1) / 2;
+    return (int)((npairs + P - 1) / P) * g.S;
+}
+
+int nparts_x2(const Geo &g) {
+    const int P = x_pairs_host(g, 4);
+    const long long npairs = ((long long)g.ny * g.nz + 1) / 2;
+    return (int)((npairs + P - 1) / P);
+}
+
+// Options of one residual evaluation.
+struct Eval {
+    bool trial = false;            // rho_t = rho0 + alpha (g0 - rho0)
+    const double *src = nullptr;   // plain: rho; trial: rho0
+    const double *g0 = nullptr;
+    const double *alpha = nullptr;
+    double *g_out = nullptr;
+    double *e_out = nullptr;
+    double *n_out = nullptr;
+    double *dphi_out = nullptr;
+    double *fslot = nullptr;
+    double *mslot = nullptr;
+    int count_kind = 1;
+    const int *gate = nullptr;
+    bool fp64 = true;              // transforms in FP64 (FP64 ctx, or FP32-mixed refresh/inspection)
+    bool refresh = false;          // FP32-mixed: write the reference fields
+};
+
+template <typename T>
+void enqueue_eval_t(dft_ctx *c, const Eval &ev, hipStream_t s) {
+    const Geo &g = c->geo;
+    const bool diff = c->mixed && !ev.fp64;
+    const double *rho_eval = ev.trial ? c->rho_t : ev.src;
+    XFwdArgs xa{};
+    xa.src = ev.src;
+    xa.g0 = ev.g0;
+    xa.alpha = ev.alpha;
+    xa.rho_t = ev.trial ? c->rho_t : nullptr;
+    xa.ref = diff ? c->rho_ref : nullptr;
+    xa.spec = c->specA;
+    xa.nfield = g.S;
+    xa.mode = ev.trial ? XF_TRIAL : XF_PLAIN;
+    xa.gate = ev.gate;
+    launch_x_forward<T>(g, xa, s);
+    YArgs ya{c->specA, g.S, -1, ev.gate};
+    launch_y<T>(g, ya, s);
+    Z1Args z1{c->specA, c->specB, 0, ev.gate};
+    launch_z1<T>(g, z1, s);
+    YArgs yb{c->specB, DFT_NALPHA, 1, ev.gate};
+    launch_y<T>(g, yb, s);
+    X2Args x2{};
+    x2.specB = c->specB;
+    x2.mode = X2_FULL;
+    x2.nref = diff ? c->nref : nullptr;
+    x2.nref_out = ev.refresh ? c->nref : nullptr;
+    x2.n_out = ev.n_out;
+    x2.dphi_out = ev.dphi_out;
+    x2.red = c->red;
+    x2.gate = ev.gate;
+    launch_x2<T>(g, x2, s);
+    YArgs yc{c->specB, DFT_NALPHA, -1, ev.gate};
+    launch_y<T>(g, yc, s);
+    Z2Args z2{};
+    z2.specB = c->specB;
+    z2.specA = c->specA;
+    z2.mode = Z2_EL;
+    z2.diff = diff ? 1 : 0;
+    z2.gate = ev.gate;
+    launch_z2<T>(g, z2, s);
+    YArgs yd{c->specA, g.S, 1, ev.gate};
+    launch_y<T>(g, yd, s);
+    X3Args x3{};
+    x3.specA = c->specA;
+    x3.nfield = g.S;
+    x3.raw = 0;
+    x3.base = diff ? c->lp : c->base;
+    x3.rho_t = rho_eval;
+    x3.g_out = ev.g_out;
+    x3.e_out = ev.e_out;
+    x3.lp_out = ev.refresh ? c->lp : nullptr;
+    x3.red = c->red;
+    x3.gate = ev.gate;
+    launch_x3<T>(g, x3, s);
+    launch_finalize(c->red, nparts_x3(g, sizeof(T) == 4), nparts_x2(g), ev.fslot, ev.mslot, c->st, ev.count_kind,
+                    ev.gate, s);
+}
+
+void enqueue_eval(dft_ctx *c, const Eval &ev, hipStream_t s) {
+    if (ev.fp64 || !c->mixed) enqueue_eval_t<double>(c, ev, s);
+    else enqueue_eval_t<float>(c, ev, s);
+}
+
+// max n3 at rho0 + alpha (g0 - rho0) without the rest of G (linear in rho).
+template <typename T>
+void enqueue_n3_t(dft_ctx *c, const double *alpha, double *mslot, const int *gate, hipStream_t s) {
+    const Geo &g = c->geo;
+    const bool diff = c->mixed;
+    XFwdArgs xa{};
+    xa.src = c->rho0;
+    xa.g0 = c->g0;
+    xa.alpha = alpha;
+    xa.rho_t = c->rho_t;
+    xa.ref = diff ? c->rho_ref : nullptr;
+    xa.spec = c->specA;
+    xa.nfield = g.S;
+    xa.mode = XF_TRIAL;
+    xa.gate = gate;
+    launch_x_forward<T>(g, xa, s);
+    YArgs ya{c->specA, g.S, -1, gate};
+    launch_y<T>(g, ya, s);
+    Z1Args z1{c->specA, c->specB, 1, gate};
+    launch_z1<T>(g, z1, s);
+    YArgs yb{c->specB, 1, 1, gate};
+    launch_y<T>(g, yb, s);
+    X2Args x2{};
+    x2.specB = c->specB;
+    x2.mode = X2_N3_ONLY;
+    x2.nref = diff ? c->nref : nullptr;
+    x2.red = c->red;
+    x2.gate = gate;
+    launch_x2<T>(g, x2, s);
+    launch_finalize(c->red, 0, nparts_x2(g), nullptr, mslot, c->st, 2, gate, s);
+}
+
+void enqueue_step(dft_ctx *c, hipStream_t s) {
+    DevState *st = c->st;
+    launch_ctl(st, CTL_BEGIN, s);
+    Eval e1;
+    e1.trial = true;
+    e1.src = c->rho0;
+    e1.g0 = c->g0;
+    e1.alpha = &st->alpha_trial;
+    e1.g_out = c->gb;
+    e1.fslot = &st->f1;
+    e1.mslot = &st->m1;
+    e1.gate = &st->gate_full1;
+    e1.fp64 = !c->mixed;
+    enqueue_eval(c, e1, s);
+    if (c->mixed) enqueue_n3_t<float>(c, &st->alpha_trial, &st->m1, &st->gate_part1, s);
+    else enqueue_n3_t<double>(c, &st->alpha_trial, &st->m1, &st->gate_part1, s);
+    launch_ctl(st, CTL_AMAX, s);
+    Eval ea = e1;
+    ea.g_out = c->ga;
+    ea.fslot = &st->fa;
+    ea.mslot = &st->ma;
+    ea.gate = &st->gate_a;
+    enqueue_eval(c, ea, s);
+    launch_ctl(st, CTL_B, s);
+    Eval eb = e1;
+    eb.g_out = c->gb;
+    eb.fslot = &st->fb;
+    eb.mslot = &st->mb;
+    eb.gate = &st->gate_b;
+    enqueue_eval(c, eb, s);
+    launch_ctl(st, CTL_FIT, s);
+    Eval es = e1;
+    es.g_out = c->gs;
+    es.fslot = &st->fs;
+    es.mslot = &st->ms;
+    es.gate = &st->gate_s;
+    enqueue_eval(c, es, s);
+    launch_ctl(st, CTL_ACCEPT, s);
+    launch_update(st, c->rho0, c->g0, c->gb, c->ga, c->gs, (long long)c->geo.S * c->geo.N, s);
+    launch_ctl(st, CTL_END, s);
+}
+
+// FP64 evaluation at rho0 that also becomes the FP32-mixed reference (or plain prime).
+void enqueue_prime(dft_ctx *c, hipStream_t s) {
+    DevState *st = c->st;
+    Eval e;
+    e.trial = true;
+    e.src = c->rho0;
+    e.g0 = c->rho0;      // alpha = 0: rho_t = rho0 exactly
+    e.alpha = &st->alpha_zero;
+    e.g_out = c->g0;
+    e.fslot = &st->f0;
+    e.mslot = &st->m0;
+    e.fp64 = true;
+    if (c->mixed) {
+        launch_copy(c->rho_ref, c->rho0, (long long)c->geo.S * c->geo.N, s);
+        e.refresh = true;
+    }
+    enqueue_eval(c, e, s);
+    launch_ctl(st, CTL_PRIME, s);
+}
+
+DevState read_state(dft_ctx *c) {
+    DevState h;
+    HIPCHK(hipMemcpyAsync(&h, c->st, sizeof h, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return h;
+}
+
+void write_state(dft_ctx *c, const DevState &h) {
+    HIPCHK(hipMemcpyAsync(c->st, &h, sizeof h, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+}
+
+DevState fresh_state(dft_ctx *c, double tol, long long max_iter) {
+    DevState h;
+    std::memset(&h, 0, sizeof h);
+    h.cap = 1.0;
+    h.tol = tol;
+    h.max_iter = max_iter;
+    h.nfluid = c->hc.nfluid;
+    h.eta_cap = c->hc.eta_cap;
+    h.alpha_zero = 0.0;
+    h.alpha_one = 1.0;
+    h.gate_one = 1;
+    return h;
+}
+
+void ensure_graph(dft_ctx *c) {
+    if (c->gexec) return;
+    if (!c->cap_stream) HIPCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    HIPCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+    try {
+        enqueue_step(c, c->cap_stream);
+    } catch (...) {
+        hipGraph_t tmp;
+        (void)hipStreamEndCapture(c->cap_stream, &tmp);
+        if (tmp) (void)hipGraphDestroy(tmp);
+        throw;
+    }
+    HIPCHK(hipStreamEndCapture(c->cap_stream, &c->graph));
+    HIPCHK(hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
+}
+
+dft_status status_from(const DevState &h) {
+    if (h.status == DFT_E_NONFINITE) return fail(DFT_E_NONFINITE, "non-finite residual at the current iterate");
+    if (h.status == DFT_E_PACKING) return fail(DFT_E_PACKING, "max n3 reached the packing cap at the current iterate");
+    return DFT_OK;
+}
+
+template <typename F>
+dft_status guarded(F &&f) {
+    try {
+        return f();
+    } catch (const HipError &e) {
+        return fail(DFT_E_DEVICE, e.what());
+    } catch (const std::exception &e) {
+        return fail(DFT_E_DEVICE, e.what());
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *dft_last_error(void) { return g_last_error.c_str(); }
+
+dft_status dft_bulk(const dft_params *params, dft_bulk_info *out) {
+    std::string msg;
+    dft_status st = bulk_info(params, out, &msg);
+    if (st != DFT_OK) return fail(st, msg);
+    return DFT_OK;
+}
+
+dft_status dft_workspace_size(const dft_params *params, size_t *bytes) {
+    std::string msg;
+    dft_status st = validate(params, &msg);
+    if (st != DFT_OK) return fail(st, msg);
+    if (!bytes) return fail(DFT_E_INVALID_ARG, "bytes is NULL");
+    *bytes = make_layout(params).total;
+    return DFT_OK;
+}
+
+dft_status dft_setup(const dft_params *params, const double *beta_vext, const double *fixed_charge, void *workspace,
+                     size_t ws_bytes, void *stream, dft_ctx **out) {
+    std::string msg;
+    if (!out) return fail(DFT_E_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    dft_bulk_info bi;
+    dft_status st = bulk_info(params, &bi, &msg);
+    if (st != DFT_OK) return fail(st, msg);
+    Layout lay = make_layout(params);
+    if (!workspace) return fail(DFT_E_WORKSPACE, "workspace is NULL");
+    if (ws_bytes < lay.total) {
+        char buf[160];
+        snprintf(buf, sizeof buf, "workspace of %zu bytes is smaller than the %zu bytes needed", ws_bytes, lay.total);
+        return fail(DFT_E_WORKSPACE, buf);
+    }
+    if (((uintptr_t)workspace) % 256 != 0) return fail(DFT_E_WORKSPACE, "workspace must be 256-byte aligned");
+    FftPlan plans[3];
+    for (int d = 0; d < 3; ++d)
+        if (!make_plan(params->n[d], &plans[d])) return fail(DFT_E_UNSUPPORTED_SIZE, "no FFT plan for this size");
+    if (fixed_charge && !params->electrostatics)
+        return fail(DFT_E_INVALID_ARG, "fixed_charge given with electrostatics off");
+
+    dft_ctx *c = new dft_ctx();
+    c->p = *params;
+    c->bulk = bi;
+    c->lay = lay;
+    c->stream = (hipStream_t)stream;
+    c->ws = (char *)workspace;
+    c->mixed = params->precision == DFT_FP32_MIXED;
+    fill_consts(params, bi, &c->hc);
+    st = guarded([&]() -> dft_status {
+        char *w = c->ws;
+        c->cs = (Consts *)(w + lay.consts);
+        c->st = (DevState *)(w + lay.state);
+        c->specA = w + lay.specA;
+        c->specB = w + lay.specB;
+        c->base = (double *)(w + lay.base);
+        c->rho0 = (double *)(w + lay.rho0);
+        c->g0 = (double *)(w + lay.g0);
+        c->ga = (double *)(w + lay.ga);
+        c->gb = (double *)(w + lay.gb);
+        c->gs = (double *)(w + lay.gs);
+        c->rho_t = (double *)(w + lay.rho_t);
+        c->phi_fix = (double *)(w + lay.phi_fix);
+        if (c->mixed) {
+            c->rho_ref = (double *)(w + lay.rho_ref);
+            c->lp = (double *)(w + lay.lp);
+            c->nref = (float *)(w + lay.nref);
+        }
+        c->red.fpart = (double *)(w + lay.fpart);
+        c->red.mpart = (double *)(w + lay.mpart);
+        c->red.fflag = (int *)(w + lay.fflag);
+        c->red.mflag = (int *)(w + lay.mflag);
+        c->red.cap = lay.red_cap;
+        Geo &g = c->geo;
+        g.cs = c->cs;
+        g.nx = params->n[0];
+        g.ny = params->n[1];
+        g.nz = params->n[2];
+        g.Kx = c->hc.Kx;
+        g.S = params->nspecies;
+        g.N = c->hc.N;
+        g.NC = c->hc.NC;
+        DevPlan *dp[3] = {&g.px, &g.py, &g.pz};
+        for (int d = 0; d < 3; ++d) {
+            dp[d]->L = plans[d].L;
+            dp[d]->nr = plans[d].nr;
+            for (int k = 0; k < kMaxRadices; ++k) dp[d]->r[k] = plans[d].r[k];
+            std::vector<double> tw;
+            twiddles(params->n[d], &tw);
+            std::vector<float> tf(tw.begin(), tw.end());
+            HIPCHK(hipMemcpyAsync(w + lay.tw64[d], tw.data(), tw.size() * sizeof(double), hipMemcpyHostToDevice,
+                                  c->stream));
+            HIPCHK(hipMemcpyAsync(w + lay.tw32[d], tf.data(), tf.size() * sizeof(float), hipMemcpyHostToDevice,
+                                  c->stream));
+            HIPCHK(hipStreamSynchronize(c->stream));
+            g.tw64[d] = w + lay.tw64[d];
+            g.tw32[d] = w + lay.tw32[d];
+        }
+        HIPCHK(hipMemcpyAsync(c->cs, &c->hc, sizeof(Consts), hipMemcpyHostToDevice, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        // potential of the fixed charges (Poisson source only), FP64
+        const double *phi = nullptr;
+        if (fixed_charge && params->electrostatics) {
+            XFwdArgs xa{};
+            xa.src = fixed_charge;
+            xa.spec = c->specA;
+            xa.nfield = 1;
+            xa.mode = XF_PLAIN;
+            launch_x_forward<double>(g, xa, c->stream);
+            YArgs ya{c->specA, 1, -1, nullptr};
+            launch_y<double>(g, ya, c->stream);
+            Z2Args z2{};
+            z2.specA = c->specA;
+            z2.mode = Z2_POISSON;
+            z2.nsrc = 1;
+            z2.wsrc[0] = 1.0;
+            launch_z2<double>(g, z2, c->stream);
+            YArgs yb{c->specA, 1, 1, nullptr};
+            launch_y<double>(g, yb, c->stream);
+            X3Args x3{};
+            x3.specA = c->specA;
+            x3.nfield = 1;
+            x3.raw = 1;
+            x3.raw_out = c->phi_fix;
+            launch_x3<double>(g, x3, c->stream);
+            phi = c->phi_fix;
+        } else {
+            HIPCHK(hipMemsetAsync(c->phi_fix, 0, sizeof(double) * g.N, c->stream));
+        }
+        double *cnt = (double *)(w + lay.count_part);
+        launch_make_base(c->cs, g.S, g.N, beta_vext, phi, c->base, bi.mu_hs, params->valence, cnt, lay.count_blocks,
+                         c->stream);
+        double nfl = 0.0;
+        launch_sum_to(cnt, lay.count_blocks, &c->st->nfluid, c->stream);
+        HIPCHK(hipMemcpyAsync(&nfl, &c->st->nfluid, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        if (!(nfl > 0.0)) throw std::runtime_error("no fluid node: every centre is excluded");
+        c->hc.nfluid = nfl;
+        HIPCHK(hipMemcpyAsync(c->cs, &c->hc, sizeof(Consts), hipMemcpyHostToDevice, c->stream));
+        DevState h = fresh_state(c, 0.0, 0);
+        write_state(c, h);
+        return DFT_OK;
+    });
+    if (st != DFT_OK) {
+        delete c;
+        return st;
+    }
+    *out = c;
+    g_last_error.clear();
+    return DFT_OK;
+}
+
+dft_status dft_set_stream(dft_ctx *ctx, void *stream) {
+    if (!ctx) return fail(DFT_E_INVALID_ARG, "ctx is NULL");
+    ctx->stream = (hipStream_t)stream;
+    return DFT_OK;
+}
+
+dft_status dft_set_reference(dft_ctx *ctx, const double *rho) {
+    if (!ctx || !rho) return fail(DFT_E_INVALID_ARG, "ctx or rho is NULL");
+    if (!ctx->mixed) return DFT_OK;
+    return guarded([&]() -> dft_status {
+        launch_copy(ctx->rho0, rho, (long long)ctx->geo.S * ctx->geo.N, ctx->stream);
+        DevState h = read_state(ctx);
+        h.tol = 0.0;
+        write_state(ctx, h);
+        enqueue_prime(ctx, ctx->stream);
+        ctx->refreshes += 1;
+        ctx->step_rho = nullptr;
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        return DFT_OK;
+    });
+}
+
+dft_status dft_residual(dft_ctx *ctx, const double *rho, double *g_out, double *norm_out) {
+    if (!ctx || !rho) return fail(DFT_E_INVALID_ARG, "ctx or rho is NULL");
+    return guarded([&]() -> dft_status {
+        if (ctx->mixed && ctx->refreshes == 0) {
+            // no reference state yet: rho becomes the reference
+            dft_status s2 = dft_set_reference(ctx, rho);
+            if (s2 != DFT_OK) return s2;
+        }
+        Eval e;
+        e.src = rho;
+        e.g_out = g_out ? g_out : ctx->gs;
+        e.fslot = &ctx->st->best_f;
+        e.mslot = nullptr;
+        e.fp64 = !ctx->mixed;
+        enqueue_eval(ctx, e, ctx->stream);
+        ctx->step_rho = nullptr;
+        if (norm_out) {
+            DevState h = read_state(ctx);
+            *norm_out = std::sqrt(h.best_f / ctx->hc.nfluid);
+        }
+        return DFT_OK;
+    });
+}
+
+dft_status dft_operators(dft_ctx *ctx, const double *rho, double *n_out, double *dphi_out, double *c_out,
+                         double *phi_out) {
+    if (!ctx || !rho) return fail(DFT_E_INVALID_ARG, "ctx or rho is NULL");
+    return guarded([&]() -> dft_status {
+        Eval e;
+        e.src = rho;
+        e.g_out = ctx->gs;
+        e.e_out = c_out;
+        e.n_out = n_out;
+        e.dphi_out = dphi_out;
+        e.fslot = &ctx->st->best_f;
+        e.fp64 = true;
+        e.count_kind = 0;
+        enqueue_eval(ctx, e, ctx->stream);
+        if (phi_out) {
+            const Geo &g = ctx->geo;
+            if (!ctx->p.electrostatics) {
+                HIPCHK(hipMemsetAsync(phi_out, 0, sizeof(double) * g.N, ctx->stream));
+            } else {
+                XFwdArgs xa{};
+                xa.src = rho;
+                xa.spec = ctx->specA;
+                xa.nfield = g.S;
+                xa.mode = XF_PLAIN;
+                launch_x_forward<double>(g, xa, ctx->stream);
+                YArgs ya{ctx->specA, g.S, -1, nullptr};
+                launch_y<double>(g, ya, ctx->stream);
+                Z2Args z2{};
+                z2.specA = ctx->specA;
+                z2.mode = Z2_POISSON;
+                z2.nsrc = g.S;
+                for (int i = 0; i < g.S; ++i) z2.wsrc[i] = ctx->p.valence[i];
+                launch_z2<double>(g, z2, ctx->stream);
+                YArgs yb{ctx->specA, 1, 1, nullptr};
+                launch_y<double>(g, yb, ctx->stream);
+                X3Args x3{};
+                x3.specA = ctx->specA;
+                x3.nfield = 1;
+                x3.raw = 1;
+                x3.addend = ctx->phi_fix;
+                x3.raw_out = phi_out;
+                launch_x3<double>(g, x3, ctx->stream);
+            }
+        }
+        ctx->step_rho = nullptr;
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        return DFT_OK;
+    });
+}
+
+dft_status dft_picard_step(dft_ctx *ctx, double *rho_inout, double *alpha_out, double *norm_out) {
+    if (!ctx || !rho_inout) return fail(DFT_E_INVALID_ARG, "ctx or rho is NULL");
+    return guarded([&]() -> dft_status {
+        const long long SN = (long long)ctx->geo.S * ctx->geo.N;
+        if (ctx->step_rho != rho_inout) {
+            DevState h = fresh_state(ctx, 0.0, 1LL << 60);
+            write_state(ctx, h);
+            launch_copy(ctx->rho0, rho_inout, SN, ctx->stream);
+            enqueue_prime(ctx, ctx->stream);
+            if (ctx->mixed) ctx->refreshes += 1;
+            ctx->step_rho = rho_inout;
+        }
+        DevState h0 = read_state(ctx);
+        if (h0.status) return status_from(h0);
+        // a single step always runs (tol = 0 keeps it from reporting convergence early)
+        h0.gate_run = 1;
+        h0.converged = 0;
+        write_state(ctx, h0);
+        enqueue_step(ctx, ctx->stream);
+        launch_copy(rho_inout, ctx->rho0, SN, ctx->stream);
+        DevState h = read_state(ctx);
+        if (alpha_out) *alpha_out = h.alpha_acc;
+        if (norm_out) *norm_out = h.r;
+        return status_from(h);
+    });
+}
+
+dft_status dft_solve(dft_ctx *ctx, double *rho_inout, double tol, int32_t max_iter, int32_t *iters_out,
+                     double *norm_out) {
+    if (!ctx || !rho_inout) return fail(DFT_E_INVALID_ARG, "ctx or rho is NULL");
+    if (!(tol >= 0.0) || max_iter < 0) return fail(DFT_E_INVALID_ARG, "tol must be >= 0 and max_iter >= 0");
+    return guarded([&]() -> dft_status {
+        const long long SN = (long long)ctx->geo.S * ctx->geo.N;
+        DevState h = fresh_state(ctx, tol, max_iter);
+        write_state(ctx, h);
+        launch_copy(ctx->rho0, rho_inout, SN, ctx->stream);
+        enqueue_prime(ctx, ctx->stream);
+        if (ctx->mixed) ctx->refreshes += 1;
+        ensure_graph(ctx);
+        const int K = ctx->geo.N >= (1LL << 22) ? 4 : 16;
+        h = read_state(ctx);
+        double r_ref = h.r;
+        double r_prev = h.r;
+        bool fp64_checked = true;   // the state's residual comes from an FP64 evaluation
+        dft_status out = DFT_OK;
+        for (;;) {
+            if (h.status) { out = status_from(h); break; }
+            if (h.converged) {
+                if (fp64_checked) break;
+                // FP32-mixed: confirm at the converged iterate with an FP64 evaluation, which
+                // also makes it the new reference state
+                enqueue_prime(ctx, ctx->stream);
+                ctx->refreshes += 1;
+                h = read_state(ctx);
+                r_ref = h.r;
+                fp64_checked = true;
+                continue;
+            }
+            if (h.iters >= max_iter || h.rejected >= 4 * (long long)max_iter + 16) {
+                out = fail(DFT_E_NOT_CONVERGED, "max_iter reached");
+                break;
+            }
+            for (int k = 0; k < K; ++k) HIPCHK(hipGraphLaunch(ctx->gexec, ctx->stream));
+            h = read_state(ctx);
+            fp64_checked = !ctx->mixed;
+            if (ctx->mixed && !h.converged && !h.status && (h.r < 1e-3 * r_ref || !(h.r < 0.99 * r_prev))) {
+                // refresh the FP64 reference once the residual has fallen far below the
+                // reference's, or stalls at the FP32 noise floor
+                enqueue_prime(ctx, ctx->stream);
+                ctx->refreshes += 1;
+                h = read_state(ctx);
+                r_ref = h.r;
+                fp64_checked = true;
+            }
+            r_prev = h.r;
+        }
+        launch_copy(rho_inout, ctx->rho0, SN, ctx->stream);
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        ctx->step_rho = rho_inout;
+        if (iters_out) *iters_out = (int32_t)h.iters;
+        if (norm_out) *norm_out = h.r;
+        return out;
+    });
+}
+
+dft_status dft_get_stats(dft_ctx *ctx, dft_stats *out) {
+    if (!ctx || !out) return fail(DFT_E_INVALID_ARG, "ctx or out is NULL");
+    return guarded([&]() -> dft_status {
+        DevState h = read_state(ctx);
+        out->iterations = h.iters;
+        out->rejected = h.rejected;
+        out->g_evals = h.gevals;
+        out->n3_evals = h.n3evals;
+        out->fp64_refresh = ctx->refreshes;
+        out->residual = h.r;
+        out->alpha = h.alpha_acc;
+        out->max_n3 = h.m0;
+        out->step_cap = h.cap;
+        return DFT_OK;
+    });
+}
+
+dft_status dft_destroy(dft_ctx *ctx) {
+    if (!ctx) return DFT_OK;
+    if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
+    if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+    delete ctx;
+    return DFT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,320 @@
+// Device building blocks for gfx950: complex arithmetic, the LDS-staged mixed-radix
+// Stockham FFT used by every pass kernel, the analytic spectra of Appendix B and of the
+// bulk-fluid section, and the pointwise derivatives of eq. (Phi).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "dft_host.h"
+
+namespace dft {
+
+template <typename T>
+struct alignas(2 * sizeof(T)) cx {
+    T x, y;
+};
+
+template <typename T>
+__device__ __forceinline__ cx<T> mk(T a, T b) { cx<T> r; r.x = a; r.y = b; return r; }
+template <typename T>
+__device__ __forceinline__ cx<T> add(cx<T> a, cx<T> b) { return mk<T>(a.x + b.x, a.y + b.y); }
+template <typename T>
+__device__ __forceinline__ cx<T> sub(cx<T> a, cx<T> b) { return mk<T>(a.x - b.x, a.y - b.y); }
+template <typename T>
+__device__ __forceinline__ cx<T> mul(cx<T> a, cx<T> b) {
+    return mk<T>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+template <typename T>
+__device__ __forceinline__ cx<T> scale(cx<T> a, T s) { return mk<T>(a.x * s, a.y * s); }
+template <typename T>
+__device__ __forceinline__ cx<T> conjg(cx<T> a) { return mk<T>(a.x, -a.y); }
+// multiply by s*i (s = +1 or -1)
+template <typename T, int SGN>
+__device__ __forceinline__ cx<T> mul_i(cx<T> a) { return SGN > 0 ? mk<T>(-a.y, a.x) : mk<T>(a.y, -a.x); }
+
+// ------------------------------------------------------------------ FFT plan on device
+struct DevPlan {
+    int L;
+    int nr;
+    int r[kMaxRadices];
+};
+
+// ------------------------------------------------------------------ radix butterflies
+// X_m = sum_q v_q exp(DIR 2 pi i q m / R), in place.
+template <typename T, int DIR>
+__device__ __forceinline__ void bfly2(cx<T> *v) {
+    cx<T> a = v[0], b = v[1];
+    v[0] = add(a, b);
+    v[1] = sub(a, b);
+}
+
+template <typename T, int DIR>
+__device__ __forceinline__ void bfly4(cx<T> *v) {
+    cx<T> t0 = add(v[0], v[2]), t1 = sub(v[0], v[2]);
+    cx<T> t2 = add(v[1], v[3]), t3 = mul_i<T, DIR>(sub(v[1], v[3]));
+    v[0] = add(t0, t2);
+    v[2] = sub(t0, t2);
+    v[1] = add(t1, t3);
+    v[3] = sub(t1, t3);
+}
+
+template <typename T, int DIR>
+__device__ __forceinline__ void bfly3(cx<T> *v) {
+    const T c = T(-0.5);
+    const T s = T(DIR) * T(0.86602540378443864676372317075293618);
+    cx<T> a = v[0];
+    cx<T> sm = add(v[1], v[2]);
+    cx<T> df = sub(v[1], v[2]);
+    v[0] = add(a, sm);
+    cx<T> m = mk<T>(a.x + c * sm.x, a.y + c * sm.y);
+    cx<T> r = mk<T>(-s * df.y, s * df.x);   // i s (b - c)
+    v[1] = add(m, r);
+    v[2] = sub(m, r);
+}
+
+template <typename T, int DIR>
+__device__ __forceinline__ void bfly8(cx<T> *v) {
+    cx<T> e[4] = {v[0], v[2], v[4], v[6]};
+    cx<T> o[4] = {v[1], v[3], v[5], v[7]};
+    bfly4<T, DIR>(e);
+    bfly4<T, DIR>(o);
+    const T r2 = T(0.70710678118654752440084436210484903);
+    // o[m] *= exp(DIR 2 pi i m / 8)
+    o[1] = mk<T>(r2 * (o[1].x - T(DIR) * o[1].y), r2 * (o[1].y + T(DIR) * o[1].x));
+    o[2] = mul_i<T, DIR>(o[2]);
+    o[3] = mk<T>(r2 * (-o[3].x - T(DIR) * o[3].y), r2 * (-o[3].y + T(DIR) * o[3].x));
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        v[m] = add(e[m], o[m]);
+        v[m + 4] = sub(e[m], o[m]);
+    }
+}
+
+template <typename T, int DIR, int R>
+__device__ __forceinline__ void bfly(cx<T> *v) {
+    if constexpr (R == 2) bfly2<T, DIR>(v);
+    else if constexpr (R == 3) bfly3<T, DIR>(v);
+    else if constexpr (R == 4) bfly4<T, DIR>(v);
+    else bfly8<T, DIR>(v);
+}
+
+// ------------------------------------------------------------------ Stockham stage in LDS
+// The tile holds P pencils of length L; element e of pencil p is tile[p*ps + e*es].
+// One stage of radix R: butterfly b of a pencil reads elements b + q*L/R, applies the
+// twiddles exp(DIR 2 pi i q k / (Ns R)) with k = b mod Ns, and writes the outputs to
+// (b / Ns) * Ns * R + k + q * Ns.  Every thread reads all of its inputs before the
+// barrier and writes after it, so the stage runs in place.
+// `bfast` selects the butterfly index as the fastest-varying work index (x tiles,
+// es == 1); otherwise the pencil index varies fastest (y/z tiles, ps == 1).
+template <typename T, int DIR, int R, int NT, int MAXE>
+__device__ __forceinline__ void stockham_stage(cx<T> *tile, int L, int P, int es, int ps, bool bfast, int Ns,
+                                               const cx<T> *__restrict__ tw) {
+    constexpr int IT = (MAXE + R - 1) / R;
+    const int nb = L / R;
+    const int total = nb * P;
+    const int tstride = L / (Ns * R);
+    cx<T> v[IT][R];
+    int obase[IT];
+    int kk[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int j = threadIdx.x + it * NT;
+        if (j < total) {
+            int p, b;
+            if (bfast) { b = j % nb; p = j / nb; }
+            else { p = j % P; b = j / P; }
+            const int ib = p * ps + b * es;
+#pragma unroll
+            for (int q = 0; q < R; ++q) v[it][q] = tile[ib + q * nb * es];
+            const int k = b % Ns;
+            kk[it] = k;
+            obase[it] = p * ps + ((b - k) * R + k) * es;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int j = threadIdx.x + it * NT;
+        if (j < total) {
+            const int k = kk[it];
+            if (Ns > 1) {
+#pragma unroll
+                for (int q = 1; q < R; ++q) {
+                    cx<T> w = tw[q * k * tstride];
+                    if (DIR > 0) w.y = -w.y;
+                    v[it][q] = mul(v[it][q], w);
+                }
+            }
+            bfly<T, DIR, R>(v[it]);
+#pragma unroll
+            for (int q = 0; q < R; ++q) tile[obase[it] + q * Ns * es] = v[it][q];
+        }
+    }
+    __syncthreads();
+}
+
+// Full FFT of every pencil in the tile (unnormalized; DIR = -1 forward, +1 inverse).
+// Requires L * P <= NT * MAXE (checked by the launchers).
+template <typename T, int DIR, int NT, int MAXE>
+__device__ __forceinline__ void fft_tile(cx<T> *tile, const DevPlan &pl, int P, int es, int ps, bool bfast,
+                                         const cx<T> *__restrict__ tw) {
+    int Ns = 1;
+    for (int s = 0; s < pl.nr; ++s) {
+        const int R = pl.r[s];
+        if (R == 8) stockham_stage<T, DIR, 8, NT, MAXE>(tile, pl.L, P, es, ps, bfast, Ns, tw);
+        else if (R == 4) stockham_stage<T, DIR, 4, NT, MAXE>(tile, pl.L, P, es, ps, bfast, Ns, tw);
+        else if (R == 2) stockham_stage<T, DIR, 2, NT, MAXE>(tile, pl.L, P, es, ps, bfast, Ns, tw);
+        else stockham_stage<T, DIR, 3, NT, MAXE>(tile, pl.L, P, es, ps, bfast, Ns, tw);
+        Ns *= R;
+    }
+}
+
+template <typename T, int NT, int MAXE>
+__device__ __forceinline__ void fft_tile_dir(int dir, cx<T> *tile, const DevPlan &pl, int P, int es, int ps,
+                                             bool bfast, const cx<T> *__restrict__ tw) {
+    if (dir < 0) fft_tile<T, -1, NT, MAXE>(tile, pl, P, es, ps, bfast, tw);
+    else fft_tile<T, 1, NT, MAXE>(tile, pl, P, es, ps, bfast, tw);
+}
+
+// ------------------------------------------------------------------ spectra (FP64)
+// Series of (4 pi / k) I_m(R, k) / (4 pi R^{m+3}) = sum_n (-1)^n y^{2n} / ((2n+1)! (2n+m+3)),
+// y = kR, used below y = 1 where the closed forms lose digits.
+constexpr int kSeriesTerms = 11;
+
+template <int M>
+struct BallSeries {
+    double c[kSeriesTerms];
+    constexpr BallSeries() : c() {
+        double fact = 1.0;   // (2n+1)!
+        for (int n = 0; n < kSeriesTerms; ++n) {
+            if (n > 0) fact *= (double)(2 * n) * (double)(2 * n + 1);
+            c[n] = ((n % 2) ? -1.0 : 1.0) / (fact * (double)(2 * n + M + 3));
+        }
+    }
+};
+
+struct SincSeries {   // sin(y)/y = sum (-1)^n y^{2n} / (2n+1)!
+    double c[kSeriesTerms];
+    constexpr SincSeries() : c() {
+        double fact = 1.0;
+        for (int n = 0; n < kSeriesTerms; ++n) {
+            if (n > 0) fact *= (double)(2 * n) * (double)(2 * n + 1);
+            c[n] = ((n % 2) ? -1.0 : 1.0) / fact;
+        }
+    }
+};
+
+template <typename S>
+__device__ __forceinline__ double horner_y2(const S &s, double y2) {
+    double acc = s.c[kSeriesTerms - 1];
+#pragma unroll
+    for (int n = kSeriesTerms - 2; n >= 0; --n) acc = fma(acc, y2, s.c[n]);
+    return acc;
+}
+
+constexpr double kFourPi = 12.566370614359172953850573533118011536788677597500;
+
+// Weight transforms of a sphere of radius R at |k| (Appendix B):
+//   w2 = 4 pi R sin(kR) / k,   w3 = 4 pi (sin kR - kR cos kR) / k^3.
+__device__ __forceinline__ void weight_w2_w3(double k, double R, double &w2, double &w3) {
+    const double y = k * R;
+    const double R2 = R * R;
+    if (y < 1.0) {
+        constexpr SincSeries s0{};
+        constexpr BallSeries<0> s3{};
+        const double y2 = y * y;
+        w2 = kFourPi * R2 * horner_y2(s0, y2);
+        w3 = kFourPi * R2 * R * horner_y2(s3, y2);
+    } else {
+        double s, c;
+        sincos(y, &s, &c);
+        const double iy = 1.0 / y;
+        w2 = kFourPi * R2 * s * iy;
+        w3 = kFourPi * R2 * R * (s - y * c) * iy * iy * iy;
+    }
+}
+
+// Bulk-fluid kernel transform for one pair: c1 F1 + c0 F0 + cm1 Fm1 with
+// F_m = integral over |r| <= Rc of r^m exp(-i k.r) = (4 pi / k) I_m(Rc, k).
+__device__ __forceinline__ double screening_hat(double k, double Rc, double c1, double c0, double cm1) {
+    const double y = k * Rc;
+    const double R2 = Rc * Rc;
+    double Fm1, F0, F1;
+    if (y < 1.0) {
+        constexpr BallSeries<-1> sm{};
+        constexpr BallSeries<0> s0{};
+        constexpr BallSeries<1> s1{};
+        const double y2 = y * y;
+        Fm1 = kFourPi * R2 * horner_y2(sm, y2);
+        F0 = kFourPi * R2 * Rc * horner_y2(s0, y2);
+        F1 = kFourPi * R2 * R2 * horner_y2(s1, y2);
+    } else {
+        double s, c;
+        sincos(y, &s, &c);
+        const double omc = (c > 0.0) ? s * s / (1.0 + c) : 1.0 - c;   // 1 - cos y without cancellation
+        const double iy = 1.0 / y, iy2 = iy * iy;
+        Fm1 = kFourPi * R2 * omc * iy2;
+        F0 = kFourPi * R2 * Rc * (s - y * c) * iy2 * iy;
+        F1 = kFourPi * R2 * R2 * (-c * iy2 + 2.0 * s * iy2 * iy - 2.0 * omc * iy2 * iy2);
+    }
+    return c1 * F1 + c0 * F0 + cm1 * Fm1;
+}
+
+// Eigenvalue of minus the 7-point Laplacian for wavenumber components kd.
+__device__ __forceinline__ double poisson_denominator(const double kd[3], const double h[3]) {
+    double D = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const double s = sin(0.5 * kd[d] * h[d]);
+        D += 4.0 * s * s / (h[d] * h[d]);
+    }
+    return D;
+}
+
+// Signed mode index of position j on an axis with n nodes (eq. Kvalues).
+__device__ __forceinline__ int signed_mode(int j, int n) { return (2 * j <= n) ? j : j - n; }
+
+// ------------------------------------------------------------------ eq. (Phi)
+// dPhi/dn_alpha of the anti-symmetrized Rosenfeld free-energy density, with the
+// bound |nV2| <= n2 enforced as xi^2 <- min(xi^2, 1).  D may be double or a dual number.
+template <typename D>
+struct FmtOps;
+
+template <>
+struct FmtOps<double> {
+    static __device__ __forceinline__ double val(double a) { return a; }
+    static __device__ __forceinline__ double cst(double a) { return a; }
+    static __device__ __forceinline__ double lg(double a) { return log(a); }
+};
+
+template <typename D>
+__device__ __forceinline__ void fmt_dphi(const D n[DFT_NALPHA], D out[DFT_NALPHA], bool &clamped) {
+    using O = FmtOps<D>;
+    const double inv8pi = 1.0 / (8.0 * 3.14159265358979323846);
+    const double inv12pi = 1.0 / (12.0 * 3.14159265358979323846);
+    const double inv4pi = 1.0 / (4.0 * 3.14159265358979323846);
+    const D one = O::cst(1.0);
+    const D Dm = one - n[3];
+    const D iD = one / Dm;
+    const D dot12 = n[4] * n[7] + n[5] * n[8] + n[6] * n[9];
+    const D dot22 = n[7] * n[7] + n[8] * n[8] + n[9] * n[9];
+    const D n2sq = n[2] * n[2];
+    const D den = (O::val(n2sq) > 1e-300) ? n2sq : O::cst(1e-300);
+    D x2 = dot22 / den;
+    clamped = !(O::val(x2) < 1.0);
+    if (clamped) x2 = one;
+    const D q = one - x2;
+    const D q2 = q * q;
+    const D iD2 = iD * iD;
+    out[0] = O::cst(0.0) - O::lg(Dm);
+    out[1] = n[2] * iD;
+    out[2] = n[1] * iD + n2sq * q2 * (one + x2) * iD2 * inv8pi;
+    out[3] = n[0] * iD + (n[1] * n[2] - dot12) * iD2 + n2sq * n[2] * q2 * q * iD2 * iD * inv12pi;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        out[4 + d] = O::cst(0.0) - n[7 + d] * iD;
+        out[7 + d] = O::cst(0.0) - n[4 + d] * iD - n[2] * q2 * n[7 + d] * iD2 * inv4pi;
+    }
+}
+
+}  // namespace dft

@@ -1,0 +1,247 @@
+// Host-side setup math of the solver.  Plain C++ (no HIP): it is also built with g++
+// and sanitizers for the host-only tests.
+#include "dft_host.h"
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+
+namespace dft {
+
+static bool smooth_23(int n) {
+    if (n < 1) return false;
+    while (n % 2 == 0) n /= 2;
+    while (n % 3 == 0) n /= 3;
+    return n == 1;
+}
+
+dft_status validate(const dft_params *p, std::string *msg) {
+    char buf[256];
+    if (!p) { *msg = "params is NULL"; return DFT_E_INVALID_ARG; }
+    if (p->nspecies < 1 || p->nspecies > DFT_MAX_SPECIES) {
+        snprintf(buf, sizeof buf, "nspecies = %d outside 1..%d", p->nspecies, DFT_MAX_SPECIES);
+        *msg = buf;
+        return DFT_E_UNSUPPORTED_SIZE;
+    }
+    for (int d = 0; d < 3; ++d) {
+        int n = p->n[d];
+        if (n < 1 || n > DFT_MAX_N || !smooth_23(n)) {
+            snprintf(buf, sizeof buf, "n[%d] = %d is not 1 or 2^a 3^b <= %d", d, n, DFT_MAX_N);
+            *msg = buf;
+            return DFT_E_UNSUPPORTED_SIZE;
+        }
+        if (!(p->h[d] > 0.0) || !std::isfinite(p->h[d])) {
+            snprintf(buf, sizeof buf, "h[%d] = %g must be positive and finite", d, p->h[d]);
+            *msg = buf;
+            return DFT_E_INVALID_ARG;
+        }
+    }
+    for (int k = 0; k < p->nspecies; ++k) {
+        if (!(p->radius[k] > 0.0) || !std::isfinite(p->radius[k])) {
+            snprintf(buf, sizeof buf, "radius[%d] = %g must be positive", k, p->radius[k]);
+            *msg = buf;
+            return DFT_E_INVALID_ARG;
+        }
+        if (!(p->rho_bulk[k] > 0.0) || !std::isfinite(p->rho_bulk[k])) {
+            snprintf(buf, sizeof buf, "rho_bulk[%d] = %g must be positive", k, p->rho_bulk[k]);
+            *msg = buf;
+            return DFT_E_INVALID_ARG;
+        }
+        if (!std::isfinite(p->valence[k])) { *msg = "valence must be finite"; return DFT_E_INVALID_ARG; }
+    }
+    if (p->precision != DFT_FP64 && p->precision != DFT_FP32_MIXED) {
+        *msg = "precision must be DFT_FP64 or DFT_FP32_MIXED";
+        return DFT_E_INVALID_ARG;
+    }
+    if (p->electrostatics != 0 && p->electrostatics != 1) {
+        *msg = "electrostatics must be 0 or 1";
+        return DFT_E_INVALID_ARG;
+    }
+    if (p->flags & ~(DFT_FLAG_ALLOW_NON_NEUTRAL | DFT_FLAG_CUTOFF_LAMBDA)) {
+        *msg = "unknown bits in flags";
+        return DFT_E_INVALID_ARG;
+    }
+    if (!(p->eta_cap >= 0.0 && p->eta_cap < 1.0)) {
+        *msg = "eta_cap must lie in [0, 1) (0 selects 0.9)";
+        return DFT_E_INVALID_ARG;
+    }
+    // packing fraction of the bath must be below 1
+    double xi3 = 0.0;
+    for (int k = 0; k < p->nspecies; ++k) xi3 += M_PI / 6.0 * p->rho_bulk[k] * std::pow(2.0 * p->radius[k], 3);
+    if (!(xi3 < 1.0)) { *msg = "bulk packing fraction >= 1"; return DFT_E_INVALID_ARG; }
+    if (p->electrostatics) {
+        if (!(p->bjerrum_length > 0.0) || !std::isfinite(p->bjerrum_length)) {
+            *msg = "bjerrum_length must be positive with electrostatics on";
+            return DFT_E_INVALID_ARG;
+        }
+        double q = 0.0, qa = 0.0;
+        for (int k = 0; k < p->nspecies; ++k) {
+            q += p->valence[k] * p->rho_bulk[k];
+            qa += std::fabs(p->valence[k]) * p->rho_bulk[k];
+        }
+        if (qa == 0.0) { *msg = "electrostatics on but no species is charged"; return DFT_E_INVALID_ARG; }
+        if (!(p->flags & DFT_FLAG_ALLOW_NON_NEUTRAL) && std::fabs(q) > 1e-12 * qa) {
+            snprintf(buf, sizeof buf, "bulk is not electroneutral: sum z rho = %g", q);
+            *msg = buf;
+            return DFT_E_NOT_NEUTRAL;
+        }
+    }
+    return DFT_OK;
+}
+
+// ---------------------------------------------------------------- Appendix A
+
+namespace {
+
+struct Msa {
+    double F, dF, eta, omega;
+};
+
+// Residual of eq. (Gamma) written as F = 4 Gamma^2 - 4 pi l_B sum rho X^2 and its derivative.
+Msa msa_eval(double g, int S, const double *rho, const double *sig, const double *z, double lB, double Delta) {
+    const double c = M_PI / (2.0 * Delta);
+    double Pn = 0, dPn = 0, Om = 1, dOm = 0;
+    for (int j = 0; j < S; ++j) {
+        const double den = 1.0 + g * sig[j];
+        Pn += rho[j] * sig[j] * z[j] / den;
+        dPn -= rho[j] * sig[j] * sig[j] * z[j] / (den * den);
+        Om += c * rho[j] * sig[j] * sig[j] * sig[j] / den;
+        dOm -= c * rho[j] * std::pow(sig[j], 4) / (den * den);
+    }
+    const double eta = c * Pn / Om;
+    const double deta = c * (dPn * Om - Pn * dOm) / (Om * Om);
+    double sum = 0, dsum = 0;
+    for (int j = 0; j < S; ++j) {
+        const double den = 1.0 + g * sig[j];
+        const double X = (z[j] - eta * sig[j] * sig[j]) / den;
+        const double dX = (-deta * sig[j] * sig[j] * den - (z[j] - eta * sig[j] * sig[j]) * sig[j]) / (den * den);
+        sum += rho[j] * X * X;
+        dsum += 2.0 * rho[j] * X * dX;
+    }
+    Msa m;
+    m.F = 4.0 * g * g - 4.0 * M_PI * lB * sum;
+    m.dF = 8.0 * g - 4.0 * M_PI * lB * dsum;
+    m.eta = eta;
+    m.omega = Om;
+    return m;
+}
+
+}  // namespace
+
+dft_status bulk_info(const dft_params *p, dft_bulk_info *out, std::string *msg) {
+    dft_status st = validate(p, msg);
+    if (st != DFT_OK) return st;
+    if (!out) { *msg = "out is NULL"; return DFT_E_INVALID_ARG; }
+    std::memset(out, 0, sizeof *out);
+    const int S = p->nspecies;
+    double sig[DFT_MAX_SPECIES];
+    for (int k = 0; k < S; ++k) sig[k] = 2.0 * p->radius[k];
+    for (int n = 0; n < 4; ++n) {
+        double s = 0;
+        for (int k = 0; k < S; ++k) s += p->rho_bulk[k] * std::pow(sig[k], n);
+        out->xi[n] = M_PI / 6.0 * s;
+    }
+    const double D = 1.0 - out->xi[3];
+    const double *xi = out->xi;
+    out->beta_p = 6.0 / M_PI * (xi[0] / D + 3.0 * xi[1] * xi[2] / (D * D) + 3.0 * xi[2] * xi[2] * xi[2] / (D * D * D));
+    for (int k = 0; k < S; ++k) {
+        const double s = sig[k];
+        out->mu_hs[k] = -std::log(D) + (3.0 * xi[2] * s + 3.0 * xi[1] * s * s) / D +
+                        9.0 * xi[2] * xi[2] * s * s / (2.0 * D * D) + out->beta_p * M_PI * s * s * s / 6.0;
+    }
+    if (!p->electrostatics) return DFT_OK;
+    const double lB = p->bjerrum_length;
+    double kap2 = 0;
+    for (int k = 0; k < S; ++k) kap2 += 4.0 * M_PI * lB * p->rho_bulk[k] * p->valence[k] * p->valence[k];
+    // Safeguarded Newton from the Debye value kappa / 2, keeping a sign-change bracket.
+    double lo = 0.0, hi = std::sqrt(kap2);
+    while (msa_eval(hi, S, p->rho_bulk, sig, p->valence, lB, D).F <= 0.0) hi *= 2.0;
+    double g = 0.5 * std::sqrt(kap2);
+    for (int it = 0; it < 200; ++it) {
+        Msa m = msa_eval(g, S, p->rho_bulk, sig, p->valence, lB, D);
+        if (m.F > 0) hi = g; else lo = g;
+        double gn = (m.dF != 0.0) ? g - m.F / m.dF : 0.5 * (lo + hi);
+        if (!(gn > lo && gn < hi)) gn = 0.5 * (lo + hi);
+        const double dg = std::fabs(gn - g);
+        g = gn;
+        if (dg <= 1e-15 * g) break;
+    }
+    Msa m = msa_eval(g, S, p->rho_bulk, sig, p->valence, lB, D);
+    out->gamma = g;
+    out->eta_msa = m.eta;
+    out->omega = m.omega;
+    for (int k = 0; k < S; ++k) {
+        const double s = sig[k], zk = p->valence[k], e = m.eta;
+        out->lambda[k] = p->radius[k] + 0.5 / g;
+        out->mu_es[k] = -lB * (g * zk * zk / (1.0 + g * s) +
+                               e * s * ((2.0 * zk - e * s * s) / (1.0 + g * s) + e * s * s / 3.0));
+    }
+    return DFT_OK;
+}
+
+// ---------------------------------------------------------------- FFT plans
+
+bool make_plan(int L, FftPlan *plan) {
+    if (L < 1 || !smooth_23(L)) return false;
+    plan->L = L;
+    plan->nr = 0;
+    int m = L;
+    while (m % 8 == 0) { plan->r[plan->nr++] = 8; m /= 8; }
+    while (m % 4 == 0) { plan->r[plan->nr++] = 4; m /= 4; }
+    while (m % 2 == 0) { plan->r[plan->nr++] = 2; m /= 2; }
+    while (m % 3 == 0) { plan->r[plan->nr++] = 3; m /= 3; }
+    return plan->nr <= kMaxRadices;
+}
+
+void twiddles(int L, std::vector<double> *out) {
+    out->resize(2 * (size_t)L);
+    for (int m = 0; m < L; ++m) {
+        // reduce m/L to the first octant for accuracy, then evaluate in long double
+        long double a = 2.0L * 3.14159265358979323846264338327950288L * (long double)m / (long double)L;
+        (*out)[2 * m] = (double)cosl(a);
+        (*out)[2 * m + 1] = (double)(-sinl(a));
+    }
+}
+
+void fill_consts(const dft_params *p, const dft_bulk_info &b, Consts *c) {
+    std::memset(c, 0, sizeof *c);
+    c->S = p->nspecies;
+    c->nx = p->n[0];
+    c->ny = p->n[1];
+    c->nz = p->n[2];
+    c->Kx = p->n[0] / 2 + 1;
+    c->es = p->electrostatics ? 1 : 0;
+    c->N = (long long)p->n[0] * p->n[1] * p->n[2];
+    c->NC = (long long)c->Kx * p->n[1] * p->n[2];
+    c->invN = 1.0 / (double)c->N;
+    for (int d = 0; d < 3; ++d) {
+        c->h[d] = p->h[d];
+        c->dk[d] = 2.0 * M_PI / (p->n[d] * p->h[d]);
+    }
+    c->four_pi_lB = p->electrostatics ? 4.0 * M_PI * p->bjerrum_length : 0.0;
+    c->eta_cap = p->eta_cap > 0.0 ? p->eta_cap : 0.9;
+    const int S = p->nspecies;
+    for (int k = 0; k < S; ++k) {
+        c->R[k] = p->radius[k];
+        c->z[k] = p->valence[k];
+        c->rho_b[k] = p->rho_bulk[k];
+        c->inv_rho_b[k] = 1.0 / p->rho_bulk[k];
+        c->i4piR2[k] = 1.0 / (4.0 * M_PI * p->radius[k] * p->radius[k]);
+        c->i4piR[k] = 1.0 / (4.0 * M_PI * p->radius[k]);
+    }
+    if (p->electrostatics) {
+        const double lB = p->bjerrum_length;
+        for (int i = 0; i < S; ++i)
+            for (int j = 0; j < S; ++j) {
+                const double li = b.lambda[i], lj = b.lambda[j], ll = li * lj;
+                const double pre = 0.5 * p->valence[i] * p->valence[j] * lB;   // z_i z_j l_B / 2
+                const int ij = i * DFT_MAX_SPECIES + j;
+                c->sc_c1[ij] = pre / (2.0 * ll);
+                c->sc_c0[ij] = -pre * (li + lj) / ll;
+                c->sc_cm1[ij] = pre * ((li - lj) * (li - lj) / (2.0 * ll) + 2.0);
+                c->sc_R[ij] = (p->flags & DFT_FLAG_CUTOFF_LAMBDA) ? li + lj : p->radius[i] + p->radius[j];
+            }
+    }
+}
+
+}  // namespace dft

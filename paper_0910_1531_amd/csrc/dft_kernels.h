@@ -1,0 +1,145 @@
+// Launch interface of the pass kernels (host side).  Every launcher checks the tile
+// shape against the kernel's compile-time capacity before launching.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "dft_device.h"
+
+namespace dft {
+
+// Line-search and status scalars kept in device memory (graph-capturable control).
+struct DevState {
+    double f0, m0;          // current iterate: f = ||rho - G(rho)||_w^2, max n3
+    double f1, m1;          // at alpha = 1 (full G, or n3 only)
+    double fa, ma, fb, mb, fs, ms;
+    double amax, t, alpha_trial, alpha_acc, cap, alpha_zero, alpha_one;
+    double r, tol, nfluid, eta_cap;
+    double best_f;
+    long long iters, rejected, gevals, n3evals, max_iter;
+    int gate_full1, gate_part1, gate_a, gate_b, gate_s, gate_upd, gate_run, gate_one;
+    int src;                // accepted sample: 0 = amax, 1 = amax/2, 2 = vertex
+    int status;             // dft_status of the device loop (NONFINITE, PACKING)
+    int converged;
+    int pad;
+};
+
+// Pointers every pass kernel needs (device memory inside the workspace).
+struct Geo {
+    const Consts *cs;
+    DevPlan px, py, pz;
+    const void *tw64[3];   // cx<double> tables per axis
+    const void *tw32[3];   // cx<float> tables per axis
+    int nx, ny, nz, Kx, S;
+    long long N, NC;
+};
+
+// Where the reductions of one residual evaluation go.
+struct RedBufs {
+    double *fpart;   // per-block partial sums of the weighted residual (X3)
+    double *mpart;   // per-block partial maxima of n3 (X2)
+    int *fflag;      // per-block flags of X3: 1 = non-finite
+    int *mflag;      // per-block flags of X2: 1 = non-finite, 2 = xi^2 clamp used
+    int cap;         // capacity of each array
+};
+
+enum XFwdMode { XF_PLAIN = 0, XF_TRIAL = 1 };
+enum X2Mode { X2_FULL = 0, X2_N3_ONLY = 1 };
+enum Z2Mode { Z2_EL = 0, Z2_POISSON = 1 };
+
+struct XFwdArgs {
+    const double *src;        // [S][N] input (plain) or rho0 (trial)
+    const double *g0;         // [S][N] Picard image (trial)
+    const double *alpha;      // device scalar (trial)
+    double *rho_t;            // [S][N] trial point out (trial), may be null
+    const double *ref;        // [S][N] FP32-mixed reference density (subtracted), may be null
+    void *spec;               // [S] half spectra out
+    int nfield;               // fields to transform
+    int mode;
+    const int *gate;
+};
+
+struct YArgs {
+    void *spec;
+    int nfield;
+    int dir;
+    const int *gate;
+};
+
+struct Z1Args {
+    void *specA;        // [S] in (after x, y forward), out: rho_hat (unnormalized)
+    void *specB;        // [10] out: n_alpha half spectra after inverse z (x invN)
+    int n3only;         // only n3 into specB[0]
+    const int *gate;
+};
+
+struct Z2Args {
+    void *specB;        // [10] dPhi/dn half spectra after x, y forward
+    void *specA;        // [S] in: rho_hat; out: E_hat after inverse z (x invN)
+    int mode;           // Z2_EL or Z2_POISSON
+    int diff;           // FP32-mixed difference evaluation: no bath subtraction
+    int nsrc;           // Z2_POISSON: number of source fields in specA
+    double wsrc[DFT_MAX_SPECIES];   // Z2_POISSON: weights of the sources
+    const int *gate;
+};
+
+struct X2Args {
+    void *specB;              // [10] in: n half spectra after y inverse; out: dPhi spectra
+    int mode;
+    const float *nref;        // FP32-mixed: reference weighted densities [10][N]
+    float *nref_out;          // FP64 refresh: write n rounded to float [10][N]
+    double *n_out;            // [10][N] FP64 copies for inspection, may be null
+    double *dphi_out;         // [10][N], may be null
+    RedBufs red;
+    const int *gate;
+};
+
+struct X3Args {
+    void *specA;              // [S] E_hat half spectra after y inverse
+    int nfield;
+    int raw;                  // write E (+ addend) only
+    const double *addend;     // raw mode: added to E (may be null)
+    double *raw_out;          // raw mode output [nfield][N]
+    const double *base;       // [S][N] exponent base (beta mu_b - beta V - z beta e phi_fixed [+ E_ref])
+    const double *rho_t;      // [S][N] point of evaluation (residual)
+    double *g_out;            // [S][N] G(rho_t), may be null
+    double *e_out;            // [S][N] E for inspection, may be null
+    double *lp_out;           // FP64 refresh: base + E, may be null
+    RedBufs red;
+    const int *gate;
+};
+
+// Launchers (precision T = double or float of the transforms).
+template <typename T> void launch_x_forward(const Geo &g, const XFwdArgs &a, hipStream_t s);
+template <typename T> void launch_y(const Geo &g, const YArgs &a, hipStream_t s);
+template <typename T> void launch_z1(const Geo &g, const Z1Args &a, hipStream_t s);
+template <typename T> void launch_z2(const Geo &g, const Z2Args &a, hipStream_t s);
+template <typename T> void launch_x2(const Geo &g, const X2Args &a, hipStream_t s);
+template <typename T> void launch_x3(const Geo &g, const X3Args &a, hipStream_t s);
+
+// Number of blocks the reductions of X2 / X3 produce (sizes the partial arrays).
+int x2_blocks(const Geo &g);
+int x3_blocks(const Geo &g);
+
+// Reduction of the partials into state slots (single block, fixed order).
+// A non-finite evaluation stores +inf in its slots (the line search then rejects it).
+void launch_finalize(const RedBufs &r, int nf, int nm, double *fslot, double *mslot, DevState *st,
+                     int count_kind, const int *gate, hipStream_t s);
+
+// Control kernels of the line search (single thread).
+enum CtlOp { CTL_BEGIN = 0, CTL_AMAX = 1, CTL_B = 2, CTL_FIT = 3, CTL_ACCEPT = 4, CTL_END = 5, CTL_PRIME = 6 };
+void launch_ctl(DevState *st, int op, hipStream_t s);
+
+// rho0 <- rho0 + alpha (G0 - rho0); G0 <- G_src (src chosen on device).
+void launch_update(DevState *st, double *rho0, double *g0, const double *gb, const double *ga, const double *gs,
+                   long long count, hipStream_t s);
+
+// Setup helpers: base_k = mu_k - beta V_k - z_k phi_fixed (-inf where V = +inf), and
+// per-block counts of fluid nodes.
+void launch_make_base(const Consts *cs, int S, long long N, const double *vext, const double *phi_fixed,
+                      double *base, const double *mu_host, const double *z_host, double *count_part, int nblk,
+                      hipStream_t s);
+void launch_sum_to(const double *part, int n, double *dst, hipStream_t s);
+void launch_copy(double *dst, const double *src, long long count, hipStream_t s);
+
+}  // namespace dft

@@ -1,0 +1,977 @@
+// Pass kernels of one residual evaluation G(rho) for gfx950.
+//
+// A residual evaluation is nine streaming passes over HBM (one per axis and direction),
+// with the method's pointwise and spectral work fused into them:
+//   X1  x: real rows -> half spectra (forward; forms the line-search trial point)
+//   Y1  y: forward
+//   Z1  z: forward, spectral products with the weight transforms (eqs. nDef, conv,
+//          Appendix B), inverse z -> ten weighted-density spectra
+//   Y2  y: inverse
+//   X2  x: inverse to real n_alpha, pointwise dPhi/dn_alpha (eq. Phi), forward again
+//   Y3  y: forward
+//   Z2  z: forward, back-convolution with conj(w_hat) (eq. muHS), bulk-fluid screening
+//          (eq. muESexpansion) and the Poisson solve (eq. potentialSolution), inverse z
+//   Y4  y: inverse
+//   X3  x: inverse to real E_k, Euler-Lagrange update (eq. rhoEquation) and residual sums
+// Each pass reads and writes every field once; the 1/N of the inverse transform is
+// applied in the z passes.  Transforms are LDS-staged mixed-radix Stockham FFTs over
+// tiles of pencils whose global accesses are contiguous along x.
+#include "dft_kernels.h"
+
+#include <cmath>
+#include <cstdio>
+#include <stdexcept>
+
+namespace dft {
+
+constexpr int NT = 256;
+
+template <typename T> struct Cfg;
+template <> struct Cfg<double> {
+    static constexpr int XE = 8, X2E = 4, YE = 8, ZE = 4, WMAX = 8;
+};
+template <> struct Cfg<float> {
+    static constexpr int XE = 16, X2E = 4, YE = 16, ZE = 4, WMAX = 16;
+};
+
+template <typename T> __device__ __forceinline__ const cx<T> *twp(const Geo &g, int axis);
+template <> __device__ __forceinline__ const cx<double> *twp<double>(const Geo &g, int axis) {
+    return reinterpret_cast<const cx<double> *>(g.tw64[axis]);
+}
+template <> __device__ __forceinline__ const cx<float> *twp<float>(const Geo &g, int axis) {
+    return reinterpret_cast<const cx<float> *>(g.tw32[axis]);
+}
+
+__device__ __forceinline__ bool gated_off(const int *gate) { return gate != nullptr && *gate == 0; }
+
+// --------------------------------------------------------------------- block reductions
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_down(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ int wave_or(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v |= __shfl_down(v, o, 64);
+    return v;
+}
+
+// Fixed-order block reduction (sum or max) of one double and an OR of one int.
+template <bool MAX>
+__device__ __forceinline__ void block_reduce(double v, int fl, double *dst, int *fdst) {
+    __shared__ double sv[NT / 64];
+    __shared__ int sf[NT / 64];
+    v = MAX ? wave_max(v) : wave_sum(v);
+    fl = wave_or(fl);
+    const int w = threadIdx.x / 64, l = threadIdx.x % 64;
+    if (l == 0) { sv[w] = v; sf[w] = fl; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = sv[0];
+        int f = sf[0];
+        for (int i = 1; i < NT / 64; ++i) { a = MAX ? fmax(a, sv[i]) : a + sv[i]; f |= sf[i]; }
+        *dst = a;
+        *fdst = f;
+    }
+}
+
+// --------------------------------------------------------------------- x passes
+// Two real rows (r0, r1) travel as the real and imaginary parts of one complex row:
+// a forward FFT of c = a + i b gives A_k = (C_k + conj C_{L-k}) / 2 and
+// B_k = (C_k - conj C_{L-k}) / (2i); the inverse rebuilds C from the Hermitian halves.
+
+template <typename T>
+__device__ __forceinline__ void x_store_halves(const cx<T> *tile, int L, int Kx, int Pact, long long pair0,
+                                               long long rows, cx<T> *out) {
+    for (int j = threadIdx.x; j < Pact * Kx; j += NT) {
+        const int pl = j / Kx, k = j - pl * Kx;
+        const cx<T> ck = tile[pl * L + k];
+        const cx<T> cm = tile[pl * L + (k == 0 ? 0 : L - k)];
+        const long long r0 = 2 * (pair0 + pl);
+        out[r0 * Kx + k] = mk<T>(T(0.5) * (ck.x + cm.x), T(0.5) * (ck.y - cm.y));
+        if (r0 + 1 < rows) out[(r0 + 1) * Kx + k] = mk<T>(T(0.5) * (ck.y + cm.y), T(-0.5) * (ck.x - cm.x));
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ cx<T> x_half_at(const cx<T> *row, int e, int L, int Kx) {
+    cx<T> v;
+    if (e < Kx) {
+        v = row[e];
+        if (e == 0 || 2 * e == L) v.y = T(0);
+    } else {
+        v = conjg(row[L - e]);
+    }
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ void x_load_halves(cx<T> *tile, int L, int Kx, int Pact, long long pair0, long long rows,
+                                              const cx<T> *in) {
+    for (int j = threadIdx.x; j < Pact * L; j += NT) {
+        const int pl = j / L, e = j - pl * L;
+        const long long r0 = 2 * (pair0 + pl);
+        const cx<T> A = x_half_at(in + r0 * Kx, e, L, Kx);
+        cx<T> B = mk<T>(T(0), T(0));
+        if (r0 + 1 < rows) B = x_half_at(in + (r0 + 1) * Kx, e, L, Kx);
+        tile[pl * L + e] = mk<T>(A.x - B.y, A.y + B.x);
+    }
+}
+
+template <typename T, int MAXE>
+__global__ __launch_bounds__(NT) void k_x_forward(Geo g, XFwdArgs a, int P) {
+    if (gated_off(a.gate)) return;
+    extern __shared__ unsigned char smem_raw[];
+    cx<T> *tile = reinterpret_cast<cx<T> *>(smem_raw);
+    const int f = blockIdx.y;
+    const int L = g.nx, Kx = g.Kx;
+    const long long rows = (long long)g.ny * g.nz;
+    const long long npairs = (rows + 1) / 2;
+    const long long pair0 = (long long)blockIdx.x * P;
+    const int Pact = (int)min((long long)P, npairs - pair0);
+    const long long foff = (long long)f * g.N;
+    const double alpha = (a.mode == XF_TRIAL) ? *a.alpha : 0.0;
+    for (int j = threadIdx.x; j < Pact * L; j += NT) {
+        const int pl = j / L, e = j - pl * L;
+        const long long r0 = 2 * (pair0 + pl);
+        double v[2] = {0.0, 0.0};
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const long long r = r0 + h;
+            if (r >= rows) break;
+            const long long idx = foff + r * L + e;
+            double x;
+            if (a.mode == XF_TRIAL) {
+                const double r0v = a.src[idx];
+                x = fma(alpha, a.g0[idx] - r0v, r0v);
+                if (a.rho_t) a.rho_t[idx] = x;
+            } else {
+                x = a.src[idx];
+            }
+            if (a.ref) x -= a.ref[idx];
+            v[h] = x;
+        }
+        tile[j] = mk<T>(T(v[0]), T(v[1]));
+    }
+    __syncthreads();
+    fft_tile<T, -1, NT, MAXE>(tile, g.px, Pact, 1, L, true, twp<T>(g, 0));
+    x_store_halves<T>(tile, L, Kx, Pact, pair0, rows, reinterpret_cast<cx<T> *>(a.spec) + (long long)f * g.NC);
+}
+
+// --------------------------------------------------------------------- y passes
+template <typename T, int MAXE>
+__global__ __launch_bounds__(NT) void k_y(Geo g, YArgs a, int W) {
+    if (gated_off(a.gate)) return;
+    extern __shared__ unsigned char smem_raw[];
+    cx<T> *tile = reinterpret_cast<cx<T> *>(smem_raw);
+    const int L = g.ny, Kx = g.Kx;
+    const int kx0 = blockIdx.x * W;
+    const int Wact = min(W, Kx - kx0);
+    const int z = blockIdx.y, f = blockIdx.z;
+    cx<T> *base = reinterpret_cast<cx<T> *>(a.spec) + (long long)f * g.NC + (long long)z * g.ny * Kx + kx0;
+    for (int j = threadIdx.x; j < Wact * L; j += NT) {
+        const int e = j / Wact, p = j - e * Wact;
+        tile[j] = base[(long long)e * Kx + p];
+    }
+    __syncthreads();
+    fft_tile_dir<T, NT, MAXE>(a.dir, tile, g.py, Wact, Wact, 1, false, twp<T>(g, 1));
+    for (int j = threadIdx.x; j < Wact * L; j += NT) {
+        const int e = j / Wact, p = j - e * Wact;
+        base[(long long)e * Kx + p] = tile[j];
+    }
+}
+
+// --------------------------------------------------------------------- z passes
+// Wavenumber data of one element of a z tile.
+struct KInfo {
+    double k[3];
+    double kmag;
+    bool nyq[3];
+    bool zero;
+};
+
+__device__ __forceinline__ KInfo kinfo(const Consts &c, int jx, int y, int e) {
+    KInfo q;
+    const int my = signed_mode(y, c.ny), mz = signed_mode(e, c.nz);
+    q.k[0] = jx * c.dk[0];
+    q.k[1] = my * c.dk[1];
+    q.k[2] = mz * c.dk[2];
+    q.kmag = sqrt(q.k[0] * q.k[0] + q.k[1] * q.k[1] + q.k[2] * q.k[2]);
+    q.nyq[0] = (c.nx % 2 == 0) && (2 * jx == c.nx);
+    q.nyq[1] = (c.ny % 2 == 0) && (2 * y == c.ny);
+    q.nyq[2] = (c.nz % 2 == 0) && (2 * e == c.nz);
+    q.zero = (jx == 0) && (y == 0) && (e == 0);
+    return q;
+}
+
+// Component d of k, zero on the Nyquist plane of axis d (register selects, no indexing).
+__device__ __forceinline__ double k_comp(const KInfo &q, int d) {
+    const double k = d == 0 ? q.k[0] : (d == 1 ? q.k[1] : q.k[2]);
+    const bool ny = d == 0 ? q.nyq[0] : (d == 1 ? q.nyq[1] : q.nyq[2]);
+    return ny ? 0.0 : k;
+}
+
+template <typename T>
+__device__ __forceinline__ void z_load(cx<T> *tile, const cx<T> *src, int Wact, int L, long long rowstride) {
+    for (int j = threadIdx.x; j < Wact * L; j += NT) {
+        const int e = j / Wact, p = j - e * Wact;
+        tile[j] = src[(long long)e * rowstride + p];
+    }
+}
+template <typename T>
+__device__ __forceinline__ void z_store(const cx<T> *tile, cx<T> *dst, int Wact, int L, long long rowstride) {
+    for (int j = threadIdx.x; j < Wact * L; j += NT) {
+        const int e = j / Wact, p = j - e * Wact;
+        dst[(long long)e * rowstride + p] = tile[j];
+    }
+}
+
+template <typename T, int MAXE>
+__global__ __launch_bounds__(NT) void k_z1(Geo g, Z1Args a, int W) {
+    if (gated_off(a.gate)) return;
+    extern __shared__ unsigned char smem_raw[];
+    cx<T> *tile = reinterpret_cast<cx<T> *>(smem_raw);
+    const Consts &c = *g.cs;
+    const int L = g.nz, Kx = g.Kx;
+    const int kx0 = blockIdx.x * W;
+    const int Wact = min(W, Kx - kx0);
+    const int y = blockIdx.y;
+    const long long rs = (long long)g.ny * Kx;
+    const long long off = (long long)y * Kx + kx0;
+    const cx<T> *tw = twp<T>(g, 2);
+    // five sums: s0 = sum rho w2/4piR^2, s1 = sum rho w2/4piR, s2 = sum rho w2, s3 = sum rho w3,
+    // s4 = sum rho w3/4piR (the vector spectra are -i k times the w3 sums)
+    double acc[5][MAXE][2];
+#pragma unroll
+    for (int m = 0; m < 5; ++m)
+#pragma unroll
+        for (int it = 0; it < MAXE; ++it) acc[m][it][0] = acc[m][it][1] = 0.0;
+    for (int i = 0; i < g.S; ++i) {
+        cx<T> *src = reinterpret_cast<cx<T> *>(a.specA) + (long long)i * g.NC + off;
+        z_load(tile, src, Wact, L, rs);
+        __syncthreads();
+        fft_tile<T, -1, NT, MAXE>(tile, g.pz, Wact, Wact, 1, false, tw);
+        const double R = c.R[i], a0 = c.i4piR2[i], a1 = c.i4piR[i];
+#pragma unroll
+        for (int it = 0; it < MAXE; ++it) {
+            const int j = threadIdx.x + it * NT;
+            if (j < Wact * L) {
+                const int e = j / Wact, p = j - e * Wact;
+                const cx<T> v = tile[j];
+                src[(long long)e * rs + p] = v;
+                const KInfo q = kinfo(c, kx0 + p, y, e);
+                double w2, w3;
+                weight_w2_w3(q.kmag, R, w2, w3);
+                const double vx = (double)v.x, vy = (double)v.y;
+                const double m0 = w2 * a0, m1 = w2 * a1, m4 = w3 * a1;
+                acc[0][it][0] += vx * m0; acc[0][it][1] += vy * m0;
+                acc[1][it][0] += vx * m1; acc[1][it][1] += vy * m1;
+                acc[2][it][0] += vx * w2; acc[2][it][1] += vy * w2;
+                acc[3][it][0] += vx * w3; acc[3][it][1] += vy * w3;
+                acc[4][it][0] += vx * m4; acc[4][it][1] += vy * m4;
+            }
+        }
+        __syncthreads();
+    }
+    const int nout = a.n3only ? 1 : DFT_NALPHA;
+    for (int o = 0; o < nout; ++o) {
+        const int alpha = a.n3only ? 3 : o;
+#pragma unroll
+        for (int it = 0; it < MAXE; ++it) {
+            const int j = threadIdx.x + it * NT;
+            if (j < Wact * L) {
+                const int e = j / Wact, p = j - e * Wact;
+                // select the source sum with compile-time register indices
+                double sx = 0.0, sy = 0.0;
+#pragma unroll
+                for (int m = 0; m < 5; ++m) {
+                    const bool pick = (alpha < 4) ? (m == alpha) : (m == (alpha < 7 ? 4 : 3));
+                    if (pick) { sx = acc[m][it][0]; sy = acc[m][it][1]; }
+                }
+                double re = sx, im = sy;
+                if (alpha >= 4) {
+                    const int d = (alpha - 4) % 3;
+                    const KInfo q = kinfo(c, kx0 + p, y, e);
+                    const double kd = k_comp(q, d);
+                    // -i k_d s
+                    re = kd * sy;
+                    im = -kd * sx;
+                }
+                tile[j] = mk<T>(T(re * c.invN), T(im * c.invN));
+            }
+        }
+        __syncthreads();
+        fft_tile<T, 1, NT, MAXE>(tile, g.pz, Wact, Wact, 1, false, tw);
+        z_store(tile, reinterpret_cast<cx<T> *>(a.specB) + (long long)o * g.NC + off, Wact, L, rs);
+        __syncthreads();
+    }
+}
+
+template <typename T, int MAXE, int MAXS>
+__global__ __launch_bounds__(NT) void k_z2(Geo g, Z2Args a, int W) {
+    if (gated_off(a.gate)) return;
+    extern __shared__ unsigned char smem_raw[];
+    cx<T> *tile = reinterpret_cast<cx<T> *>(smem_raw);
+    const Consts &c = *g.cs;
+    const int L = g.nz, Kx = g.Kx;
+    const int kx0 = blockIdx.x * W;
+    const int Wact = min(W, Kx - kx0);
+    const int y = blockIdx.y;
+    const long long rs = (long long)g.ny * Kx;
+    const long long off = (long long)y * Kx + kx0;
+    const cx<T> *tw = twp<T>(g, 2);
+    const int S = g.S;
+
+    if (a.mode == Z2_POISSON) {
+        // phi_hat = 4 pi l_B (sum_j w_j src_j) / D(k), zero mode 0; x invN; output in specA[0].
+        double acc[MAXE][2];
+#pragma unroll
+        for (int it = 0; it < MAXE; ++it) acc[it][0] = acc[it][1] = 0.0;
+        for (int i = 0; i < a.nsrc; ++i) {
+            const cx<T> *src = reinterpret_cast<const cx<T> *>(a.specA) + (long long)i * g.NC + off;
+            z_load(tile, src, Wact, L, rs);
+            __syncthreads();
+            fft_tile<T, -1, NT, MAXE>(tile, g.pz, Wact, Wact, 1, false, tw);
+#pragma unroll
+            for (int it = 0; it < MAXE; ++it) {
+                const int j = threadIdx.x + it * NT;
+                if (j < Wact * L) {
+                    acc[it][0] += a.wsrc[i] * (double)tile[j].x;
+                    acc[it][1] += a.wsrc[i] * (double)tile[j].y;
+                }
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int it = 0; it < MAXE; ++it) {
+            const int j = threadIdx.x + it * NT;
+            if (j < Wact * L) {
+                const int e = j / Wact, p = j - e * Wact;
+                const KInfo q = kinfo(c, kx0 + p, y, e);
+                double m = 0.0;
+                if (!q.zero) m = c.four_pi_lB / poisson_denominator(q.k, c.h) * c.invN;
+                tile[j] = mk<T>(T(acc[it][0] * m), T(acc[it][1] * m));
+            }
+        }
+        __syncthreads();
+        fft_tile<T, 1, NT, MAXE>(tile, g.pz, Wact, Wact, 1, false, tw);
+        z_store(tile, reinterpret_cast<cx<T> *>(a.specA) + off, Wact, L, rs);
+        return;
+    }
+
+    // six sums of the derivative spectra: u0..u3 and v1 = sum_d i k_d dPhi_V1,d, v2 likewise
+    double u[6][MAXE][2];
+#pragma unroll
+    for (int m = 0; m < 6; ++m)
+#pragma unroll
+        for (int it = 0; it < MAXE; ++it) u[m][it][0] = u[m][it][1] = 0.0;
+    for (int al = 0; al < DFT_NALPHA; ++al) {
+        const cx<T> *src = reinterpret_cast<const cx<T> *>(a.specB) + (long long)al * g.NC + off;
+        z_load(tile, src, Wact, L, rs);
+        __syncthreads();
+        fft_tile<T, -1, NT, MAXE>(tile, g.pz, Wact, Wact, 1, false, tw);
+#pragma unroll
+        for (int it = 0; it < MAXE; ++it) {
+            const int j = threadIdx.x + it * NT;
+            if (j < Wact * L) {
+                double vx = (double)tile[j].x, vy = (double)tile[j].y;
+                if (al >= 4) {
+                    const int e = j / Wact, p = j - e * Wact;
+                    const int d = (al - 4) % 3;
+                    const KInfo q = kinfo(c, kx0 + p, y, e);
+                    const double kd = k_comp(q, d);
+                    // + i k_d v
+                    const double tx = -kd * vy;
+                    vy = kd * vx;
+                    vx = tx;
+                }
+                const int m = al < 4 ? al : (al < 7 ? 4 : 5);
+#pragma unroll
+                for (int mm = 0; mm < 6; ++mm)
+                    if (mm == m) { u[mm][it][0] += vx; u[mm][it][1] += vy; }
+            }
+        }
+        __syncthreads();
+    }
+    // rho_hat of every species for the owned elements
+    double rh[MAXS][MAXE][2];
+#pragma unroll
+    for (int it = 0; it < MAXE; ++it) {
+        const int j = threadIdx.x + it * NT;
+        const int e = j / max(Wact, 1), p = j - e * Wact;
+#pragma unroll
+        for (int s = 0; s < MAXS; ++s) {
+            rh[s][it][0] = rh[s][it][1] = 0.0;
+            if (s < S && j < Wact * L) {
+                const cx<T> v = reinterpret_cast<const cx<T> *>(a.specA)[(long long)s * g.NC + off + (long long)e * rs + p];
+                rh[s][it][0] = (double)v.x;
+                rh[s][it][1] = (double)v.y;
+            }
+        }
+    }
+    __syncthreads();
+    for (int i = 0; i < S; ++i) {
+        const double R = c.R[i], a0 = c.i4piR2[i], a1 = c.i4piR[i];
+#pragma unroll
+        for (int it = 0; it < MAXE; ++it) {
+            const int j = threadIdx.x + it * NT;
+            if (j < Wact * L) {
+                const int e = j / Wact, p = j - e * Wact;
+                const KInfo q = kinfo(c, kx0 + p, y, e);
+                double w2, w3;
+                weight_w2_w3(q.kmag, R, w2, w3);
+                const double s2x = u[0][it][0] * a0 + u[1][it][0] * a1 + u[2][it][0];
+                const double s2y = u[0][it][1] * a0 + u[1][it][1] * a1 + u[2][it][1];
+                const double s3x = u[3][it][0] + u[4][it][0] * a1 + u[5][it][0];
+                const double s3y = u[3][it][1] + u[4][it][1] * a1 + u[5][it][1];
+                double ex = -(s2x * w2 + s3x * w3);
+                double ey = -(s2y * w2 + s3y * w3);
+                if (c.es) {
+                    double qx = 0.0, qy = 0.0;
+#pragma unroll
+                    for (int s = 0; s < MAXS; ++s) {
+                        if (s < S) {
+                            const int ij = i * DFT_MAX_SPECIES + s;
+                            const double C = screening_hat(q.kmag, c.sc_R[ij], c.sc_c1[ij], c.sc_c0[ij], c.sc_cm1[ij]);
+                            double rx = rh[s][it][0];
+                            if (q.zero && !a.diff) rx -= (double)c.N * c.rho_b[s];
+                            ex += C * rx;
+                            ey += C * rh[s][it][1];
+                            qx += c.z[s] * rh[s][it][0];
+                            qy += c.z[s] * rh[s][it][1];
+                        }
+                    }
+                    if (!q.zero) {
+                        const double m = c.four_pi_lB / poisson_denominator(q.k, c.h) * c.z[i];
+                        ex -= m * qx;
+                        ey -= m * qy;
+                    }
+                }
+                tile[j] = mk<T>(T(ex * c.invN), T(ey * c.invN));
+            }
+        }
+        __syncthreads();
+        fft_tile<T, 1, NT, MAXE>(tile, g.pz, Wact, Wact, 1, false, tw);
+        z_store(tile, reinterpret_cast<cx<T> *>(a.specA) + (long long)i * g.NC + off, Wact, L, rs);
+        __syncthreads();
+    }
+}
+
+// --------------------------------------------------------------------- X2: pointwise FMT
+template <typename T, int MAXE>
+__global__ __launch_bounds__(NT) void k_x2(Geo g, X2Args a, int P) {
+    if (gated_off(a.gate)) return;
+    extern __shared__ unsigned char smem_raw[];
+    cx<T> *tile = reinterpret_cast<cx<T> *>(smem_raw);
+    const int L = g.nx, Kx = g.Kx;
+    const long long rows = (long long)g.ny * g.nz;
+    const long long npairs = (rows + 1) / 2;
+    const long long pair0 = (long long)blockIdx.x * P;
+    const int Pact = (int)min((long long)P, npairs - pair0);
+    const cx<T> *tw = twp<T>(g, 0);
+    const bool n3only = a.mode == X2_N3_ONLY;
+    const int nf = n3only ? 1 : DFT_NALPHA;
+    double nv[DFT_NALPHA][MAXE][2];
+    for (int f = 0; f < nf; ++f) {
+        x_load_halves<T>(tile, L, Kx, Pact, pair0, rows, reinterpret_cast<const cx<T> *>(a.specB) + (long long)f * g.NC);
+        __syncthreads();
+        fft_tile<T, 1, NT, MAXE>(tile, g.px, Pact, 1, L, true, tw);
+#pragma unroll
+        for (int it = 0; it < MAXE; ++it) {
+            const int j = threadIdx.x + it * NT;
+            if (j < Pact * L) {
+                const double vx = (double)tile[j].x, vy = (double)tile[j].y;
+#pragma unroll
+                for (int ff = 0; ff < DFT_NALPHA; ++ff)
+                    if (ff == f) { nv[ff][it][0] = vx; nv[ff][it][1] = vy; }
+            }
+        }
+        __syncthreads();
+    }
+    double mloc = -INFINITY;
+    int flag = 0;
+#pragma unroll
+    for (int it = 0; it < MAXE; ++it) {
+        const int j = threadIdx.x + it * NT;
+        if (j >= Pact * L) continue;
+        const int pl = j / L, e = j - pl * L;
+        const long long r0 = 2 * (pair0 + pl);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const long long r = r0 + h;
+            if (r >= rows) {
+#pragma unroll
+                for (int f = 0; f < DFT_NALPHA; ++f) nv[f][it][h] = 0.0;
+                continue;
+            }
+            const long long idx = r * L + e;
+            if (n3only) {
+                double n3 = nv[0][it][h];
+                if (a.nref) n3 += (double)a.nref[3 * g.N + idx];
+                if (!isfinite(n3)) flag |= 1;
+                mloc = fmax(mloc, n3);
+                continue;
+            }
+            double n[DFT_NALPHA], d[DFT_NALPHA];
+#pragma unroll
+            for (int f = 0; f < DFT_NALPHA; ++f) n[f] = nv[f][it][h];
+            bool clamped = false;
+            if (a.nref) {
+                double nr[DFT_NALPHA], dr[DFT_NALPHA];
+#pragma unroll
+                for (int f = 0; f < DFT_NALPHA; ++f) {
+                    nr[f] = (double)a.nref[f * g.N + idx];
+                    n[f] += nr[f];
+                }
+                bool c2;
+                fmt_dphi<double>(n, d, clamped);
+                fmt_dphi<double>(nr, dr, c2);
+#pragma unroll
+                for (int f = 0; f < DFT_NALPHA; ++f) d[f] -= dr[f];
+            } else {
+                fmt_dphi<double>(n, d, clamped);
+            }
+            if (clamped) flag |= 2;
+            if (!isfinite(n[3]) || !isfinite(d[0]) || !isfinite(d[3])) flag |= 1;
+            mloc = fmax(mloc, n[3]);
+#pragma unroll
+            for (int f = 0; f < DFT_NALPHA; ++f) {
+                if (a.nref_out) a.nref_out[f * g.N + idx] = (float)n[f];
+                if (a.n_out) a.n_out[f * g.N + idx] = n[f];
+                if (a.dphi_out) a.dphi_out[f * g.N + idx] = d[f];
+                nv[f][it][h] = d[f];
+            }
+        }
+    }
+    if (flag & 1) mloc = INFINITY;
+    block_reduce<true>(mloc, flag, a.red.mpart + blockIdx.x, a.red.mflag + blockIdx.x);
+    if (n3only) return;
+    __syncthreads();
+    for (int f = 0; f < DFT_NALPHA; ++f) {
+#pragma unroll
+        for (int it = 0; it < MAXE; ++it) {
+            const int j = threadIdx.x + it * NT;
+            if (j < Pact * L) {
+                double vx = 0.0, vy = 0.0;
+#pragma unroll
+                for (int ff = 0; ff < DFT_NALPHA; ++ff)
+                    if (ff == f) { vx = nv[ff][it][0]; vy = nv[ff][it][1]; }
+                tile[j] = mk<T>(T(vx), T(vy));
+            }
+        }
+        __syncthreads();
+        fft_tile<T, -1, NT, MAXE>(tile, g.px, Pact, 1, L, true, tw);
+        x_store_halves<T>(tile, L, Kx, Pact, pair0, rows, reinterpret_cast<cx<T> *>(a.specB) + (long long)f * g.NC);
+        __syncthreads();
+    }
+}
+
+// --------------------------------------------------------------------- X3: Euler-Lagrange update
+template <typename T, int MAXE>
+__global__ __launch_bounds__(NT) void k_x3(Geo g, X3Args a, int P) {
+    if (gated_off(a.gate)) return;
+    extern __shared__ unsigned char smem_raw[];
+    cx<T> *tile = reinterpret_cast<cx<T> *>(smem_raw);
+    const Consts &c = *g.cs;
+    const int i = blockIdx.y;
+    const int L = g.nx, Kx = g.Kx;
+    const long long rows = (long long)g.ny * g.nz;
+    const long long npairs = (rows + 1) / 2;
+    const long long pair0 = (long long)blockIdx.x * P;
+    const int Pact = (int)min((long long)P, npairs - pair0);
+    x_load_halves<T>(tile, L, Kx, Pact, pair0, rows, reinterpret_cast<const cx<T> *>(a.specA) + (long long)i * g.NC);
+    __syncthreads();
+    fft_tile<T, 1, NT, MAXE>(tile, g.px, Pact, 1, L, true, twp<T>(g, 0));
+    double acc = 0.0;
+    int flag = 0;
+    const double rb = c.rho_b[i], irb = c.inv_rho_b[i];
+    for (int j = threadIdx.x; j < Pact * L; j += NT) {
+        const int pl = j / L, e = j - pl * L;
+        const long long r0 = 2 * (pair0 + pl);
+        const cx<T> v = tile[j];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const long long r = r0 + h;
+            if (r >= rows) break;
+            const double E = h == 0 ? (double)v.x : (double)v.y;
+            const long long idx = (long long)i * g.N + r * L + e;
+            if (a.raw) {
+                double o = E;
+                if (a.addend) o += a.addend[r * L + e];
+                a.raw_out[idx] = o;
+                continue;
+            }
+            const double b = a.base[idx];
+            const bool fluid = b > -INFINITY;
+            const double G = fluid ? rb * exp(b + E) : 0.0;
+            if (a.g_out) a.g_out[idx] = G;
+            if (a.e_out) a.e_out[idx] = E;
+            if (a.lp_out) a.lp_out[idx] = fluid ? b + E : -INFINITY;
+            if (fluid) {
+                const double dlt = (a.rho_t[idx] - G) * irb;
+                acc += dlt * dlt;
+                if (!isfinite(G)) flag |= 1;
+            }
+        }
+    }
+    if (a.raw) return;
+    block_reduce<false>(acc, flag, a.red.fpart + (long long)blockIdx.y * gridDim.x + blockIdx.x,
+                        a.red.fflag + (long long)blockIdx.y * gridDim.x + blockIdx.x);
+}
+
+// --------------------------------------------------------------------- launch geometry
+static void check_launch(const char *what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) throw std::runtime_error(std::string(what) + ": " + hipGetErrorString(e));
+}
+
+template <typename T, int MAXE>
+static int x_pairs(const Geo &g) {
+    int P = (NT * MAXE) / g.nx;
+    if (P < 1) throw std::runtime_error("x pass: row longer than one tile");
+    const long long npairs = ((long long)g.ny * g.nz + 1) / 2;
+    if (P > npairs) P = (int)npairs;
+    return P;
+}
+
+template <typename T, int MAXE>
+static int yz_width(int L, int Kx) {
+    int W = (NT * MAXE) / L;
+    if (W > Cfg<T>::WMAX) W = Cfg<T>::WMAX;
+    if (W > Kx) W = Kx;
+    if (W < 1) throw std::runtime_error("y/z pass: pencil longer than one tile");
+    return W;
+}
+
+static long long ceil_div(long long a, long long b) { return (a + b - 1) / b; }
+
+template <typename T>
+void launch_x_forward(const Geo &g, const XFwdArgs &a, hipStream_t s) {
+    constexpr int E = Cfg<T>::XE;
+    const int P = x_pairs<T, E>(g);
+    const long long npairs = ((long long)g.ny * g.nz + 1) / 2;
+    dim3 grid((unsigned)ceil_div(npairs, P), (unsigned)a.nfield);
+    const size_t sh = (size_t)P * g.nx * sizeof(cx<T>);
+    hipLaunchKernelGGL((k_x_forward<T, E>), grid, dim3(NT), sh, s, g, a, P);
+    check_launch("x_forward");
+}
+
+template <typename T>
+void launch_y(const Geo &g, const YArgs &a, hipStream_t s) {
+    if (g.ny == 1) return;   // a length-1 transform is the identity
+    constexpr int E = Cfg<T>::YE;
+    const int W = yz_width<T, E>(g.ny, g.Kx);
+    dim3 grid((unsigned)ceil_div(g.Kx, W), (unsigned)g.nz, (unsigned)a.nfield);
+    const size_t sh = (size_t)W * g.ny * sizeof(cx<T>);
+    hipLaunchKernelGGL((k_y<T, E>), grid, dim3(NT), sh, s, g, a, W);
+    check_launch("y");
+}
+
+template <typename T>
+void launch_z1(const Geo &g, const Z1Args &a, hipStream_t s) {
+    constexpr int E = Cfg<T>::ZE;
+    const int W = yz_width<T, E>(g.nz, g.Kx);
+    dim3 grid((unsigned)ceil_div(g.Kx, W), (unsigned)g.ny);
+    const size_t sh = (size_t)W * g.nz * sizeof(cx<T>);
+    hipLaunchKernelGGL((k_z1<T, E>), grid, dim3(NT), sh, s, g, a, W);
+    check_launch("z1");
+}
+
+template <typename T>
+void launch_z2(const Geo &g, const Z2Args &a, hipStream_t s) {
+    constexpr int E = Cfg<T>::ZE;
+    const int W = yz_width<T, E>(g.nz, g.Kx);
+    dim3 grid((unsigned)ceil_div(g.Kx, W), (unsigned)g.ny);
+    const size_t sh = (size_t)W * g.nz * sizeof(cx<T>);
+    if (g.S <= 4)
+        hipLaunchKernelGGL((k_z2<T, E, 4>), grid, dim3(NT), sh, s, g, a, W);
+    else
+        hipLaunchKernelGGL((k_z2<T, E, DFT_MAX_SPECIES>), grid, dim3(NT), sh, s, g, a, W);
+    check_launch("z2");
+}
+
+int x2_blocks(const Geo &g) {
+    const int P = (NT * 4) / g.nx > 0 ? std::min<long long>((NT * 4) / g.nx, ((long long)g.ny * g.nz + 1) / 2) : 1;
+    return (int)ceil_div(((long long)g.ny * g.nz + 1) / 2, P);
+}
+
+int x3_blocks(const Geo &g) {
+    // the larger of the two precisions' block counts
+    const long long npairs = ((long long)g.ny * g.nz + 1) / 2;
+    long long P = (NT * Cfg<double>::XE) / g.nx;
+    if (P < 1) P = 1;
+    if (P > npairs) P = npairs;
+    return (int)ceil_div(npairs, P) * g.S;
+}
+
+template <typename T>
+void launch_x2(const Geo &g, const X2Args &a, hipStream_t s) {
+    constexpr int E = Cfg<T>::X2E;
+    const int P = x_pairs<T, E>(g);
+    const long long npairs = ((long long)g.ny * g.nz + 1) / 2;
+    const long long nb = ceil_div(npairs, P);
+    if (nb > a.red.cap) throw std::runtime_error("x2: reduction buffer too small");
+    const size_t sh = (size_t)P * g.nx * sizeof(cx<T>);
+    hipLaunchKernelGGL((k_x2<T, E>), dim3((unsigned)nb), dim3(NT), sh, s, g, a, P);
+    check_launch("x2");
+}
+
+template <typename T>
+void launch_x3(const Geo &g, const X3Args &a, hipStream_t s) {
+    constexpr int E = Cfg<T>::XE;
+    const int P = x_pairs<T, E>(g);
+    const long long npairs = ((long long)g.ny * g.nz + 1) / 2;
+    const long long nb = ceil_div(npairs, P);
+    if (!a.raw && nb * a.nfield > a.red.cap) throw std::runtime_error("x3: reduction buffer too small");
+    dim3 grid((unsigned)nb, (unsigned)a.nfield);
+    const size_t sh = (size_t)P * g.nx * sizeof(cx<T>);
+    hipLaunchKernelGGL((k_x3<T, E>), grid, dim3(NT), sh, s, g, a, P);
+    check_launch("x3");
+}
+
+template void launch_x_forward<double>(const Geo &, const XFwdArgs &, hipStream_t);
+template void launch_x_forward<float>(const Geo &, const XFwdArgs &, hipStream_t);
+template void launch_y<double>(const Geo &, const YArgs &, hipStream_t);
+template void launch_y<float>(const Geo &, const YArgs &, hipStream_t);
+template void launch_z1<double>(const Geo &, const Z1Args &, hipStream_t);
+template void launch_z1<float>(const Geo &, const Z1Args &, hipStream_t);
+template void launch_z2<double>(const Geo &, const Z2Args &, hipStream_t);
+template void launch_z2<float>(const Geo &, const Z2Args &, hipStream_t);
+template void launch_x2<double>(const Geo &, const X2Args &, hipStream_t);
+template void launch_x2<float>(const Geo &, const X2Args &, hipStream_t);
+template void launch_x3<double>(const Geo &, const X3Args &, hipStream_t);
+template void launch_x3<float>(const Geo &, const X3Args &, hipStream_t);
+
+// --------------------------------------------------------------------- reductions, control
+__global__ __launch_bounds__(NT) void k_finalize(RedBufs r, int nf, int nm, double *fslot, double *mslot,
+                                                 DevState *st, int count_kind, const int *gate) {
+    if (gated_off(gate)) return;
+    __shared__ double ss[NT], sm[NT];
+    __shared__ int sf[NT];
+    double a = 0.0, m = -INFINITY;
+    int fl = 0;
+    for (int b = threadIdx.x; b < nf; b += NT) { a += r.fpart[b]; fl |= r.fflag[b]; }
+    for (int b = threadIdx.x; b < nm; b += NT) { m = fmax(m, r.mpart[b]); fl |= r.mflag[b]; }
+    ss[threadIdx.x] = a;
+    sm[threadIdx.x] = m;
+    sf[threadIdx.x] = fl;
+    __syncthreads();
+    for (int w = NT / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            ss[threadIdx.x] += ss[threadIdx.x + w];
+            sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + w]);
+            sf[threadIdx.x] |= sf[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const bool bad = (sf[0] & 1) || !isfinite(ss[0]);
+        if (fslot) *fslot = bad ? INFINITY : ss[0];
+        if (mslot) *mslot = (sf[0] & 1) ? INFINITY : sm[0];
+        if (st) {
+            if (count_kind == 1) st->gevals += 1;
+            if (count_kind == 2) st->n3evals += 1;
+        }
+    }
+}
+
+void launch_finalize(const RedBufs &r, int nf, int nm, double *fslot, double *mslot, DevState *st, int count_kind,
+                     const int *gate, hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(NT), 0, s, r, nf, nm, fslot, mslot, st, count_kind, gate);
+    check_launch("finalize");
+}
+
+constexpr double kCapFloor = 1.0 / 1024.0;
+
+// Line-search state machine (one thread).  The order of samples and the acceptance rule
+// follow the nonlinear-solver section as read in the oracle: samples at amax/2 and amax,
+// quadratic fit in t = alpha / amax, best evaluated point accepted if it lowers f.
+__global__ void k_ctl(DevState *st, int op) {
+    if (threadIdx.x != 0) return;
+    DevState &s = *st;
+    switch (op) {
+    case CTL_PRIME: {
+        s.r = sqrt(s.f0 / s.nfluid);
+        if (!isfinite(s.f0)) s.status = DFT_E_NONFINITE;
+        s.converged = s.r <= s.tol ? 1 : 0;
+        s.gate_run = (!s.converged && s.status == 0 && s.iters < s.max_iter) ? 1 : 0;
+        s.gate_one = 1;
+        s.alpha_zero = 0.0;
+        s.alpha_one = 1.0;
+        break;
+    }
+    case CTL_BEGIN: {
+        int run = s.gate_run && s.status == 0 && !s.converged && s.iters < s.max_iter &&
+                  s.rejected < 4 * s.max_iter + 16;
+        if (run && !(s.m0 < s.eta_cap)) { s.status = DFT_E_PACKING; run = 0; }
+        s.gate_run = run;
+        s.gate_full1 = run && s.cap >= 1.0;
+        s.gate_part1 = run && s.cap < 1.0;
+        s.gate_a = run;
+        s.gate_b = 0;
+        s.gate_s = 0;
+        s.gate_upd = 0;
+        s.alpha_trial = 1.0;
+        break;
+    }
+    case CTL_AMAX: {
+        if (!s.gate_run) break;
+        const double bound = (s.m1 <= s.eta_cap) ? 1.0 : (s.eta_cap - s.m0) / (s.m1 - s.m0);
+        s.amax = fmin(s.cap, bound);
+        s.alpha_trial = 0.5 * s.amax;
+        break;
+    }
+    case CTL_B: {
+        if (!s.gate_run) break;
+        s.gate_b = !(s.gate_full1 && s.amax == 1.0);
+        if (!s.gate_b) { s.fb = s.f1; s.mb = s.m1; }
+        s.alpha_trial = s.amax;
+        break;
+    }
+    case CTL_FIT: {
+        if (!s.gate_run) break;
+        const double c2 = 2.0 * (s.f0 - 2.0 * s.fa + s.fb);
+        const double c1 = s.fb - s.f0 - c2;
+        double t;
+        if (c2 > 0.0) t = fmin(fmax(-c1 / (2.0 * c2), 0.01), 1.0);
+        else t = (s.fb <= s.fa) ? 1.0 : 0.5;
+        s.t = t;
+        s.gate_s = (t != 1.0 && t != 0.5);
+        s.alpha_trial = t * s.amax;
+        break;
+    }
+    case CTL_ACCEPT: {
+        if (!s.gate_run) break;
+        double bf = s.fb, bt = 1.0, bm = s.mb;
+        int src = 0;
+        if (s.fa < bf || (s.fa == bf && 0.5 > bt)) { bf = s.fa; bt = 0.5; bm = s.ma; src = 1; }
+        if (s.gate_s && (s.fs < bf || (s.fs == bf && s.t > bt))) { bf = s.fs; bt = s.t; bm = s.ms; src = 2; }
+        s.best_f = bf;
+        if (bf < s.f0 || s.amax <= kCapFloor) {
+            if (!isfinite(bf)) { s.status = DFT_E_NONFINITE; s.gate_upd = 0; s.gate_run = 0; break; }
+            s.alpha_acc = bt * s.amax;
+            s.f0 = bf;
+            s.m0 = bm;
+            s.src = src;
+            s.gate_upd = 1;
+            if (s.alpha_acc >= 0.5 * s.cap) s.cap = fmin(1.0, 2.0 * s.cap);
+            s.iters += 1;
+        } else {
+            s.alpha_acc = 0.0;
+            s.gate_upd = 0;
+            s.cap = fmax(0.25 * s.amax, kCapFloor);
+            s.rejected += 1;
+        }
+        break;
+    }
+    case CTL_END: {
+        s.r = sqrt(s.f0 / s.nfluid);
+        s.converged = s.r <= s.tol ? 1 : 0;
+        s.gate_run = (s.gate_run && !s.converged && s.status == 0 && s.iters < s.max_iter) ? 1 : 0;
+        break;
+    }
+    }
+}
+
+void launch_ctl(DevState *st, int op, hipStream_t s) {
+    hipLaunchKernelGGL(k_ctl, dim3(1), dim3(64), 0, s, st, op);
+    check_launch("ctl");
+}
+
+__global__ __launch_bounds__(NT) void k_update(const DevState *st, double *rho0, double *g0, const double *gb,
+                                               const double *ga, const double *gs, long long count) {
+    if (!st->gate_upd) return;
+    const double alpha = st->alpha_acc;
+    const int src = st->src;
+    const double *gsrc = src == 0 ? gb : (src == 1 ? ga : gs);
+    for (long long i = (long long)blockIdx.x * NT + threadIdx.x; i < count; i += (long long)gridDim.x * NT) {
+        const double r = rho0[i];
+        rho0[i] = fma(alpha, g0[i] - r, r);
+        g0[i] = gsrc[i];
+    }
+}
+
+void launch_update(DevState *st, double *rho0, double *g0, const double *gb, const double *ga, const double *gs,
+                   long long count, hipStream_t s) {
+    const long long nb = std::min<long long>(ceil_div(count, NT), 8192);
+    hipLaunchKernelGGL(k_update, dim3((unsigned)nb), dim3(NT), 0, s, st, rho0, g0, gb, ga, gs, count);
+    check_launch("update");
+}
+
+struct BaseArgs {
+    double mu[DFT_MAX_SPECIES];
+    double z[DFT_MAX_SPECIES];
+};
+
+__global__ __launch_bounds__(NT) void k_make_base(int S, long long N, const double *vext, const double *phi,
+                                                  double *base, BaseArgs ba, double *count_part) {
+    double cnt = 0.0;
+    for (long long t = (long long)blockIdx.x * NT + threadIdx.x; t < (long long)S * N; t += (long long)gridDim.x * NT) {
+        const int i = (int)(t / N);
+        const long long x = t - (long long)i * N;
+        const double v = vext ? vext[t] : 0.0;
+        double b = -INFINITY;
+        if (isfinite(v)) {
+            b = ba.mu[i] - v;
+            if (phi) b -= ba.z[i] * phi[x];
+            cnt += 1.0;
+        } else if (isnan(v)) {
+            b = NAN;
+        }
+        base[t] = b;
+    }
+    __shared__ double sc[NT];
+    sc[threadIdx.x] = cnt;
+    __syncthreads();
+    for (int w = NT / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) sc[threadIdx.x] += sc[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) count_part[blockIdx.x] = sc[0];
+}
+
+void launch_make_base(const Consts *, int S, long long N, const double *vext, const double *phi_fixed, double *base,
+                      const double *mu_host, const double *z_host, double *count_part, int nblk, hipStream_t s) {
+    BaseArgs ba;
+    for (int i = 0; i < DFT_MAX_SPECIES; ++i) {
+        ba.mu[i] = i < S ? mu_host[i] : 0.0;
+        ba.z[i] = i < S ? z_host[i] : 0.0;
+    }
+    hipLaunchKernelGGL(k_make_base, dim3(nblk), dim3(NT), 0, s, S, N, vext, phi_fixed, base, ba, count_part);
+    check_launch("make_base");
+}
+
+__global__ __launch_bounds__(NT) void k_sum_to(const double *part, int n, double *dst) {
+    __shared__ double sc[NT];
+    double a = 0.0;
+    for (int b = threadIdx.x; b < n; b += NT) a += part[b];
+    sc[threadIdx.x] = a;
+    __syncthreads();
+    for (int w = NT / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) sc[threadIdx.x] += sc[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *dst = sc[0];
+}
+
+void launch_sum_to(const double *part, int n, double *dst, hipStream_t s) {
+    hipLaunchKernelGGL(k_sum_to, dim3(1), dim3(NT), 0, s, part, n, dst);
+    check_launch("sum_to");
+}
+
+__global__ __launch_bounds__(NT) void k_copy(double *dst, const double *src, long long n) {
+    for (long long i = (long long)blockIdx.x * NT + threadIdx.x; i < n; i += (long long)gridDim.x * NT) dst[i] = src[i];
+}
+
+void launch_copy(double *dst, const double *src, long long count, hipStream_t s) {
+    const long long nb = std::min<long long>(ceil_div(count, NT), 8192);
+    hipLaunchKernelGGL(k_copy, dim3((unsigned)nb), dim3(NT), 0, s, dst, src, count);
+    check_launch("copy");
+}
+
+}  // namespace dft

@@ -1,0 +1,156 @@
+"""Thin Python wrapper over the C ABI: argument marshalling only.
+
+Every entry point has the name of its C counterpart (dft_setup -> Solver(...),
+dft_residual -> Solver.residual, ...).  Device buffers are torch float64 CUDA
+tensors laid out [species][z][y][x]; the workspace is a torch uint8 tensor.
+"""
+import ctypes
+
+import torch
+
+from . import _abi
+
+
+def make_params(n, h, radius, valence, rho_bulk, bjerrum=0.0, electrostatics=False, precision=_abi.DFT_FP64,
+                eta_cap=0.0, flags=0):
+    """Fill a dft_params struct."""
+    p = _abi.Params()
+    S = len(radius)
+    for d in range(3):
+        p.n[d] = int(n[d])
+        p.h[d] = float(h[d])
+    p.nspecies = S
+    for k in range(min(S, _abi.MAX_SPECIES)):
+        p.radius[k] = float(radius[k])
+        p.valence[k] = float(valence[k])
+        p.rho_bulk[k] = float(rho_bulk[k])
+    p.bjerrum_length = float(bjerrum)
+    p.electrostatics = 1 if electrostatics else 0
+    p.precision = int(precision)
+    p.eta_cap = float(eta_cap)
+    p.flags = int(flags)
+    return p
+
+
+def bulk(params):
+    """dft_bulk: Appendix A bath quantities (host only)."""
+    out = _abi.BulkInfo()
+    _abi.check(_abi.load().dft_bulk(ctypes.byref(params), ctypes.byref(out)), "dft_bulk")
+    S = params.nspecies
+    return {"mu_hs": list(out.mu_hs[:S]), "beta_p": out.beta_p, "xi": list(out.xi), "gamma": out.gamma,
+            "eta_msa": out.eta_msa, "omega": out.omega, "lambda": list(out.lambda_[:S]),
+            "mu_es": list(out.mu_es[:S])}
+
+
+def workspace_size(params):
+    """dft_workspace_size (host only)."""
+    b = ctypes.c_size_t()
+    _abi.check(_abi.load().dft_workspace_size(ctypes.byref(params), ctypes.byref(b)), "dft_workspace_size")
+    return b.value
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _dev(t, shape, device):
+    if t is None:
+        return None
+    t = torch.as_tensor(t, dtype=torch.float64, device=device)
+    if tuple(t.shape) != tuple(shape):
+        t = t.reshape(shape)
+    return t.contiguous()
+
+
+class Solver:
+    """One problem on one GPU (dft_setup ... dft_destroy)."""
+
+    def __init__(self, params, beta_vext=None, fixed_charge=None, device="cuda", stream=None):
+        self.lib = _abi.load()
+        self.params = params
+        self.device = torch.device(device)
+        self.S = params.nspecies
+        nx, ny, nz = params.n[0], params.n[1], params.n[2]
+        self.shape = (self.S, nz, ny, nx)
+        self.N = nx * ny * nz
+        self.ws = torch.empty(workspace_size(params), dtype=torch.uint8, device=self.device)
+        self._vext = _dev(beta_vext, self.shape, self.device)
+        self._q = _dev(fixed_charge, (nz, ny, nx), self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        ctx = ctypes.c_void_p()
+        _abi.check(self.lib.dft_setup(ctypes.byref(params), _ptr(self._vext), _ptr(self._q), _ptr(self.ws),
+                                      self.ws.numel(), ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(ctx)),
+                   "dft_setup")
+        self.ctx = ctx
+
+    def _check_rho(self, rho):
+        if rho.dtype != torch.float64 or rho.device != self.device or not rho.is_contiguous() \
+                or tuple(rho.shape) != self.shape:
+            raise ValueError(f"rho must be a contiguous float64 {self.device} tensor of shape {self.shape}")
+
+    def residual(self, rho, g_out=None):
+        """dft_residual: (G(rho), r)."""
+        self._check_rho(rho)
+        if g_out is None:
+            g_out = torch.empty_like(rho)
+        r = ctypes.c_double()
+        _abi.check(self.lib.dft_residual(self.ctx, _ptr(rho), _ptr(g_out), ctypes.byref(r)), "dft_residual")
+        return g_out, r.value
+
+    def operators(self, rho, n=True, dphi=True, c=True, phi=True):
+        """dft_operators: weighted densities, dPhi/dn, exponent E and beta e phi at rho (FP64)."""
+        self._check_rho(rho)
+        nz, ny, nx = self.shape[1:]
+        out = {}
+        t = lambda k: torch.empty((k, nz, ny, nx), dtype=torch.float64, device=self.device)
+        out["n"] = t(_abi.NALPHA) if n else None
+        out["dphi"] = t(_abi.NALPHA) if dphi else None
+        out["c"] = t(self.S) if c else None
+        out["phi"] = t(1)[0] if phi else None
+        _abi.check(self.lib.dft_operators(self.ctx, _ptr(rho), _ptr(out["n"]), _ptr(out["dphi"]), _ptr(out["c"]),
+                                          _ptr(out["phi"])), "dft_operators")
+        return out
+
+    def set_reference(self, rho):
+        self._check_rho(rho)
+        _abi.check(self.lib.dft_set_reference(self.ctx, _ptr(rho)), "dft_set_reference")
+
+    def picard_step(self, rho):
+        """dft_picard_step: in place; returns (alpha, r)."""
+        self._check_rho(rho)
+        a, r = ctypes.c_double(), ctypes.c_double()
+        _abi.check(self.lib.dft_picard_step(self.ctx, _ptr(rho), ctypes.byref(a), ctypes.byref(r)),
+                   "dft_picard_step")
+        return a.value, r.value
+
+    def solve(self, rho, tol, max_iter=10000, raise_on_fail=True):
+        """dft_solve: in place; returns (iterations, r, status)."""
+        self._check_rho(rho)
+        it, r = ctypes.c_int32(), ctypes.c_double()
+        st = self.lib.dft_solve(self.ctx, _ptr(rho), float(tol), int(max_iter), ctypes.byref(it), ctypes.byref(r))
+        if raise_on_fail:
+            _abi.check(st, "dft_solve")
+        return it.value, r.value, st
+
+    def stats(self):
+        s = _abi.Stats()
+        _abi.check(self.lib.dft_get_stats(self.ctx, ctypes.byref(s)), "dft_get_stats")
+        return {k: getattr(s, k) for k, _ in _abi.Stats._fields_}
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.dft_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def from_problem(prob, precision=_abi.DFT_FP64, device="cuda", flags=0):
+    """Build a Solver from a workloads.Problem-like object (attributes n, h, radius, ...)."""
+    p = make_params(prob.n, prob.h, prob.radius, prob.valence, prob.rho_bulk, prob.bjerrum, prob.electrostatics,
+                    precision, 0.0 if prob.eta_cap == 0.9 else prob.eta_cap, flags)
+    return Solver(p, prob.beta_vext, prob.fixed_charge, device=device)
