@@ -213,6 +213,7 @@ void enqueue_eval_t(dft_ctx *c, const Eval &ev, hipStream_t s) {
     x3.rho_t = rho_eval;
     x3.g_out = ev.g_out;
     x3.e_out = ev.e_out;
+    x3.e_phi = (ev.e_out && c->p.electrostatics) ? c->phi_fix : nullptr;
     x3.lp_out = ev.refresh ? c->lp : nullptr;
     x3.red = c->red;
     x3.gate = ev.gate;

@@ -104,6 +104,7 @@ struct X3Args {
     const double *rho_t;      // [S][N] point of evaluation (residual)
     double *g_out;            // [S][N] G(rho_t), may be null
     double *e_out;            // [S][N] E for inspection, may be null
+    const double *e_phi;      // with e_out: beta e phi_fixed, subtracted z_k times from E (may be null)
     double *lp_out;           // FP64 refresh: base + E, may be null
     RedBufs red;
     const int *gate;

@@ -610,7 +610,7 @@ __global__ __launch_bounds__(NT) void k_x3(Geo g, X3Args a, int P) {
             const bool fluid = b > -INFINITY;
             const double G = fluid ? rb * exp(b + E) : 0.0;
             if (a.g_out) a.g_out[idx] = G;
-            if (a.e_out) a.e_out[idx] = E;
+            if (a.e_out) a.e_out[idx] = a.e_phi ? E - c.z[i] * a.e_phi[r * L + e] : E;
             if (a.lp_out) a.lp_out[idx] = fluid ? b + E : -INFINITY;
             if (fluid) {
                 const double dlt = (a.rho_t[idx] - G) * irb;

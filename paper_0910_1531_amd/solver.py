@@ -69,6 +69,8 @@ class Solver:
         self.lib = _abi.load()
         self.params = params
         self.device = torch.device(device)
+        if self.device.type == "cuda" and self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
         self.S = params.nspecies
         nx, ny, nz = params.n[0], params.n[1], params.n[2]
         self.shape = (self.S, nz, ny, nx)
