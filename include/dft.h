@@ -198,6 +198,27 @@ dft_status dft_picard_step(dft_ctx *ctx, double *rho_inout, double *alpha_out, d
 dft_status dft_solve(dft_ctx *ctx, double *rho_inout, double tol, int32_t max_iter,
                      int32_t *iters_out, double *norm_out);
 
+/*
+ * Exactly nsteps line-search Picard steps (nonlinear-solver section) on rho_inout
+ * (device [S][N]), launched as the captured HIP graph with no convergence stop and one
+ * synchronization at the end.  Continues from the previous dft_run / dft_picard_step /
+ * dft_solve state when rho_inout is the buffer those calls last used.  FP32-mixed mode
+ * keeps the current reference state (no refresh).  iters_out (accepted steps) and
+ * norm_out (r at the last iterate): host, may be NULL.  For benchmarks and for callers
+ * that schedule their own stopping rule.
+ */
+dft_status dft_run(dft_ctx *ctx, double *rho_inout, int32_t nsteps, int32_t *iters_out, double *norm_out);
+
+/* Passes of one residual evaluation, in launch order (see dft_profile). */
+#define DFT_NPASS 10   /* x fwd, y fwd, z weights, y inv, x FMT, y fwd, z back+ES, y inv, x EL, reduce */
+
+/*
+ * Timing of the passes of one residual evaluation at rho (device [S][N]) in the ctx's
+ * precision, measured with HIP events recorded between the launches on the ctx stream
+ * and averaged over reps evaluations.  ms_out: host [DFT_NPASS], milliseconds per launch.
+ */
+dft_status dft_profile(dft_ctx *ctx, const double *rho, int32_t reps, double *ms_out);
+
 /* Counters of the ctx (host out). */
 dft_status dft_get_stats(dft_ctx *ctx, dft_stats *out);
 

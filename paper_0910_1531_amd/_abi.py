@@ -7,6 +7,9 @@ LIB_PATH = os.path.join(HERE, "libdftpicard.so")
 
 MAX_SPECIES = 8
 NALPHA = 10
+NPASS = 10
+PASS_NAMES = ["x_fwd", "y_fwd", "z_weights", "y_inv", "x_fmt", "y_fwd2", "z_back_es", "y_inv2",
+              "x_el", "reduce"]
 
 DFT_OK = 0
 STATUS_NAMES = {0: "DFT_OK", 1: "DFT_E_INVALID_ARG", 2: "DFT_E_UNSUPPORTED_SIZE", 3: "DFT_E_WORKSPACE",
@@ -59,6 +62,8 @@ SIGNATURES = [
     ("dft_set_reference", [_vp, _vp]),
     ("dft_picard_step", [_vp, _vp, _dp, _dp]),
     ("dft_solve", [_vp, _vp, ctypes.c_double, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), _dp]),
+    ("dft_run", [_vp, _vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), _dp]),
+    ("dft_profile", [_vp, _vp, ctypes.c_int32, _dp]),
     ("dft_get_stats", [_vp, ctypes.POINTER(Stats)]),
     ("dft_destroy", [_vp]),
 ]

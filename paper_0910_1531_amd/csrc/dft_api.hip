@@ -160,7 +160,12 @@ struct Eval {
     const int *gate = nullptr;
     bool fp64 = true;              // transforms in FP64 (FP64 ctx, or FP32-mixed refresh/inspection)
     bool refresh = false;          // FP32-mixed: write the reference fields
+    hipEvent_t *events = nullptr;  // if set: DFT_NPASS + 1 events recorded around the launches
 };
+
+inline void mark(const Eval &ev, int k, hipStream_t s) {
+    if (ev.events) HIPCHK(hipEventRecord(ev.events[k], s));
+}
 
 template <typename T>
 void enqueue_eval_t(dft_ctx *c, const Eval &ev, hipStream_t s) {
@@ -177,13 +182,18 @@ void enqueue_eval_t(dft_ctx *c, const Eval &ev, hipStream_t s) {
     xa.nfield = g.S;
     xa.mode = ev.trial ? XF_TRIAL : XF_PLAIN;
     xa.gate = ev.gate;
+    mark(ev, 0, s);
     launch_x_forward<T>(g, xa, s);
+    mark(ev, 1, s);
     YArgs ya{c->specA, g.S, -1, ev.gate};
     launch_y<T>(g, ya, s);
+    mark(ev, 2, s);
     Z1Args z1{c->specA, c->specB, 0, ev.gate};
     launch_z1<T>(g, z1, s);
+    mark(ev, 3, s);
     YArgs yb{c->specB, DFT_NALPHA, 1, ev.gate};
     launch_y<T>(g, yb, s);
+    mark(ev, 4, s);
     X2Args x2{};
     x2.specB = c->specB;
     x2.mode = X2_FULL;
@@ -194,8 +204,10 @@ void enqueue_eval_t(dft_ctx *c, const Eval &ev, hipStream_t s) {
     x2.red = c->red;
     x2.gate = ev.gate;
     launch_x2<T>(g, x2, s);
+    mark(ev, 5, s);
     YArgs yc{c->specB, DFT_NALPHA, -1, ev.gate};
     launch_y<T>(g, yc, s);
+    mark(ev, 6, s);
     Z2Args z2{};
     z2.specB = c->specB;
     z2.specA = c->specA;
@@ -203,8 +215,10 @@ void enqueue_eval_t(dft_ctx *c, const Eval &ev, hipStream_t s) {
     z2.diff = diff ? 1 : 0;
     z2.gate = ev.gate;
     launch_z2<T>(g, z2, s);
+    mark(ev, 7, s);
     YArgs yd{c->specA, g.S, 1, ev.gate};
     launch_y<T>(g, yd, s);
+    mark(ev, 8, s);
     X3Args x3{};
     x3.specA = c->specA;
     x3.nfield = g.S;
@@ -218,8 +232,10 @@ void enqueue_eval_t(dft_ctx *c, const Eval &ev, hipStream_t s) {
     x3.red = c->red;
     x3.gate = ev.gate;
     launch_x3<T>(g, x3, s);
+    mark(ev, 9, s);
     launch_finalize(c->red, nparts_x3(g, sizeof(T) == 4), nparts_x2(g), ev.fslot, ev.mslot, c->st, ev.count_kind,
                     ev.gate, s);
+    mark(ev, 10, s);
 }
 
 void enqueue_eval(dft_ctx *c, const Eval &ev, hipStream_t s) {
@@ -713,6 +729,75 @@ dft_status dft_solve(dft_ctx *ctx, double *rho_inout, double tol, int32_t max_it
         if (iters_out) *iters_out = (int32_t)h.iters;
         if (norm_out) *norm_out = h.r;
         return out;
+    });
+}
+
+dft_status dft_run(dft_ctx *ctx, double *rho_inout, int32_t nsteps, int32_t *iters_out, double *norm_out) {
+    if (!ctx || !rho_inout) return fail(DFT_E_INVALID_ARG, "ctx or rho is NULL");
+    if (nsteps < 0) return fail(DFT_E_INVALID_ARG, "nsteps must be >= 0");
+    return guarded([&]() -> dft_status {
+        const long long SN = (long long)ctx->geo.S * ctx->geo.N;
+        if (ctx->step_rho != rho_inout) {
+            DevState h = fresh_state(ctx, 0.0, 1LL << 60);
+            write_state(ctx, h);
+            launch_copy(ctx->rho0, rho_inout, SN, ctx->stream);
+            enqueue_prime(ctx, ctx->stream);
+            if (ctx->mixed) ctx->refreshes += 1;
+            ctx->step_rho = rho_inout;
+        }
+        DevState h0 = read_state(ctx);
+        if (h0.status) return status_from(h0);
+        const long long it0 = h0.iters;
+        h0.tol = 0.0;
+        h0.max_iter = 1LL << 60;
+        h0.gate_run = 1;
+        h0.converged = 0;
+        write_state(ctx, h0);
+        ensure_graph(ctx);
+        for (int k = 0; k < nsteps; ++k) HIPCHK(hipGraphLaunch(ctx->gexec, ctx->stream));
+        launch_copy(rho_inout, ctx->rho0, SN, ctx->stream);
+        DevState h = read_state(ctx);
+        if (iters_out) *iters_out = (int32_t)(h.iters - it0);
+        if (norm_out) *norm_out = h.r;
+        return status_from(h);
+    });
+}
+
+dft_status dft_profile(dft_ctx *ctx, const double *rho, int32_t reps, double *ms_out) {
+    if (!ctx || !rho || !ms_out || reps < 1) return fail(DFT_E_INVALID_ARG, "bad argument to dft_profile");
+    return guarded([&]() -> dft_status {
+        if (ctx->mixed && ctx->refreshes == 0) {
+            dft_status s2 = dft_set_reference(ctx, rho);
+            if (s2 != DFT_OK) return s2;
+        }
+        hipEvent_t ev[DFT_NPASS + 1];
+        for (auto &e : ev) HIPCHK(hipEventCreate(&e));
+        std::vector<double> acc(DFT_NPASS, 0.0);
+        try {
+            for (int r = 0; r < reps; ++r) {
+                Eval e;
+                e.src = rho;
+                e.g_out = ctx->gs;
+                e.fslot = &ctx->st->best_f;
+                e.fp64 = !ctx->mixed;
+                e.count_kind = 0;
+                e.events = ev;
+                enqueue_eval(ctx, e, ctx->stream);
+                HIPCHK(hipEventSynchronize(ev[DFT_NPASS]));
+                for (int k = 0; k < DFT_NPASS; ++k) {
+                    float ms = 0.f;
+                    HIPCHK(hipEventElapsedTime(&ms, ev[k], ev[k + 1]));
+                    acc[k] += ms;
+                }
+            }
+        } catch (...) {
+            for (auto &e : ev) (void)hipEventDestroy(e);
+            throw;
+        }
+        for (auto &e : ev) HIPCHK(hipEventDestroy(e));
+        for (int k = 0; k < DFT_NPASS; ++k) ms_out[k] = acc[k] / reps;
+        ctx->step_rho = nullptr;
+        return DFT_OK;
     });
 }
 

@@ -134,6 +134,20 @@ class Solver:
             _abi.check(st, "dft_solve")
         return it.value, r.value, st
 
+    def run(self, rho, nsteps):
+        """dft_run: exactly nsteps graph-launched steps in place; returns (accepted, r)."""
+        self._check_rho(rho)
+        it, r = ctypes.c_int32(), ctypes.c_double()
+        _abi.check(self.lib.dft_run(self.ctx, _ptr(rho), int(nsteps), ctypes.byref(it), ctypes.byref(r)), "dft_run")
+        return it.value, r.value
+
+    def profile(self, rho, reps=5):
+        """dft_profile: milliseconds per pass of one residual evaluation (HIP events)."""
+        self._check_rho(rho)
+        ms = (ctypes.c_double * _abi.NPASS)()
+        _abi.check(self.lib.dft_profile(self.ctx, _ptr(rho), int(reps), ms), "dft_profile")
+        return dict(zip(_abi.PASS_NAMES, list(ms)))
+
     def stats(self):
         s = _abi.Stats()
         _abi.check(self.lib.dft_get_stats(self.ctx, ctypes.byref(s)), "dft_get_stats")
