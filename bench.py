@@ -127,6 +127,8 @@ def main():
     ap.add_argument("--profile-reps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fp64-only", action="store_true")
+    ap.add_argument("--profile-only", action="store_true",
+                    help="only the per-pass HIP-event profile (for rocprofv3 runs: every launch does full work)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -139,6 +141,21 @@ def main():
     from paper_0910_1531_amd import _abi
 
     prob = W.config_pore(n=args.n, tol=args.tol)
+    if args.profile_only:
+        from paper_0910_1531_amd import solver as sv
+        out = {}
+        for name, prec in (("mixed", _abi.DFT_FP32_MIXED), ("fp64", _abi.DFT_FP64)):
+            if args.fp64_only and name == "mixed":
+                continue
+            sol = sv.from_problem(prob, precision=prec)
+            rho = torch.tensor(prob.initial_density(), dtype=torch.float64, device="cuda")
+            prof = sol.profile(rho, reps=args.profile_reps)
+            pb = pass_bytes(prob, name == "mixed")
+            out[name] = {k: {"ms": round(v, 4), "GBs": round(pb[k] / (v * 1e-3) / 1e9, 1) if v > 0 else None}
+                         for k, v in prof.items()}
+            sol.close()
+        print(json.dumps({"profile_only": True, "workload": f"charged pore {args.n}^3", "passes": out}), flush=True)
+        return
     legs = {}
     if not args.fp64_only:
         legs["mixed"] = gpu_leg(prob, _abi.DFT_FP32_MIXED, args.steps, args.warmup, args.tol, args.profile_reps)

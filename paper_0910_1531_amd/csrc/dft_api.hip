@@ -188,7 +188,7 @@ void enqueue_eval_t(dft_ctx *c, const Eval &ev, hipStream_t s) {
     YArgs ya{c->specA, g.S, -1, ev.gate};
     launch_y<T>(g, ya, s);
     mark(ev, 2, s);
-    Z1Args z1{c->specA, c->specB, 0, ev.gate};
+    Z1Args z1{c->specA, c->specB, 0, diff ? 1 : 0, ev.gate};
     launch_z1<T>(g, z1, s);
     mark(ev, 3, s);
     YArgs yb{c->specB, DFT_NALPHA, 1, ev.gate};
@@ -212,7 +212,6 @@ void enqueue_eval_t(dft_ctx *c, const Eval &ev, hipStream_t s) {
     z2.specB = c->specB;
     z2.specA = c->specA;
     z2.mode = Z2_EL;
-    z2.diff = diff ? 1 : 0;
     z2.gate = ev.gate;
     launch_z2<T>(g, z2, s);
     mark(ev, 7, s);
@@ -233,8 +232,8 @@ void enqueue_eval_t(dft_ctx *c, const Eval &ev, hipStream_t s) {
     x3.gate = ev.gate;
     launch_x3<T>(g, x3, s);
     mark(ev, 9, s);
-    launch_finalize(c->red, nparts_x3(g, sizeof(T) == 4), nparts_x2(g), ev.fslot, ev.mslot, c->st, ev.count_kind,
-                    ev.gate, s);
+    launch_finalize(c->red, nparts_x3(g, sizeof(T) == 4), x2_nblocks<T>(g), ev.fslot, ev.mslot, c->st,
+                    ev.count_kind, ev.gate, s);
     mark(ev, 10, s);
 }
 
@@ -261,7 +260,7 @@ void enqueue_n3_t(dft_ctx *c, const double *alpha, double *mslot, const int *gat
     launch_x_forward<T>(g, xa, s);
     YArgs ya{c->specA, g.S, -1, gate};
     launch_y<T>(g, ya, s);
-    Z1Args z1{c->specA, c->specB, 1, gate};
+    Z1Args z1{c->specA, c->specB, 1, diff ? 1 : 0, gate};
     launch_z1<T>(g, z1, s);
     YArgs yb{c->specB, 1, 1, gate};
     launch_y<T>(g, yb, s);
@@ -272,7 +271,7 @@ void enqueue_n3_t(dft_ctx *c, const double *alpha, double *mslot, const int *gat
     x2.red = c->red;
     x2.gate = gate;
     launch_x2<T>(g, x2, s);
-    launch_finalize(c->red, 0, nparts_x2(g), nullptr, mslot, c->st, 2, gate, s);
+    launch_finalize(c->red, 0, x2_nblocks<T>(g), nullptr, mslot, c->st, 2, gate, s);
 }
 
 void enqueue_step(dft_ctx *c, hipStream_t s) {

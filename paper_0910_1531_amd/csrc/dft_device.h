@@ -204,69 +204,78 @@ struct SincSeries {   // sin(y)/y = sum (-1)^n y^{2n} / (2n+1)!
     }
 };
 
-template <typename S>
-__device__ __forceinline__ double horner_y2(const S &s, double y2) {
-    double acc = s.c[kSeriesTerms - 1];
+template <typename R, typename S>
+__device__ __forceinline__ R horner_y2(const S &s, R y2) {
+    R acc = R(s.c[kSeriesTerms - 1]);
 #pragma unroll
-    for (int n = kSeriesTerms - 2; n >= 0; --n) acc = fma(acc, y2, s.c[n]);
+    for (int n = kSeriesTerms - 2; n >= 0; --n) acc = fma(acc, y2, R(s.c[n]));
     return acc;
 }
 
 constexpr double kFourPi = 12.566370614359172953850573533118011536788677597500;
 
+__device__ __forceinline__ void sincos_r(double y, double *s, double *c) { sincos(y, s, c); }
+__device__ __forceinline__ void sincos_r(float y, float *s, float *c) { sincosf(y, s, c); }
+
 // Weight transforms of a sphere of radius R at |k| (Appendix B):
 //   w2 = 4 pi R sin(kR) / k,   w3 = 4 pi (sin kR - kR cos kR) / k^3.
-__device__ __forceinline__ void weight_w2_w3(double k, double R, double &w2, double &w3) {
-    const double y = k * R;
-    const double R2 = R * R;
-    if (y < 1.0) {
+// R is the arithmetic type (double for FP64 evaluations, float for FP32 differences).
+template <typename R>
+__device__ __forceinline__ void weight_w2_w3(R k, R Rad, R &w2, R &w3) {
+    const R y = k * Rad;
+    const R R2 = Rad * Rad;
+    if (y < R(1)) {
         constexpr SincSeries s0{};
         constexpr BallSeries<0> s3{};
-        const double y2 = y * y;
-        w2 = kFourPi * R2 * horner_y2(s0, y2);
-        w3 = kFourPi * R2 * R * horner_y2(s3, y2);
+        const R y2 = y * y;
+        w2 = R(kFourPi) * R2 * horner_y2<R>(s0, y2);
+        w3 = R(kFourPi) * R2 * Rad * horner_y2<R>(s3, y2);
     } else {
-        double s, c;
-        sincos(y, &s, &c);
-        const double iy = 1.0 / y;
-        w2 = kFourPi * R2 * s * iy;
-        w3 = kFourPi * R2 * R * (s - y * c) * iy * iy * iy;
+        R s, c;
+        sincos_r(y, &s, &c);
+        const R iy = R(1) / y;
+        w2 = R(kFourPi) * R2 * s * iy;
+        w3 = R(kFourPi) * R2 * Rad * (s - y * c) * iy * iy * iy;
     }
 }
 
 // Bulk-fluid kernel transform for one pair: c1 F1 + c0 F0 + cm1 Fm1 with
 // F_m = integral over |r| <= Rc of r^m exp(-i k.r) = (4 pi / k) I_m(Rc, k).
-__device__ __forceinline__ double screening_hat(double k, double Rc, double c1, double c0, double cm1) {
-    const double y = k * Rc;
-    const double R2 = Rc * Rc;
-    double Fm1, F0, F1;
-    if (y < 1.0) {
+template <typename R>
+__device__ __forceinline__ R screening_hat(R k, R Rc, R c1, R c0, R cm1) {
+    const R y = k * Rc;
+    const R R2 = Rc * Rc;
+    R Fm1, F0, F1;
+    if (y < R(1)) {
         constexpr BallSeries<-1> sm{};
         constexpr BallSeries<0> s0{};
         constexpr BallSeries<1> s1{};
-        const double y2 = y * y;
-        Fm1 = kFourPi * R2 * horner_y2(sm, y2);
-        F0 = kFourPi * R2 * Rc * horner_y2(s0, y2);
-        F1 = kFourPi * R2 * R2 * horner_y2(s1, y2);
+        const R y2 = y * y;
+        Fm1 = R(kFourPi) * R2 * horner_y2<R>(sm, y2);
+        F0 = R(kFourPi) * R2 * Rc * horner_y2<R>(s0, y2);
+        F1 = R(kFourPi) * R2 * R2 * horner_y2<R>(s1, y2);
     } else {
-        double s, c;
-        sincos(y, &s, &c);
-        const double omc = (c > 0.0) ? s * s / (1.0 + c) : 1.0 - c;   // 1 - cos y without cancellation
-        const double iy = 1.0 / y, iy2 = iy * iy;
-        Fm1 = kFourPi * R2 * omc * iy2;
-        F0 = kFourPi * R2 * Rc * (s - y * c) * iy2 * iy;
-        F1 = kFourPi * R2 * R2 * (-c * iy2 + 2.0 * s * iy2 * iy - 2.0 * omc * iy2 * iy2);
+        R s, c;
+        sincos_r(y, &s, &c);
+        const R omc = (c > R(0)) ? s * s / (R(1) + c) : R(1) - c;   // 1 - cos y without cancellation
+        const R iy = R(1) / y, iy2 = iy * iy;
+        Fm1 = R(kFourPi) * R2 * omc * iy2;
+        F0 = R(kFourPi) * R2 * Rc * (s - y * c) * iy2 * iy;
+        F1 = R(kFourPi) * R2 * R2 * (-c * iy2 + R(2) * s * iy2 * iy - R(2) * omc * iy2 * iy2);
     }
     return c1 * F1 + c0 * F0 + cm1 * Fm1;
 }
 
 // Eigenvalue of minus the 7-point Laplacian for wavenumber components kd.
-__device__ __forceinline__ double poisson_denominator(const double kd[3], const double h[3]) {
-    double D = 0.0;
+template <typename R>
+__device__ __forceinline__ R poisson_denominator(const R kd[3], const double h[3]) {
+    R D = R(0);
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        const double s = sin(0.5 * kd[d] * h[d]);
-        D += 4.0 * s * s / (h[d] * h[d]);
+        const R hd = R(h[d]);
+        R s, c;
+        sincos_r(R(0.5) * kd[d] * hd, &s, &c);
+        D += R(4) * s * s / (hd * hd);
     }
     return D;
 }

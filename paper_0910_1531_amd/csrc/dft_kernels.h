@@ -67,17 +67,18 @@ struct YArgs {
 };
 
 struct Z1Args {
-    void *specA;        // [S] in (after x, y forward), out: rho_hat (unnormalized)
+    void *specA;        // [S] in (after x, y forward); out with electrostatics: the unnormalized
+                        // electrostatic spectra sum_j (C_ij - z_i z_j 4 pi l_B / D) rho_hat_j
     void *specB;        // [10] out: n_alpha half spectra after inverse z (x invN)
     int n3only;         // only n3 into specB[0]
+    int diff;           // FP32-mixed difference evaluation: no bath subtraction
     const int *gate;
 };
 
 struct Z2Args {
     void *specB;        // [10] dPhi/dn half spectra after x, y forward
-    void *specA;        // [S] in: rho_hat; out: E_hat after inverse z (x invN)
+    void *specA;        // [S] in: electrostatic spectra from Z1; out: E_hat after inverse z (x invN)
     int mode;           // Z2_EL or Z2_POISSON
-    int diff;           // FP32-mixed difference evaluation: no bath subtraction
     int nsrc;           // Z2_POISSON: number of source fields in specA
     double wsrc[DFT_MAX_SPECIES];   // Z2_POISSON: weights of the sources
     const int *gate;
@@ -120,6 +121,7 @@ template <typename T> void launch_x3(const Geo &g, const X3Args &a, hipStream_t 
 
 // Number of blocks the reductions of X2 / X3 produce (sizes the partial arrays).
 int x2_blocks(const Geo &g);
+template <typename T> int x2_nblocks(const Geo &g);   // partials written by launch_x2<T>
 int x3_blocks(const Geo &g);
 
 // Reduction of the partials into state slots (single block, fixed order).

@@ -44,6 +44,19 @@ template <> __device__ __forceinline__ const cx<float> *twp<float>(const Geo &g,
 
 __device__ __forceinline__ bool gated_off(const int *gate) { return gate != nullptr && *gate == 0; }
 
+// Block coordinates with consecutive column chunks kept on one XCD: blocks are dispatched
+// round-robin over the 8 XCDs by linear id, so linear ids are regrouped into 8 contiguous
+// runs (when the grid divides evenly) and neighbouring chunks share an L2.
+__device__ __forceinline__ void xcd_block(int &bx, int &by) {
+    const int gx = gridDim.x, gy = gridDim.y;
+    const int B = gx * gy;
+    int l = blockIdx.x + gx * blockIdx.y;
+    if ((B & 7) == 0) l = (l & 7) * (B >> 3) + (l >> 3);
+    bx = l % gx;
+    by = l / gx;
+}
+
+
 // --------------------------------------------------------------------- block reductions
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -62,10 +75,10 @@ __device__ __forceinline__ int wave_or(int v) {
 }
 
 // Fixed-order block reduction (sum or max) of one double and an OR of one int.
-template <bool MAX>
-__device__ __forceinline__ void block_reduce(double v, int fl, double *dst, int *fdst) {
-    __shared__ double sv[NT / 64];
-    __shared__ int sf[NT / 64];
+template <bool MAX, int NTB>
+__device__ __forceinline__ void block_reduce_nt(double v, int fl, double *dst, int *fdst) {
+    __shared__ double sv[NTB / 64];
+    __shared__ int sf[NTB / 64];
     v = MAX ? wave_max(v) : wave_sum(v);
     fl = wave_or(fl);
     const int w = threadIdx.x / 64, l = threadIdx.x % 64;
@@ -74,10 +87,15 @@ __device__ __forceinline__ void block_reduce(double v, int fl, double *dst, int 
     if (threadIdx.x == 0) {
         double a = sv[0];
         int f = sf[0];
-        for (int i = 1; i < NT / 64; ++i) { a = MAX ? fmax(a, sv[i]) : a + sv[i]; f |= sf[i]; }
+        for (int i = 1; i < NTB / 64; ++i) { a = MAX ? fmax(a, sv[i]) : a + sv[i]; f |= sf[i]; }
         *dst = a;
         *fdst = f;
     }
+}
+
+template <bool MAX>
+__device__ __forceinline__ void block_reduce(double v, int fl, double *dst, int *fdst) {
+    block_reduce_nt<MAX, NT>(v, fl, dst, fdst);
 }
 
 // --------------------------------------------------------------------- x passes
@@ -170,9 +188,11 @@ __global__ __launch_bounds__(NT) void k_y(Geo g, YArgs a, int W) {
     extern __shared__ unsigned char smem_raw[];
     cx<T> *tile = reinterpret_cast<cx<T> *>(smem_raw);
     const int L = g.ny, Kx = g.Kx;
-    const int kx0 = blockIdx.x * W;
+    int bx, z;
+    xcd_block(bx, z);
+    const int kx0 = bx * W;
     const int Wact = min(W, Kx - kx0);
-    const int z = blockIdx.y, f = blockIdx.z;
+    const int f = blockIdx.z;
     cx<T> *base = reinterpret_cast<cx<T> *>(a.spec) + (long long)f * g.NC + (long long)z * g.ny * Kx + kx0;
     for (int j = threadIdx.x; j < Wact * L; j += NT) {
         const int e = j / Wact, p = j - e * Wact;
@@ -231,54 +251,111 @@ __device__ __forceinline__ void z_store(const cx<T> *tile, cx<T> *dst, int Wact,
     }
 }
 
-template <typename T, int MAXE>
+// Z1: forward z transform of every species, then
+//   (a) the five weighted sums of Appendix B spectra that give the ten n_alpha spectra
+//       (the vector spectra are -i k times a w3 sum), inverse z -> specB;
+//   (b) with electrostatics, per species i the linear electrostatic part of the exponent
+//       sum_j [C_ij(k) - z_i z_j 4 pi l_B / D(k)] (rho_hat_j - N rho_b_j delta_k0)
+//       (eqs. muESexpansion, potentialSolution), written unnormalized over rho_hat in specA.
+// Spectral factors are evaluated in the transform precision T.
+template <typename T, int MAXE, int MAXS>
 __global__ __launch_bounds__(NT) void k_z1(Geo g, Z1Args a, int W) {
     if (gated_off(a.gate)) return;
     extern __shared__ unsigned char smem_raw[];
     cx<T> *tile = reinterpret_cast<cx<T> *>(smem_raw);
     const Consts &c = *g.cs;
-    const int L = g.nz, Kx = g.Kx;
-    const int kx0 = blockIdx.x * W;
+    const int L = g.nz, Kx = g.Kx, S = g.S;
+    int bx, y;
+    xcd_block(bx, y);
+    const int kx0 = bx * W;
     const int Wact = min(W, Kx - kx0);
-    const int y = blockIdx.y;
     const long long rs = (long long)g.ny * Kx;
     const long long off = (long long)y * Kx + kx0;
     const cx<T> *tw = twp<T>(g, 2);
-    // five sums: s0 = sum rho w2/4piR^2, s1 = sum rho w2/4piR, s2 = sum rho w2, s3 = sum rho w3,
-    // s4 = sum rho w3/4piR (the vector spectra are -i k times the w3 sums)
-    double acc[5][MAXE][2];
+    const bool es = c.es && !a.n3only;
+    T kmag[MAXE], invD[MAXE];
+    bool kzero[MAXE];
 #pragma unroll
-    for (int m = 0; m < 5; ++m)
+    for (int it = 0; it < MAXE; ++it) {
+        const int j = threadIdx.x + it * NT;
+        kmag[it] = T(0);
+        invD[it] = T(0);
+        kzero[it] = false;
+        if (j < Wact * L) {
+            const int e = j / Wact, p = j - e * Wact;
+            const KInfo q = kinfo(c, kx0 + p, y, e);
+            kmag[it] = T(q.kmag);
+            kzero[it] = q.zero;
+            if (es && !q.zero) {
+                const T kd[3] = {T(q.k[0]), T(q.k[1]), T(q.k[2])};
+                invD[it] = T(c.four_pi_lB) / poisson_denominator<T>(kd, c.h);
+            }
+        }
+    }
+    T acc[5][MAXE][2];
+    T esa[MAXS][MAXE][2];
 #pragma unroll
-        for (int it = 0; it < MAXE; ++it) acc[m][it][0] = acc[m][it][1] = 0.0;
-    for (int i = 0; i < g.S; ++i) {
-        cx<T> *src = reinterpret_cast<cx<T> *>(a.specA) + (long long)i * g.NC + off;
+    for (int it = 0; it < MAXE; ++it) {
+#pragma unroll
+        for (int m = 0; m < 5; ++m) acc[m][it][0] = acc[m][it][1] = T(0);
+#pragma unroll
+        for (int m = 0; m < MAXS; ++m) esa[m][it][0] = esa[m][it][1] = T(0);
+    }
+    for (int jsp = 0; jsp < S; ++jsp) {
+        const cx<T> *src = reinterpret_cast<const cx<T> *>(a.specA) + (long long)jsp * g.NC + off;
         z_load(tile, src, Wact, L, rs);
         __syncthreads();
         fft_tile<T, -1, NT, MAXE>(tile, g.pz, Wact, Wact, 1, false, tw);
-        const double R = c.R[i], a0 = c.i4piR2[i], a1 = c.i4piR[i];
+        const T Rj = T(c.R[jsp]), a0 = T(c.i4piR2[jsp]), a1 = T(c.i4piR[jsp]);
 #pragma unroll
         for (int it = 0; it < MAXE; ++it) {
             const int j = threadIdx.x + it * NT;
             if (j < Wact * L) {
-                const int e = j / Wact, p = j - e * Wact;
                 const cx<T> v = tile[j];
-                src[(long long)e * rs + p] = v;
-                const KInfo q = kinfo(c, kx0 + p, y, e);
-                double w2, w3;
-                weight_w2_w3(q.kmag, R, w2, w3);
-                const double vx = (double)v.x, vy = (double)v.y;
-                const double m0 = w2 * a0, m1 = w2 * a1, m4 = w3 * a1;
-                acc[0][it][0] += vx * m0; acc[0][it][1] += vy * m0;
-                acc[1][it][0] += vx * m1; acc[1][it][1] += vy * m1;
-                acc[2][it][0] += vx * w2; acc[2][it][1] += vy * w2;
-                acc[3][it][0] += vx * w3; acc[3][it][1] += vy * w3;
-                acc[4][it][0] += vx * m4; acc[4][it][1] += vy * m4;
+                T w2, w3;
+                weight_w2_w3<T>(kmag[it], Rj, w2, w3);
+                const T m0 = w2 * a0, m1 = w2 * a1, m4 = w3 * a1;
+                acc[0][it][0] += v.x * m0; acc[0][it][1] += v.y * m0;
+                acc[1][it][0] += v.x * m1; acc[1][it][1] += v.y * m1;
+                acc[2][it][0] += v.x * w2; acc[2][it][1] += v.y * w2;
+                acc[3][it][0] += v.x * w3; acc[3][it][1] += v.y * w3;
+                acc[4][it][0] += v.x * m4; acc[4][it][1] += v.y * m4;
+                if (es) {
+                    T vx = v.x;
+                    if (kzero[it] && !a.diff) vx -= T((double)c.N * c.rho_b[jsp]);
+#pragma unroll
+                    for (int i = 0; i < MAXS; ++i) {
+                        if (i < S) {
+                            const int ij = i * DFT_MAX_SPECIES + jsp;
+                            const T C = screening_hat<T>(kmag[it], T(c.sc_R[ij]), T(c.sc_c1[ij]), T(c.sc_c0[ij]),
+                                                         T(c.sc_cm1[ij]));
+                            const T P = invD[it] * T(c.z[i] * c.z[jsp]);
+                            esa[i][it][0] += C * vx - P * v.x;
+                            esa[i][it][1] += (C - P) * v.y;
+                        }
+                    }
+                }
             }
         }
         __syncthreads();
     }
+    if (es) {
+#pragma unroll
+        for (int i = 0; i < MAXS; ++i) {
+            if (i >= S) break;
+            cx<T> *dst = reinterpret_cast<cx<T> *>(a.specA) + (long long)i * g.NC + off;
+#pragma unroll
+            for (int it = 0; it < MAXE; ++it) {
+                const int j = threadIdx.x + it * NT;
+                if (j < Wact * L) {
+                    const int e = j / Wact, p = j - e * Wact;
+                    dst[(long long)e * rs + p] = mk<T>(esa[i][it][0], esa[i][it][1]);
+                }
+            }
+        }
+    }
     const int nout = a.n3only ? 1 : DFT_NALPHA;
+    const T invN = T(c.invN);
     for (int o = 0; o < nout; ++o) {
         const int alpha = a.n3only ? 3 : o;
 #pragma unroll
@@ -287,22 +364,22 @@ __global__ __launch_bounds__(NT) void k_z1(Geo g, Z1Args a, int W) {
             if (j < Wact * L) {
                 const int e = j / Wact, p = j - e * Wact;
                 // select the source sum with compile-time register indices
-                double sx = 0.0, sy = 0.0;
+                T sx = T(0), sy = T(0);
 #pragma unroll
                 for (int m = 0; m < 5; ++m) {
                     const bool pick = (alpha < 4) ? (m == alpha) : (m == (alpha < 7 ? 4 : 3));
                     if (pick) { sx = acc[m][it][0]; sy = acc[m][it][1]; }
                 }
-                double re = sx, im = sy;
+                T re = sx, im = sy;
                 if (alpha >= 4) {
                     const int d = (alpha - 4) % 3;
                     const KInfo q = kinfo(c, kx0 + p, y, e);
-                    const double kd = k_comp(q, d);
+                    const T kd = T(k_comp(q, d));
                     // -i k_d s
                     re = kd * sy;
                     im = -kd * sx;
                 }
-                tile[j] = mk<T>(T(re * c.invN), T(im * c.invN));
+                tile[j] = mk<T>(re * invN, im * invN);
             }
         }
         __syncthreads();
@@ -312,16 +389,21 @@ __global__ __launch_bounds__(NT) void k_z1(Geo g, Z1Args a, int W) {
     }
 }
 
-template <typename T, int MAXE, int MAXS>
+// Z2: forward z transform of the ten dPhi/dn spectra, back-convolution with conj(w_hat)
+// (eq. muHS; the vector parts enter as +i k_d times a w3 weight), plus the electrostatic
+// spectra Z1 left in specA, times 1/N, inverse z -> specA.  Z2_POISSON instead forms the
+// potential of weighted source spectra.
+template <typename T, int MAXE>
 __global__ __launch_bounds__(NT) void k_z2(Geo g, Z2Args a, int W) {
     if (gated_off(a.gate)) return;
     extern __shared__ unsigned char smem_raw[];
     cx<T> *tile = reinterpret_cast<cx<T> *>(smem_raw);
     const Consts &c = *g.cs;
     const int L = g.nz, Kx = g.Kx;
-    const int kx0 = blockIdx.x * W;
+    int bx, y;
+    xcd_block(bx, y);
+    const int kx0 = bx * W;
     const int Wact = min(W, Kx - kx0);
-    const int y = blockIdx.y;
     const long long rs = (long long)g.ny * Kx;
     const long long off = (long long)y * Kx + kx0;
     const cx<T> *tw = twp<T>(g, 2);
@@ -354,7 +436,7 @@ __global__ __launch_bounds__(NT) void k_z2(Geo g, Z2Args a, int W) {
                 const int e = j / Wact, p = j - e * Wact;
                 const KInfo q = kinfo(c, kx0 + p, y, e);
                 double m = 0.0;
-                if (!q.zero) m = c.four_pi_lB / poisson_denominator(q.k, c.h) * c.invN;
+                if (!q.zero) m = c.four_pi_lB / poisson_denominator<double>(q.k, c.h) * c.invN;
                 tile[j] = mk<T>(T(acc[it][0] * m), T(acc[it][1] * m));
             }
         }
@@ -365,11 +447,11 @@ __global__ __launch_bounds__(NT) void k_z2(Geo g, Z2Args a, int W) {
     }
 
     // six sums of the derivative spectra: u0..u3 and v1 = sum_d i k_d dPhi_V1,d, v2 likewise
-    double u[6][MAXE][2];
+    T u[6][MAXE][2];
 #pragma unroll
     for (int m = 0; m < 6; ++m)
 #pragma unroll
-        for (int it = 0; it < MAXE; ++it) u[m][it][0] = u[m][it][1] = 0.0;
+        for (int it = 0; it < MAXE; ++it) u[m][it][0] = u[m][it][1] = T(0);
     for (int al = 0; al < DFT_NALPHA; ++al) {
         const cx<T> *src = reinterpret_cast<const cx<T> *>(a.specB) + (long long)al * g.NC + off;
         z_load(tile, src, Wact, L, rs);
@@ -379,14 +461,14 @@ __global__ __launch_bounds__(NT) void k_z2(Geo g, Z2Args a, int W) {
         for (int it = 0; it < MAXE; ++it) {
             const int j = threadIdx.x + it * NT;
             if (j < Wact * L) {
-                double vx = (double)tile[j].x, vy = (double)tile[j].y;
+                T vx = tile[j].x, vy = tile[j].y;
                 if (al >= 4) {
                     const int e = j / Wact, p = j - e * Wact;
                     const int d = (al - 4) % 3;
                     const KInfo q = kinfo(c, kx0 + p, y, e);
-                    const double kd = k_comp(q, d);
+                    const T kd = T(k_comp(q, d));
                     // + i k_d v
-                    const double tx = -kd * vy;
+                    const T tx = -kd * vy;
                     vy = kd * vx;
                     vx = tx;
                 }
@@ -398,61 +480,30 @@ __global__ __launch_bounds__(NT) void k_z2(Geo g, Z2Args a, int W) {
         }
         __syncthreads();
     }
-    // rho_hat of every species for the owned elements
-    double rh[MAXS][MAXE][2];
-#pragma unroll
-    for (int it = 0; it < MAXE; ++it) {
-        const int j = threadIdx.x + it * NT;
-        const int e = j / max(Wact, 1), p = j - e * Wact;
-#pragma unroll
-        for (int s = 0; s < MAXS; ++s) {
-            rh[s][it][0] = rh[s][it][1] = 0.0;
-            if (s < S && j < Wact * L) {
-                const cx<T> v = reinterpret_cast<const cx<T> *>(a.specA)[(long long)s * g.NC + off + (long long)e * rs + p];
-                rh[s][it][0] = (double)v.x;
-                rh[s][it][1] = (double)v.y;
-            }
-        }
-    }
-    __syncthreads();
+    const T invN = T(c.invN);
     for (int i = 0; i < S; ++i) {
-        const double R = c.R[i], a0 = c.i4piR2[i], a1 = c.i4piR[i];
+        const T Ri = T(c.R[i]), a0 = T(c.i4piR2[i]), a1 = T(c.i4piR[i]);
+        const cx<T> *esrc = reinterpret_cast<const cx<T> *>(a.specA) + (long long)i * g.NC + off;
 #pragma unroll
         for (int it = 0; it < MAXE; ++it) {
             const int j = threadIdx.x + it * NT;
             if (j < Wact * L) {
                 const int e = j / Wact, p = j - e * Wact;
                 const KInfo q = kinfo(c, kx0 + p, y, e);
-                double w2, w3;
-                weight_w2_w3(q.kmag, R, w2, w3);
-                const double s2x = u[0][it][0] * a0 + u[1][it][0] * a1 + u[2][it][0];
-                const double s2y = u[0][it][1] * a0 + u[1][it][1] * a1 + u[2][it][1];
-                const double s3x = u[3][it][0] + u[4][it][0] * a1 + u[5][it][0];
-                const double s3y = u[3][it][1] + u[4][it][1] * a1 + u[5][it][1];
-                double ex = -(s2x * w2 + s3x * w3);
-                double ey = -(s2y * w2 + s3y * w3);
+                T w2, w3;
+                weight_w2_w3<T>(T(q.kmag), Ri, w2, w3);
+                const T s2x = u[0][it][0] * a0 + u[1][it][0] * a1 + u[2][it][0];
+                const T s2y = u[0][it][1] * a0 + u[1][it][1] * a1 + u[2][it][1];
+                const T s3x = u[3][it][0] + u[4][it][0] * a1 + u[5][it][0];
+                const T s3y = u[3][it][1] + u[4][it][1] * a1 + u[5][it][1];
+                T ex = -(s2x * w2 + s3x * w3);
+                T ey = -(s2y * w2 + s3y * w3);
                 if (c.es) {
-                    double qx = 0.0, qy = 0.0;
-#pragma unroll
-                    for (int s = 0; s < MAXS; ++s) {
-                        if (s < S) {
-                            const int ij = i * DFT_MAX_SPECIES + s;
-                            const double C = screening_hat(q.kmag, c.sc_R[ij], c.sc_c1[ij], c.sc_c0[ij], c.sc_cm1[ij]);
-                            double rx = rh[s][it][0];
-                            if (q.zero && !a.diff) rx -= (double)c.N * c.rho_b[s];
-                            ex += C * rx;
-                            ey += C * rh[s][it][1];
-                            qx += c.z[s] * rh[s][it][0];
-                            qy += c.z[s] * rh[s][it][1];
-                        }
-                    }
-                    if (!q.zero) {
-                        const double m = c.four_pi_lB / poisson_denominator(q.k, c.h) * c.z[i];
-                        ex -= m * qx;
-                        ey -= m * qy;
-                    }
+                    const cx<T> ev = esrc[(long long)e * rs + p];
+                    ex += ev.x;
+                    ey += ev.y;
                 }
-                tile[j] = mk<T>(T(ex * c.invN), T(ey * c.invN));
+                tile[j] = mk<T>(ex * invN, ey * invN);
             }
         }
         __syncthreads();
@@ -571,6 +622,113 @@ __global__ __launch_bounds__(NT) void k_x2(Geo g, X2Args a, int P) {
     }
 }
 
+// Batched variant: all ten fields of PB row pairs sit in LDS as 10*PB pencils, so each
+// direction is one FFT over the batch (one barrier pair per stage for all fields) and
+// the pointwise work reads and writes LDS instead of holding the fields in registers.
+template <typename T, int NTB, int MAXE>
+__global__ __launch_bounds__(NTB) void k_x2b(Geo g, X2Args a, int PB) {
+    if (gated_off(a.gate)) return;
+    extern __shared__ unsigned char smem_raw[];
+    cx<T> *tile = reinterpret_cast<cx<T> *>(smem_raw);
+    const int L = g.nx, Kx = g.Kx;
+    const long long rows = (long long)g.ny * g.nz;
+    const long long npairs = (rows + 1) / 2;
+    const long long pair0 = (long long)blockIdx.x * PB;
+    const int Pact = (int)min((long long)PB, npairs - pair0);
+    const cx<T> *tw = twp<T>(g, 0);
+    const bool n3only = a.mode == X2_N3_ONLY;
+    const int nf = n3only ? 1 : DFT_NALPHA;
+    const int span = Pact * L;          // elements of one field in the tile
+    const int P = nf * Pact;            // pencils in the batch
+    for (int j = threadIdx.x; j < P * L; j += NTB) {
+        const int f = j / span;
+        const int jj = j - f * span;
+        const int pl = jj / L, e = jj - pl * L;
+        const long long r0 = 2 * (pair0 + pl);
+        const cx<T> *in = reinterpret_cast<const cx<T> *>(a.specB) + (long long)f * g.NC;
+        const cx<T> A = x_half_at(in + r0 * Kx, e, L, Kx);
+        cx<T> B = mk<T>(T(0), T(0));
+        if (r0 + 1 < rows) B = x_half_at(in + (r0 + 1) * Kx, e, L, Kx);
+        tile[j] = mk<T>(A.x - B.y, A.y + B.x);
+    }
+    __syncthreads();
+    fft_tile<T, 1, NTB, MAXE>(tile, g.px, P, 1, L, true, tw);
+    double mloc = -INFINITY;
+    int flag = 0;
+    for (int jj = threadIdx.x; jj < span; jj += NTB) {
+        const int pl = jj / L, e = jj - pl * L;
+        const long long r0 = 2 * (pair0 + pl);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const long long r = r0 + h;
+            if (r >= rows) break;
+            const long long idx = r * L + e;
+            if (n3only) {
+                double n3 = h == 0 ? (double)tile[jj].x : (double)tile[jj].y;
+                if (a.nref) n3 += (double)a.nref[3 * g.N + idx];
+                if (!isfinite(n3)) flag |= 1;
+                mloc = fmax(mloc, n3);
+                continue;
+            }
+            double n[DFT_NALPHA], d[DFT_NALPHA];
+#pragma unroll
+            for (int f = 0; f < DFT_NALPHA; ++f) {
+                const cx<T> v = tile[f * span + jj];
+                n[f] = h == 0 ? (double)v.x : (double)v.y;
+            }
+            bool clamped = false;
+            if (a.nref) {
+                double nr[DFT_NALPHA], dr[DFT_NALPHA];
+#pragma unroll
+                for (int f = 0; f < DFT_NALPHA; ++f) {
+                    nr[f] = (double)a.nref[f * g.N + idx];
+                    n[f] += nr[f];
+                }
+                bool c2;
+                fmt_dphi<double>(n, d, clamped);
+                fmt_dphi<double>(nr, dr, c2);
+#pragma unroll
+                for (int f = 0; f < DFT_NALPHA; ++f) d[f] -= dr[f];
+            } else {
+                fmt_dphi<double>(n, d, clamped);
+            }
+            if (clamped) flag |= 2;
+            if (!isfinite(n[3]) || !isfinite(d[0]) || !isfinite(d[3])) flag |= 1;
+            mloc = fmax(mloc, n[3]);
+#pragma unroll
+            for (int f = 0; f < DFT_NALPHA; ++f) {
+                if (a.nref_out) a.nref_out[f * g.N + idx] = (float)n[f];
+                if (a.n_out) a.n_out[f * g.N + idx] = n[f];
+                if (a.dphi_out) a.dphi_out[f * g.N + idx] = d[f];
+                if (h == 0) tile[f * span + jj].x = T(d[f]);
+                else tile[f * span + jj].y = T(d[f]);
+            }
+        }
+        if (!n3only && r0 + 1 >= rows) {
+            // the missing partner row transforms as zero
+#pragma unroll
+            for (int f = 0; f < DFT_NALPHA; ++f) tile[f * span + jj].y = T(0);
+        }
+    }
+    if (flag & 1) mloc = INFINITY;
+    block_reduce_nt<true, NTB>(mloc, flag, a.red.mpart + blockIdx.x, a.red.mflag + blockIdx.x);
+    if (n3only) return;
+    __syncthreads();
+    fft_tile<T, -1, NTB, MAXE>(tile, g.px, P, 1, L, true, tw);
+    for (int j = threadIdx.x; j < nf * Pact * Kx; j += NTB) {
+        const int f = j / (Pact * Kx);
+        const int jj = j - f * (Pact * Kx);
+        const int pl = jj / Kx, k = jj - pl * Kx;
+        const cx<T> *tf = tile + f * span;
+        const cx<T> ck = tf[pl * L + k];
+        const cx<T> cm = tf[pl * L + (k == 0 ? 0 : L - k)];
+        const long long r0 = 2 * (pair0 + pl);
+        cx<T> *out = reinterpret_cast<cx<T> *>(a.specB) + (long long)f * g.NC;
+        out[r0 * Kx + k] = mk<T>(T(0.5) * (ck.x + cm.x), T(0.5) * (ck.y - cm.y));
+        if (r0 + 1 < rows) out[(r0 + 1) * Kx + k] = mk<T>(T(0.5) * (ck.y + cm.y), T(-0.5) * (ck.x - cm.x));
+    }
+}
+
 // --------------------------------------------------------------------- X3: Euler-Lagrange update
 template <typename T, int MAXE>
 __global__ __launch_bounds__(NT) void k_x3(Geo g, X3Args a, int P) {
@@ -678,7 +836,10 @@ void launch_z1(const Geo &g, const Z1Args &a, hipStream_t s) {
     const int W = yz_width<T, E>(g.nz, g.Kx);
     dim3 grid((unsigned)ceil_div(g.Kx, W), (unsigned)g.ny);
     const size_t sh = (size_t)W * g.nz * sizeof(cx<T>);
-    hipLaunchKernelGGL((k_z1<T, E>), grid, dim3(NT), sh, s, g, a, W);
+    if (g.S <= 4)
+        hipLaunchKernelGGL((k_z1<T, E, 4>), grid, dim3(NT), sh, s, g, a, W);
+    else
+        hipLaunchKernelGGL((k_z1<T, E, DFT_MAX_SPECIES>), grid, dim3(NT), sh, s, g, a, W);
     check_launch("z1");
 }
 
@@ -688,16 +849,8 @@ void launch_z2(const Geo &g, const Z2Args &a, hipStream_t s) {
     const int W = yz_width<T, E>(g.nz, g.Kx);
     dim3 grid((unsigned)ceil_div(g.Kx, W), (unsigned)g.ny);
     const size_t sh = (size_t)W * g.nz * sizeof(cx<T>);
-    if (g.S <= 4)
-        hipLaunchKernelGGL((k_z2<T, E, 4>), grid, dim3(NT), sh, s, g, a, W);
-    else
-        hipLaunchKernelGGL((k_z2<T, E, DFT_MAX_SPECIES>), grid, dim3(NT), sh, s, g, a, W);
+    hipLaunchKernelGGL((k_z2<T, E>), grid, dim3(NT), sh, s, g, a, W);
     check_launch("z2");
-}
-
-int x2_blocks(const Geo &g) {
-    const int P = (NT * 4) / g.nx > 0 ? std::min<long long>((NT * 4) / g.nx, ((long long)g.ny * g.nz + 1) / 2) : 1;
-    return (int)ceil_div(((long long)g.ny * g.nz + 1) / 2, P);
 }
 
 int x3_blocks(const Geo &g) {
@@ -709,17 +862,62 @@ int x3_blocks(const Geo &g) {
     return (int)ceil_div(npairs, P) * g.S;
 }
 
+// Batched x_fmt geometry: NTB threads, PB row pairs per block (10 PB nx <= NTB * 12),
+// LDS of at most 64 KiB.  Returns false when the row is too long for it.
+constexpr int kX2bE = 12;
+
+template <typename T>
+static bool x2b_geometry(const Geo &g, int *ntb, int *pb) {
+    const long long npairs = ((long long)g.ny * g.nz + 1) / 2;
+    for (int nt : {256, 512}) {
+        int P = (nt * kX2bE) / (DFT_NALPHA * g.nx);
+        if (P < 1) continue;
+        if (P > npairs) P = (int)npairs;
+        if ((size_t)DFT_NALPHA * P * g.nx * sizeof(cx<T>) > 65536) continue;
+        *ntb = nt;
+        *pb = P;
+        return true;
+    }
+    return false;
+}
+
+template <typename T>
+int x2_nblocks(const Geo &g) {
+    const long long npairs = ((long long)g.ny * g.nz + 1) / 2;
+    int ntb, pb;
+    if (x2b_geometry<T>(g, &ntb, &pb)) return (int)ceil_div(npairs, pb);
+    const int P = x_pairs<T, Cfg<T>::X2E>(g);
+    return (int)ceil_div(npairs, P);
+}
+
 template <typename T>
 void launch_x2(const Geo &g, const X2Args &a, hipStream_t s) {
+    const long long npairs = ((long long)g.ny * g.nz + 1) / 2;
+    int ntb, pb;
+    if (x2b_geometry<T>(g, &ntb, &pb)) {
+        const long long nb = ceil_div(npairs, pb);
+        if (nb > a.red.cap) throw std::runtime_error("x2: reduction buffer too small");
+        const size_t sh = (size_t)DFT_NALPHA * pb * g.nx * sizeof(cx<T>);
+        if (ntb == 256)
+            hipLaunchKernelGGL((k_x2b<T, 256, kX2bE>), dim3((unsigned)nb), dim3(256), sh, s, g, a, pb);
+        else
+            hipLaunchKernelGGL((k_x2b<T, 512, kX2bE>), dim3((unsigned)nb), dim3(512), sh, s, g, a, pb);
+        check_launch("x2b");
+        return;
+    }
     constexpr int E = Cfg<T>::X2E;
     const int P = x_pairs<T, E>(g);
-    const long long npairs = ((long long)g.ny * g.nz + 1) / 2;
     const long long nb = ceil_div(npairs, P);
     if (nb > a.red.cap) throw std::runtime_error("x2: reduction buffer too small");
     const size_t sh = (size_t)P * g.nx * sizeof(cx<T>);
     hipLaunchKernelGGL((k_x2<T, E>), dim3((unsigned)nb), dim3(NT), sh, s, g, a, P);
     check_launch("x2");
 }
+
+template int x2_nblocks<double>(const Geo &);
+template int x2_nblocks<float>(const Geo &);
+
+int x2_blocks(const Geo &g) { return std::max(x2_nblocks<double>(g), x2_nblocks<float>(g)); }
 
 template <typename T>
 void launch_x3(const Geo &g, const X3Args &a, hipStream_t s) {
