@@ -219,6 +219,35 @@ dft_status dft_run(dft_ctx *ctx, double *rho_inout, int32_t nsteps, int32_t *ite
  */
 dft_status dft_profile(dft_ctx *ctx, const double *rho, int32_t reps, double *ms_out);
 
+/*
+ * Bytes of device workspace dft_adjoint needs for these parameters.  Host only.
+ */
+dft_status dft_adjoint_workspace_size(const dft_params *params, size_t *bytes);
+
+/*
+ * Gradient of an observable O(rho*) through the converged fixed point rho* = G(rho*)
+ * (eq. rhoEquation) by the implicit adjoint: with J = dG/drho = diag(G) H and H = dE/drho
+ * symmetric, the adjoint weights w = G o lambda solve (diag(G)^-1 - H) w = dO/drho on
+ * fluid nodes, by conjugate gradients preconditioned with diag(G) (a Krylov-accelerated
+ * adjoint Picard iteration w <- G o (dO/drho + H w)).  Each iteration applies H through the
+ * residual passes in FP64 with the exact Hessian of eq. (Phi).  Then
+ *   dO/d(beta V_k(x)) = -w_k(x),
+ *   dO/d rho_bulk_k, dO/d sigma_k = sum_i <w_i, d ln G_i / d theta>, including the bath terms
+ *   of Appendix A (beta mu^HS, Gamma) and the screening kernel's dependence on R and Gamma;
+ *   hard-core exclusion masks are held fixed.
+ *   rho_star      device [S][N]: a converged solution (e.g. from dft_solve).
+ *   dO_drho       device [S][N]: the observable's derivative.
+ *   adj_ws        device workspace of dft_adjoint_workspace_size bytes, 256-byte aligned.
+ *   tol           relative residual of the adjoint system; max_iter its iteration limit.
+ *   dO_dvext      device [S][N] out (NULL to skip); dO_drho_bulk, dO_dsigma: host [S] out (NULL to skip).
+ *   iters_out, resid_out: host, may be NULL.  Synchronizes the stream.
+ * Supports up to 4 species and n_x <= 384.  Errors: DFT_E_NOT_CONVERGED, DFT_E_NONFINITE
+ * (the system is not positive definite at rho*: rho* is not a stable solution).
+ */
+dft_status dft_adjoint(dft_ctx *ctx, const double *rho_star, const double *dO_drho, void *adj_ws, size_t adj_ws_bytes,
+                       double tol, int32_t max_iter, double *dO_dvext, double *dO_drho_bulk, double *dO_dsigma,
+                       int32_t *iters_out, double *resid_out);
+
 /* Counters of the ctx (host out). */
 dft_status dft_get_stats(dft_ctx *ctx, dft_stats *out);
 

@@ -64,6 +64,9 @@ SIGNATURES = [
     ("dft_solve", [_vp, _vp, ctypes.c_double, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), _dp]),
     ("dft_run", [_vp, _vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), _dp]),
     ("dft_profile", [_vp, _vp, ctypes.c_int32, _dp]),
+    ("dft_adjoint_workspace_size", [ctypes.POINTER(Params), ctypes.POINTER(ctypes.c_size_t)]),
+    ("dft_adjoint", [_vp, _vp, _vp, _vp, ctypes.c_size_t, ctypes.c_double, ctypes.c_int32, _vp, _dp, _dp,
+                     ctypes.POINTER(ctypes.c_int32), _dp]),
     ("dft_get_stats", [_vp, ctypes.POINTER(Stats)]),
     ("dft_destroy", [_vp]),
 ]

@@ -11,6 +11,7 @@
 #include <string>
 #include <vector>
 
+#include "dft_adjoint.h"
 #include "dft_host.h"
 #include "dft_kernels.h"
 
@@ -796,6 +797,266 @@ dft_status dft_profile(dft_ctx *ctx, const double *rho, int32_t reps, double *ms
         for (auto &e : ev) HIPCHK(hipEventDestroy(e));
         for (int k = 0; k < DFT_NPASS; ++k) ms_out[k] = acc[k] / reps;
         ctx->step_rho = nullptr;
+        return DFT_OK;
+    });
+}
+
+// ------------------------------------------------------------------ implicit adjoint
+namespace {
+
+struct AdjLayout {
+    size_t nstar, dphi, G, w, r, p, q, Hp, t, wh, rh, dh, th, part, scal, ac, total;
+    int nparts;
+};
+
+AdjLayout adj_layout(const dft_params *p) {
+    AdjLayout L;
+    const long long N = (long long)p->n[0] * p->n[1] * p->n[2];
+    const long long NC = (long long)(p->n[0] / 2 + 1) * p->n[1] * p->n[2];
+    const int S = p->nspecies;
+    size_t off = 0;
+    auto take = [&](size_t b) { size_t o = off; off = align_up(off + b); return o; };
+    const size_t RF = sizeof(double) * (size_t)N, CF = 2 * sizeof(double) * (size_t)NC;
+    L.nstar = take(DFT_NALPHA * RF);
+    L.dphi = take(DFT_NALPHA * RF);
+    L.G = take(S * RF);
+    L.w = take(S * RF);
+    L.r = take(S * RF);
+    L.p = take(S * RF);
+    L.q = take(S * RF);
+    L.Hp = take(S * RF);
+    L.t = take(DFT_NALPHA * RF);
+    L.wh = take(S * CF);
+    L.rh = take(S * CF);
+    L.dh = take(DFT_NALPHA * CF);
+    L.th = take(DFT_NALPHA * CF);
+    L.nparts = 2048 * DFT_MAX_SPECIES;
+    L.part = take(sizeof(double) * (size_t)L.nparts * kAdjNV);
+    L.scal = take(sizeof(double) * 64);
+    L.ac = take(sizeof(AdjConsts));
+    L.total = off;
+    return L;
+}
+
+// H u = dE/drho . u at the expansion point whose weighted densities are nstar: the residual
+// passes in FP64 with the Hessian-vector FMT kernel and no bath subtraction.
+void enqueue_hess(dft_ctx *c, const double *u, double *hu, const double *nstar, double *t_out, hipStream_t s) {
+    const Geo &g = c->geo;
+    XFwdArgs xa{};
+    xa.src = u;
+    xa.spec = c->specA;
+    xa.nfield = g.S;
+    xa.mode = XF_PLAIN;
+    launch_x_forward<double>(g, xa, s);
+    YArgs ya{c->specA, g.S, -1, nullptr};
+    launch_y<double>(g, ya, s);
+    Z1Args z1{c->specA, c->specB, 0, 1, nullptr};
+    launch_z1<double>(g, z1, s);
+    YArgs yb{c->specB, DFT_NALPHA, 1, nullptr};
+    launch_y<double>(g, yb, s);
+    X2Args x2{};
+    x2.specB = c->specB;
+    x2.mode = X2_HESS;
+    x2.nstar = nstar;
+    x2.t_out = t_out;
+    x2.red = c->red;
+    launch_x2<double>(g, x2, s);
+    YArgs yc{c->specB, DFT_NALPHA, -1, nullptr};
+    launch_y<double>(g, yc, s);
+    Z2Args z2{};
+    z2.specB = c->specB;
+    z2.specA = c->specA;
+    z2.mode = Z2_EL;
+    launch_z2<double>(g, z2, s);
+    YArgs yd{c->specA, g.S, 1, nullptr};
+    launch_y<double>(g, yd, s);
+    X3Args x3{};
+    x3.specA = c->specA;
+    x3.nfield = g.S;
+    x3.raw = 1;
+    x3.raw_out = hu;
+    launch_x3<double>(g, x3, s);
+}
+
+// Forward 3-D transform (FP64) of nfield contiguous real fields into half spectra.
+void forward3d(dft_ctx *c, const double *src, int nfield, void *dst, hipStream_t s) {
+    const Geo &g = c->geo;
+    XFwdArgs xa{};
+    xa.src = src;
+    xa.spec = dst;
+    xa.nfield = nfield;
+    xa.mode = XF_PLAIN;
+    launch_x_forward<double>(g, xa, s);
+    YArgs ya{dst, nfield, -1, nullptr};
+    launch_y<double>(g, ya, s);
+    YArgs za{dst, nfield, -1, nullptr, 2};
+    launch_y<double>(g, za, s);
+}
+
+std::vector<double> read_scalars(dft_ctx *c, const double *dev, int n) {
+    std::vector<double> h(n);
+    HIPCHK(hipMemcpyAsync(h.data(), dev, sizeof(double) * n, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return h;
+}
+
+}  // namespace
+
+dft_status dft_adjoint_workspace_size(const dft_params *params, size_t *bytes) {
+    std::string msg;
+    dft_status st = validate(params, &msg);
+    if (st != DFT_OK) return fail(st, msg);
+    if (!bytes) return fail(DFT_E_INVALID_ARG, "bytes is NULL");
+    *bytes = adj_layout(params).total;
+    return DFT_OK;
+}
+
+dft_status dft_adjoint(dft_ctx *ctx, const double *rho_star, const double *dO_drho, void *adj_ws, size_t adj_ws_bytes,
+                       double tol, int32_t max_iter, double *dO_dvext, double *dO_drho_bulk, double *dO_dsigma,
+                       int32_t *iters_out, double *resid_out) {
+    if (!ctx || !rho_star || !dO_drho) return fail(DFT_E_INVALID_ARG, "ctx, rho_star or dO_drho is NULL");
+    if (!(tol > 0.0) || max_iter < 1) return fail(DFT_E_INVALID_ARG, "tol must be > 0 and max_iter >= 1");
+    const AdjLayout L = adj_layout(&ctx->p);
+    if (!adj_ws || adj_ws_bytes < L.total || ((uintptr_t)adj_ws) % 256 != 0)
+        return fail(DFT_E_WORKSPACE, "adjoint workspace missing, misaligned or smaller than dft_adjoint_workspace_size");
+    if (ctx->geo.S > 4) return fail(DFT_E_UNSUPPORTED_SIZE, "adjoint gradients support at most 4 species");
+    if ((size_t)DFT_NALPHA * ctx->geo.nx * 16 > 65536)
+        return fail(DFT_E_UNSUPPORTED_SIZE, "adjoint needs n_x <= 384 (FP64 Hessian pass)");
+    return guarded([&]() -> dft_status {
+        dft_ctx *c = ctx;
+        const Geo &g = c->geo;
+        const int S = g.S;
+        const long long N = g.N, SN = (long long)S * N;
+        hipStream_t s = c->stream;
+        char *w8 = (char *)adj_ws;
+        double *nstar = (double *)(w8 + L.nstar), *dphi = (double *)(w8 + L.dphi), *G = (double *)(w8 + L.G);
+        double *w = (double *)(w8 + L.w), *r = (double *)(w8 + L.r), *p = (double *)(w8 + L.p);
+        double *q = (double *)(w8 + L.q), *Hp = (double *)(w8 + L.Hp), *t = (double *)(w8 + L.t);
+        double *part = (double *)(w8 + L.part), *scal = (double *)(w8 + L.scal);
+        AdjConsts *acd = (AdjConsts *)(w8 + L.ac);
+        // FP64 evaluation at rho*: G*, n*, dPhi(n*)
+        Eval e;
+        e.src = rho_star;
+        e.g_out = G;
+        e.n_out = nstar;
+        e.dphi_out = dphi;
+        e.fslot = &c->st->best_f;
+        e.fp64 = true;
+        e.count_kind = 0;
+        enqueue_eval(c, e, s);
+        // ||g|| on fluid nodes via the (r, r) partial of r0 with Hw := g
+        int nb = adj_r0(SN, G, dO_drho, r, p, part, s);
+        adj_reduce(part, nb, 2, scal, s);
+        const double gnorm = std::sqrt(read_scalars(c, scal, 2)[1]);
+        if (!(gnorm > 0.0)) return fail(DFT_E_INVALID_ARG, "dO_drho vanishes on every fluid node");
+        // w0 = G o g, r0 = g - (w0/G - H w0) = H w0, p0 = G o r0
+        adj_init(SN, G, dO_drho, w, s);
+        enqueue_hess(c, w, Hp, nstar, nullptr, s);
+        nb = adj_r0(SN, G, Hp, r, p, part, s);
+        adj_reduce(part, nb, 2, scal, s);
+        std::vector<double> sc = read_scalars(c, scal, 2);
+        double rz = sc[0], rr = sc[1];
+        int it = 0;
+        double rel = std::sqrt(rr) / gnorm;
+        while (rel > tol && it < max_iter) {
+            enqueue_hess(c, p, Hp, nstar, nullptr, s);
+            nb = adj_q(SN, G, p, Hp, q, part, s);
+            adj_reduce(part, nb, 1, scal, s);
+            const double pq = read_scalars(c, scal, 1)[0];
+            if (!(pq > 0.0)) return fail(DFT_E_NONFINITE, "adjoint system is not positive definite at rho*");
+            const double alpha = rz / pq;
+            nb = adj_step(SN, alpha, G, p, q, w, r, part, s);
+            adj_reduce(part, nb, 2, scal, s);
+            sc = read_scalars(c, scal, 2);
+            const double rz_new = sc[0];
+            rr = sc[1];
+            adj_dir(SN, rz_new / rz, G, r, p, s);
+            rz = rz_new;
+            rel = std::sqrt(rr) / gnorm;
+            ++it;
+            if (!std::isfinite(rel)) return fail(DFT_E_NONFINITE, "non-finite adjoint residual");
+        }
+        if (iters_out) *iters_out = it;
+        if (resid_out) *resid_out = rel;
+        if (rel > tol) return fail(DFT_E_NOT_CONVERGED, "adjoint solve reached max_iter");
+        if (dO_dvext) adj_neg(SN, w, dO_dvext, s);
+        if (!dO_drho_bulk && !dO_dsigma) {
+            HIPCHK(hipStreamSynchronize(s));
+            return DFT_OK;
+        }
+        // t = Phi''(n*) (A w) for the final w
+        enqueue_hess(c, w, Hp, nstar, t, s);
+        // W_i = sum_x w_i
+        nb = adj_fieldsum(N, S, w, part, s);
+        std::vector<double> Wsum(S, 0.0);
+        for (int i = 0; i < S; ++i) {
+            adj_reduce(part + (long long)i * nb, nb, 1, scal + i, s);
+        }
+        sc = read_scalars(c, scal, S);
+        for (int i = 0; i < S; ++i) Wsum[i] = sc[i];
+        // spectra of w, rho*, dPhi(n*) and t
+        forward3d(c, w, S, w8 + L.wh, s);
+        forward3d(c, rho_star, S, w8 + L.rh, s);
+        forward3d(c, dphi, DFT_NALPHA, w8 + L.dh, s);
+        forward3d(c, t, DFT_NALPHA, w8 + L.th, s);
+        // kernel-coefficient derivatives with respect to lambda_i, lambda_j
+        const dft_bulk_info &b = c->bulk;
+        AdjConsts ac;
+        std::memset(&ac, 0, sizeof ac);
+        for (int i = 0; i < S; ++i)
+            for (int j = 0; j < S; ++j) {
+                const int ij = i * DFT_MAX_SPECIES + j;
+                if (!c->p.electrostatics) continue;
+                const double li = b.lambda[i], lj = b.lambda[j];
+                const double pre = 0.5 * c->p.valence[i] * c->p.valence[j] * c->p.bjerrum_length;
+                ac.li_c1[ij] = -pre / (2.0 * li * li * lj);
+                ac.lj_c1[ij] = -pre / (2.0 * li * lj * lj);
+                ac.li_c0[ij] = pre / (li * li);
+                ac.lj_c0[ij] = pre / (lj * lj);
+                ac.li_cm1[ij] = 0.5 * pre * (1.0 / lj - lj / (li * li));
+                ac.lj_cm1[ij] = 0.5 * pre * (1.0 / li - li / (lj * lj));
+            }
+        HIPCHK(hipMemcpyAsync(acd, &ac, sizeof ac, hipMemcpyHostToDevice, s));
+        AdjSpecArgs sa{w8 + L.wh, w8 + L.rh, w8 + L.dh, w8 + L.th, acd, part};
+        nb = adj_spec(g, sa, s);
+        adj_reduce(part, nb, kAdjNV, scal, s);
+        sc = read_scalars(c, scal, kAdjNV);
+        const double invN = 1.0 / (double)N;
+        BulkDeriv bd;
+        bulk_derivatives(&c->p, b, &bd);
+        auto B = [&](int i, int j, int m) { return sc[4 + 3 * (i * 4 + j) + m] * invN; };
+        double Bgam = 0.0;   // sum_ij <w_i, dC_ij/dGamma * drho_j>
+        if (c->p.electrostatics) {
+            const double G2 = b.gamma * b.gamma;
+            const double dRc = (c->p.flags & DFT_FLAG_CUTOFF_LAMBDA) ? -1.0 / G2 : 0.0;
+            for (int i = 0; i < S; ++i)
+                for (int j = 0; j < S; ++j) Bgam += -(B(i, j, 0) + B(i, j, 1)) / (2.0 * G2) + B(i, j, 2) * dRc;
+        }
+        for (int k = 0; k < S; ++k) {
+            double dr = Wsum[k] / c->p.rho_bulk[k];
+            double dR = 0.0;
+            for (int i = 0; i < S; ++i) {
+                dr += Wsum[i] * bd.dmu_drho[i][k];
+                dR += Wsum[i] * 2.0 * bd.dmu_dsigma[i][k];
+            }
+            dR -= sc[k] * invN;
+            if (c->p.electrostatics) {
+                for (int i = 0; i < S; ++i) {
+                    const int ik = i * DFT_MAX_SPECIES + k;
+                    const double Rc = c->hc.sc_R[ik];
+                    const double C0 = c->hc.sc_c1[ik] * M_PI * Rc * Rc * Rc * Rc +
+                                      c->hc.sc_c0[ik] * 4.0 * M_PI * Rc * Rc * Rc / 3.0 +
+                                      c->hc.sc_cm1[ik] * 2.0 * M_PI * Rc * Rc;
+                    dr -= Wsum[i] * C0;
+                }
+                dr += bd.dgamma_drho[k] * Bgam;
+                for (int j = 0; j < S; ++j) dR += B(k, j, 0) + B(k, j, 2);
+                for (int i = 0; i < S; ++i) dR += B(i, k, 1) + B(i, k, 2);
+                dR += 2.0 * bd.dgamma_dsigma[k] * Bgam;
+            }
+            if (dO_drho_bulk) dO_drho_bulk[k] = dr;
+            if (dO_dsigma) dO_dsigma[k] = 0.5 * dR;
+        }
         return DFT_OK;
     });
 }

@@ -283,6 +283,61 @@ __device__ __forceinline__ R poisson_denominator(const R kd[3], const double h[3
 // Signed mode index of position j on an axis with n nodes (eq. Kvalues).
 __device__ __forceinline__ int signed_mode(int j, int n) { return (2 * j <= n) ? j : j - n; }
 
+// Wavenumber data of one element of a z tile.
+struct KInfo {
+    double k[3];
+    double kmag;
+    bool nyq[3];
+    bool zero;
+};
+
+__device__ __forceinline__ KInfo kinfo(const Consts &c, int jx, int y, int e) {
+    KInfo q;
+    const int my = signed_mode(y, c.ny), mz = signed_mode(e, c.nz);
+    q.k[0] = jx * c.dk[0];
+    q.k[1] = my * c.dk[1];
+    q.k[2] = mz * c.dk[2];
+    q.kmag = sqrt(q.k[0] * q.k[0] + q.k[1] * q.k[1] + q.k[2] * q.k[2]);
+    q.nyq[0] = (c.nx % 2 == 0) && (2 * jx == c.nx);
+    q.nyq[1] = (c.ny % 2 == 0) && (2 * y == c.ny);
+    q.nyq[2] = (c.nz % 2 == 0) && (2 * e == c.nz);
+    q.zero = (jx == 0) && (y == 0) && (e == 0);
+    return q;
+}
+
+// Component d of k, zero on the Nyquist plane of axis d (register selects, no indexing).
+__device__ __forceinline__ double k_comp(const KInfo &q, int d) {
+    const double k = d == 0 ? q.k[0] : (d == 1 ? q.k[1] : q.k[2]);
+    const bool ny = d == 0 ? q.nyq[0] : (d == 1 ? q.nyq[1] : q.nyq[2]);
+    return ny ? 0.0 : k;
+}
+
+// Ball moments F_m = integral over |r| <= Rc of r^m exp(-i k.r), m = 1, 0, -1, and j0(k Rc).
+__device__ __forceinline__ void ball_moments(double k, double Rc, double &F1, double &F0, double &Fm1, double &j0) {
+    const double y = k * Rc;
+    const double R2 = Rc * Rc;
+    if (y < 1.0) {
+        constexpr BallSeries<-1> sm{};
+        constexpr BallSeries<0> s0{};
+        constexpr BallSeries<1> s1{};
+        constexpr SincSeries sj{};
+        const double y2 = y * y;
+        Fm1 = kFourPi * R2 * horner_y2<double>(sm, y2);
+        F0 = kFourPi * R2 * Rc * horner_y2<double>(s0, y2);
+        F1 = kFourPi * R2 * R2 * horner_y2<double>(s1, y2);
+        j0 = horner_y2<double>(sj, y2);
+    } else {
+        double s, c;
+        sincos(y, &s, &c);
+        const double omc = (c > 0.0) ? s * s / (1.0 + c) : 1.0 - c;
+        const double iy = 1.0 / y, iy2 = iy * iy;
+        Fm1 = kFourPi * R2 * omc * iy2;
+        F0 = kFourPi * R2 * Rc * (s - y * c) * iy2 * iy;
+        F1 = kFourPi * R2 * R2 * (-c * iy2 + 2.0 * s * iy2 * iy - 2.0 * omc * iy2 * iy2);
+        j0 = s * iy;
+    }
+}
+
 // ------------------------------------------------------------------ eq. (Phi)
 // dPhi/dn_alpha of the anti-symmetrized Rosenfeld free-energy density, with the
 // bound |nV2| <= n2 enforced as xi^2 <- min(xi^2, 1).  D may be double or a dual number.
@@ -294,6 +349,27 @@ struct FmtOps<double> {
     static __device__ __forceinline__ double val(double a) { return a; }
     static __device__ __forceinline__ double cst(double a) { return a; }
     static __device__ __forceinline__ double lg(double a) { return log(a); }
+};
+
+// Forward-mode dual number: value and derivative along one direction.  fmt_dphi on duals
+// returns dPhi/dn at the value and the Hessian-vector product Phi''(n) dn in the tangent.
+struct Dual {
+    double v, d;
+};
+__device__ __forceinline__ Dual operator+(Dual a, Dual b) { return {a.v + b.v, a.d + b.d}; }
+__device__ __forceinline__ Dual operator-(Dual a, Dual b) { return {a.v - b.v, a.d - b.d}; }
+__device__ __forceinline__ Dual operator*(Dual a, Dual b) { return {a.v * b.v, a.d * b.v + a.v * b.d}; }
+__device__ __forceinline__ Dual operator*(Dual a, double b) { return {a.v * b, a.d * b}; }
+__device__ __forceinline__ Dual operator/(Dual a, Dual b) {
+    const double q = a.v / b.v;
+    return {q, (a.d - q * b.d) / b.v};
+}
+
+template <>
+struct FmtOps<Dual> {
+    static __device__ __forceinline__ double val(Dual a) { return a.v; }
+    static __device__ __forceinline__ Dual cst(double a) { return {a, 0.0}; }
+    static __device__ __forceinline__ Dual lg(Dual a) { return {log(a.v), a.d / a.v}; }
 };
 
 template <typename D>

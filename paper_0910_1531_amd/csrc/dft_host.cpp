@@ -3,6 +3,7 @@
 #include "dft_host.h"
 
 #include <cmath>
+#include <complex>
 #include <cstdio>
 #include <cstring>
 
@@ -177,6 +178,85 @@ dft_status bulk_info(const dft_params *p, dft_bulk_info *out, std::string *msg) 
                                e * s * ((2.0 * zk - e * s * s) / (1.0 + g * s) + e * s * s / 3.0));
     }
     return DFT_OK;
+}
+
+// ---------------------------------------------------------------- bath derivatives
+
+namespace {
+
+using cd = std::complex<double>;
+
+// beta mu_i^HS,bath (eq. muHSBath) for complex-step arguments.
+cd mu_hs_c(int i, int S, const cd *rho, const cd *sig) {
+    cd xi[4];
+    for (int n = 0; n < 4; ++n) {
+        cd sum = 0.0;
+        for (int k = 0; k < S; ++k) sum += rho[k] * std::pow(sig[k], n);
+        xi[n] = M_PI / 6.0 * sum;
+    }
+    const cd D = 1.0 - xi[3];
+    const cd bP = 6.0 / M_PI * (xi[0] / D + 3.0 * xi[1] * xi[2] / (D * D) + 3.0 * xi[2] * xi[2] * xi[2] / (D * D * D));
+    const cd s = sig[i];
+    return -std::log(D) + (3.0 * xi[2] * s + 3.0 * xi[1] * s * s) / D + 9.0 * xi[2] * xi[2] * s * s / (2.0 * D * D) +
+           bP * M_PI * s * s * s / 6.0;
+}
+
+// F(Gamma) of eq. (Gamma) for complex-step arguments.
+cd msa_F_c(cd g, int S, const cd *rho, const cd *sig, const double *z, double lB) {
+    cd xi3 = 0.0;
+    for (int k = 0; k < S; ++k) xi3 += M_PI / 6.0 * rho[k] * sig[k] * sig[k] * sig[k];
+    const cd c = M_PI / (2.0 * (1.0 - xi3));
+    cd Pn = 0.0, Om = 1.0;
+    for (int j = 0; j < S; ++j) {
+        const cd den = 1.0 + g * sig[j];
+        Pn += rho[j] * sig[j] * z[j] / den;
+        Om += c * rho[j] * sig[j] * sig[j] * sig[j] / den;
+    }
+    const cd eta = c * Pn / Om;
+    cd sum = 0.0;
+    for (int j = 0; j < S; ++j) {
+        const cd X = (z[j] - eta * sig[j] * sig[j]) / (1.0 + g * sig[j]);
+        sum += rho[j] * X * X;
+    }
+    return 4.0 * g * g - 4.0 * M_PI * lB * sum;
+}
+
+}  // namespace
+
+void bulk_derivatives(const dft_params *p, const dft_bulk_info &b, BulkDeriv *out) {
+    std::memset(out, 0, sizeof *out);
+    const int S = p->nspecies;
+    const double hstep = 1e-30;
+    cd rho[DFT_MAX_SPECIES], sig[DFT_MAX_SPECIES];
+    auto reset = [&]() {
+        for (int k = 0; k < S; ++k) {
+            rho[k] = p->rho_bulk[k];
+            sig[k] = 2.0 * p->radius[k];
+        }
+    };
+    const bool es = p->electrostatics && b.gamma > 0.0;
+    double FG = 0.0;
+    if (es) {
+        reset();
+        FG = std::imag(msa_F_c(cd(b.gamma, hstep), S, rho, sig, p->valence, p->bjerrum_length)) / hstep;
+    }
+    for (int k = 0; k < S; ++k) {
+        for (int which = 0; which < 2; ++which) {
+            reset();
+            if (which == 0) rho[k] += cd(0.0, hstep);
+            else sig[k] += cd(0.0, hstep);
+            for (int i = 0; i < S; ++i) {
+                const double d = std::imag(mu_hs_c(i, S, rho, sig)) / hstep;
+                if (which == 0) out->dmu_drho[i][k] = d;
+                else out->dmu_dsigma[i][k] = d;
+            }
+            if (es) {
+                const double Ft = std::imag(msa_F_c(cd(b.gamma, 0.0), S, rho, sig, p->valence, p->bjerrum_length)) / hstep;
+                if (which == 0) out->dgamma_drho[k] = -Ft / FG;
+                else out->dgamma_dsigma[k] = -Ft / FG;
+            }
+        }
+    }
 }
 
 // ---------------------------------------------------------------- FFT plans

@@ -58,6 +58,17 @@ bool make_plan(int L, FftPlan *plan);
 // tw[m] = exp(-2 pi i m / L), m = 0..L-1, interleaved (re, im), long-double accurate.
 void twiddles(int L, std::vector<double> *out);
 
+// Derivatives of the bath quantities with respect to rho_bulk_k and sigma_k = 2 R_k, by
+// complex-step differentiation of the Appendix A formulas (exact to rounding); dGamma
+// follows from implicit differentiation of eq. (Gamma).
+struct BulkDeriv {
+    double dmu_drho[DFT_MAX_SPECIES][DFT_MAX_SPECIES];    // [i][k]: d beta mu_i^HS / d rho_b,k
+    double dmu_dsigma[DFT_MAX_SPECIES][DFT_MAX_SPECIES];  // [i][k]: d beta mu_i^HS / d sigma_k
+    double dgamma_drho[DFT_MAX_SPECIES];
+    double dgamma_dsigma[DFT_MAX_SPECIES];
+};
+void bulk_derivatives(const dft_params *p, const dft_bulk_info &b, BulkDeriv *out);
+
 // Fill the constant block (nfluid is filled in by setup).
 void fill_consts(const dft_params *p, const dft_bulk_info &b, Consts *c);
 

@@ -44,7 +44,7 @@ struct RedBufs {
 };
 
 enum XFwdMode { XF_PLAIN = 0, XF_TRIAL = 1 };
-enum X2Mode { X2_FULL = 0, X2_N3_ONLY = 1 };
+enum X2Mode { X2_FULL = 0, X2_N3_ONLY = 1, X2_HESS = 2 };
 enum Z2Mode { Z2_EL = 0, Z2_POISSON = 1 };
 
 struct XFwdArgs {
@@ -64,6 +64,7 @@ struct YArgs {
     int nfield;
     int dir;
     const int *gate;
+    int axis = 1;       // 1: y, 2: z (plain transform along z)
 };
 
 struct Z1Args {
@@ -91,6 +92,8 @@ struct X2Args {
     float *nref_out;          // FP64 refresh: write n rounded to float [10][N]
     double *n_out;            // [10][N] FP64 copies for inspection, may be null
     double *dphi_out;         // [10][N], may be null
+    const double *nstar;      // X2_HESS: weighted densities of the expansion point [10][N] (FP64)
+    double *t_out;            // X2_HESS: Phi''(nstar) n written as [10][N] FP64, may be null
     RedBufs red;
     const int *gate;
 };

@@ -187,55 +187,30 @@ __global__ __launch_bounds__(NT) void k_y(Geo g, YArgs a, int W) {
     if (gated_off(a.gate)) return;
     extern __shared__ unsigned char smem_raw[];
     cx<T> *tile = reinterpret_cast<cx<T> *>(smem_raw);
-    const int L = g.ny, Kx = g.Kx;
-    int bx, z;
-    xcd_block(bx, z);
+    const bool zax = a.axis == 2;
+    const int L = zax ? g.nz : g.ny, Kx = g.Kx;
+    int bx, o;
+    xcd_block(bx, o);
     const int kx0 = bx * W;
     const int Wact = min(W, Kx - kx0);
     const int f = blockIdx.z;
-    cx<T> *base = reinterpret_cast<cx<T> *>(a.spec) + (long long)f * g.NC + (long long)z * g.ny * Kx + kx0;
+    // y: rows of one z plane (stride Kx); z: one y line through every plane (stride ny Kx)
+    const long long rs = zax ? (long long)g.ny * Kx : (long long)Kx;
+    const long long ob = zax ? (long long)o * Kx : (long long)o * g.ny * Kx;
+    cx<T> *base = reinterpret_cast<cx<T> *>(a.spec) + (long long)f * g.NC + ob + kx0;
     for (int j = threadIdx.x; j < Wact * L; j += NT) {
         const int e = j / Wact, p = j - e * Wact;
-        tile[j] = base[(long long)e * Kx + p];
+        tile[j] = base[(long long)e * rs + p];
     }
     __syncthreads();
-    fft_tile_dir<T, NT, MAXE>(a.dir, tile, g.py, Wact, Wact, 1, false, twp<T>(g, 1));
+    fft_tile_dir<T, NT, MAXE>(a.dir, tile, zax ? g.pz : g.py, Wact, Wact, 1, false, twp<T>(g, zax ? 2 : 1));
     for (int j = threadIdx.x; j < Wact * L; j += NT) {
         const int e = j / Wact, p = j - e * Wact;
-        base[(long long)e * Kx + p] = tile[j];
+        base[(long long)e * rs + p] = tile[j];
     }
 }
 
 // --------------------------------------------------------------------- z passes
-// Wavenumber data of one element of a z tile.
-struct KInfo {
-    double k[3];
-    double kmag;
-    bool nyq[3];
-    bool zero;
-};
-
-__device__ __forceinline__ KInfo kinfo(const Consts &c, int jx, int y, int e) {
-    KInfo q;
-    const int my = signed_mode(y, c.ny), mz = signed_mode(e, c.nz);
-    q.k[0] = jx * c.dk[0];
-    q.k[1] = my * c.dk[1];
-    q.k[2] = mz * c.dk[2];
-    q.kmag = sqrt(q.k[0] * q.k[0] + q.k[1] * q.k[1] + q.k[2] * q.k[2]);
-    q.nyq[0] = (c.nx % 2 == 0) && (2 * jx == c.nx);
-    q.nyq[1] = (c.ny % 2 == 0) && (2 * y == c.ny);
-    q.nyq[2] = (c.nz % 2 == 0) && (2 * e == c.nz);
-    q.zero = (jx == 0) && (y == 0) && (e == 0);
-    return q;
-}
-
-// Component d of k, zero on the Nyquist plane of axis d (register selects, no indexing).
-__device__ __forceinline__ double k_comp(const KInfo &q, int d) {
-    const double k = d == 0 ? q.k[0] : (d == 1 ? q.k[1] : q.k[2]);
-    const bool ny = d == 0 ? q.nyq[0] : (d == 1 ? q.nyq[1] : q.nyq[2]);
-    return ny ? 0.0 : k;
-}
-
 template <typename T>
 __device__ __forceinline__ void z_load(cx<T> *tile, const cx<T> *src, int Wact, int L, long long rowstride) {
     for (int j = threadIdx.x; j < Wact * L; j += NT) {
@@ -677,6 +652,24 @@ __global__ __launch_bounds__(NTB) void k_x2b(Geo g, X2Args a, int PB) {
                 n[f] = h == 0 ? (double)v.x : (double)v.y;
             }
             bool clamped = false;
+            if (a.mode == X2_HESS) {
+                // t = Phi''(n*) n by forward-mode differentiation of dPhi/dn at n*
+                Dual nd[DFT_NALPHA], dd[DFT_NALPHA];
+#pragma unroll
+                for (int f = 0; f < DFT_NALPHA; ++f) nd[f] = Dual{a.nstar[f * g.N + idx], n[f]};
+                fmt_dphi<Dual>(nd, dd, clamped);
+                bool bad = false;
+#pragma unroll
+                for (int f = 0; f < DFT_NALPHA; ++f) {
+                    d[f] = dd[f].d;
+                    bad |= !isfinite(d[f]);
+                    if (a.t_out) a.t_out[f * g.N + idx] = d[f];
+                    if (h == 0) tile[f * span + jj].x = T(d[f]);
+                    else tile[f * span + jj].y = T(d[f]);
+                }
+                if (bad) flag |= 1;
+                continue;
+            }
             if (a.nref) {
                 double nr[DFT_NALPHA], dr[DFT_NALPHA];
 #pragma unroll
@@ -821,11 +814,13 @@ void launch_x_forward(const Geo &g, const XFwdArgs &a, hipStream_t s) {
 
 template <typename T>
 void launch_y(const Geo &g, const YArgs &a, hipStream_t s) {
-    if (g.ny == 1) return;   // a length-1 transform is the identity
+    const bool zax = a.axis == 2;
+    const int L = zax ? g.nz : g.ny;
+    if (L == 1) return;   // a length-1 transform is the identity
     constexpr int E = Cfg<T>::YE;
-    const int W = yz_width<T, E>(g.ny, g.Kx);
-    dim3 grid((unsigned)ceil_div(g.Kx, W), (unsigned)g.nz, (unsigned)a.nfield);
-    const size_t sh = (size_t)W * g.ny * sizeof(cx<T>);
+    const int W = yz_width<T, E>(L, g.Kx);
+    dim3 grid((unsigned)ceil_div(g.Kx, W), (unsigned)(zax ? g.ny : g.nz), (unsigned)a.nfield);
+    const size_t sh = (size_t)W * L * sizeof(cx<T>);
     hipLaunchKernelGGL((k_y<T, E>), grid, dim3(NT), sh, s, g, a, W);
     check_launch("y");
 }
@@ -905,6 +900,7 @@ void launch_x2(const Geo &g, const X2Args &a, hipStream_t s) {
         check_launch("x2b");
         return;
     }
+    if (a.mode == X2_HESS) throw std::runtime_error("x2: Hessian mode needs the batched kernel (n_x <= 384)");
     constexpr int E = Cfg<T>::X2E;
     const int P = x_pairs<T, E>(g);
     const long long nb = ceil_div(npairs, P);

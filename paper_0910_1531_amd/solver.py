@@ -148,6 +148,27 @@ class Solver:
         _abi.check(self.lib.dft_profile(self.ctx, _ptr(rho), int(reps), ms), "dft_profile")
         return dict(zip(_abi.PASS_NAMES, list(ms)))
 
+    def adjoint(self, rho_star, dO_drho, tol=1e-11, max_iter=500, vext=True):
+        """dft_adjoint: gradients of an observable through the fixed point rho_star.
+
+        Returns dict with 'vext' (device [S][nz][ny][nx] or None), 'rho_bulk', 'sigma' (lists),
+        'iters' and 'resid'."""
+        self._check_rho(rho_star)
+        g = dO_drho.contiguous()
+        self._check_rho(g)
+        nbytes = ctypes.c_size_t()
+        _abi.check(self.lib.dft_adjoint_workspace_size(ctypes.byref(self.params), ctypes.byref(nbytes)),
+                   "dft_adjoint_workspace_size")
+        ws = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
+        dv = torch.empty_like(rho_star) if vext else None
+        drb = (ctypes.c_double * self.S)()
+        dsg = (ctypes.c_double * self.S)()
+        it, res = ctypes.c_int32(), ctypes.c_double()
+        _abi.check(self.lib.dft_adjoint(self.ctx, _ptr(rho_star), _ptr(g), _ptr(ws), ws.numel(), float(tol),
+                                        int(max_iter), _ptr(dv), drb, dsg, ctypes.byref(it), ctypes.byref(res)),
+                   "dft_adjoint")
+        return {"vext": dv, "rho_bulk": list(drb), "sigma": list(dsg), "iters": it.value, "resid": res.value}
+
     def stats(self):
         s = _abi.Stats()
         _abi.check(self.lib.dft_get_stats(self.ctx, ctypes.byref(s)), "dft_get_stats")

