@@ -248,6 +248,41 @@ dft_status dft_adjoint(dft_ctx *ctx, const double *rho_star, const double *dO_dr
                        double tol, int32_t max_iter, double *dO_dvext, double *dO_drho_bulk, double *dO_dsigma,
                        int32_t *iters_out, double *resid_out);
 
+/*
+ * Batches of independent state points (different concentrations, valences, radii, grids).
+ * Points of one shape (n, nspecies, precision) form a group; every pass of a residual
+ * evaluation is ONE launch over all points of a group, the line-search state machines run
+ * one device thread per point, and a whole Picard step of a group is one captured HIP
+ * graph.  Converged points retire (their work is gated off) while the others continue.
+ */
+typedef struct dft_batch dft_batch;
+
+/* Bytes of device workspace for `count` state points.  Host only. */
+dft_status dft_batch_workspace_size(const dft_params *params, int32_t count, size_t *bytes);
+
+/*
+ * Set up `count` state points.  params: host [count].  beta_vext, fixed_charge: host arrays
+ * [count] of device pointers (each as in dft_setup; the arrays themselves may be NULL).
+ * workspace: device, dft_batch_workspace_size bytes, 256-byte aligned, caller-owned.
+ */
+dft_status dft_setup_batch(const dft_params *params, int32_t count, const double *const *beta_vext,
+                           const double *const *fixed_charge, void *workspace, size_t ws_bytes, void *stream,
+                           dft_batch **out);
+
+/* The per-point ctx (for dft_residual, dft_get_stats, dft_adjoint ...); owned by the batch. */
+dft_status dft_batch_member(dft_batch *batch, int32_t i, dft_ctx **out);
+
+/*
+ * Solve every state point (as dft_solve) from the densities rho_inout[i] (host array of
+ * device pointers).  iters_out, norm_out, status_out: host [count], may be NULL.  Returns
+ * the first failing point's status (DFT_OK if all converged).
+ */
+dft_status dft_solve_batch(dft_batch *batch, double *const *rho_inout, double tol, int32_t max_iter,
+                           int32_t *iters_out, double *norm_out, int32_t *status_out);
+
+/* Free the batch, its points' ctxs and graphs; caller memory is untouched. */
+dft_status dft_batch_destroy(dft_batch *batch);
+
 /* Counters of the ctx (host out). */
 dft_status dft_get_stats(dft_ctx *ctx, dft_stats *out);
 

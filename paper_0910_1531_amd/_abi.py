@@ -67,6 +67,13 @@ SIGNATURES = [
     ("dft_adjoint_workspace_size", [ctypes.POINTER(Params), ctypes.POINTER(ctypes.c_size_t)]),
     ("dft_adjoint", [_vp, _vp, _vp, _vp, ctypes.c_size_t, ctypes.c_double, ctypes.c_int32, _vp, _dp, _dp,
                      ctypes.POINTER(ctypes.c_int32), _dp]),
+    ("dft_batch_workspace_size", [ctypes.POINTER(Params), ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]),
+    ("dft_setup_batch", [ctypes.POINTER(Params), ctypes.c_int32, _vp, _vp, _vp, ctypes.c_size_t, _vp,
+                         ctypes.POINTER(_vp)]),
+    ("dft_batch_member", [_vp, ctypes.c_int32, ctypes.POINTER(_vp)]),
+    ("dft_solve_batch", [_vp, _vp, ctypes.c_double, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), _dp,
+                         ctypes.POINTER(ctypes.c_int32)]),
+    ("dft_batch_destroy", [_vp]),
     ("dft_get_stats", [_vp, ctypes.POINTER(Stats)]),
     ("dft_destroy", [_vp]),
 ]

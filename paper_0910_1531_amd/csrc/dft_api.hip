@@ -234,7 +234,7 @@ void enqueue_eval_t(dft_ctx *c, const Eval &ev, hipStream_t s) {
     launch_x3<T>(g, x3, s);
     mark(ev, 9, s);
     launch_finalize(c->red, nparts_x3(g, sizeof(T) == 4), x2_nblocks<T>(g), ev.fslot, ev.mslot, c->st,
-                    ev.count_kind, ev.gate, s);
+                    ev.count_kind, ev.gate, s, g.nprob, g.pstride);
     mark(ev, 10, s);
 }
 
@@ -272,12 +272,12 @@ void enqueue_n3_t(dft_ctx *c, const double *alpha, double *mslot, const int *gat
     x2.red = c->red;
     x2.gate = gate;
     launch_x2<T>(g, x2, s);
-    launch_finalize(c->red, 0, x2_nblocks<T>(g), nullptr, mslot, c->st, 2, gate, s);
+    launch_finalize(c->red, 0, x2_nblocks<T>(g), nullptr, mslot, c->st, 2, gate, s, g.nprob, g.pstride);
 }
 
 void enqueue_step(dft_ctx *c, hipStream_t s) {
     DevState *st = c->st;
-    launch_ctl(st, CTL_BEGIN, s);
+    launch_ctl(st, CTL_BEGIN, s, c->geo.nprob, c->geo.pstride);
     Eval e1;
     e1.trial = true;
     e1.src = c->rho0;
@@ -291,36 +291,40 @@ void enqueue_step(dft_ctx *c, hipStream_t s) {
     enqueue_eval(c, e1, s);
     if (c->mixed) enqueue_n3_t<float>(c, &st->alpha_trial, &st->m1, &st->gate_part1, s);
     else enqueue_n3_t<double>(c, &st->alpha_trial, &st->m1, &st->gate_part1, s);
-    launch_ctl(st, CTL_AMAX, s);
+    launch_ctl(st, CTL_AMAX, s, c->geo.nprob, c->geo.pstride);
     Eval ea = e1;
     ea.g_out = c->ga;
     ea.fslot = &st->fa;
     ea.mslot = &st->ma;
     ea.gate = &st->gate_a;
     enqueue_eval(c, ea, s);
-    launch_ctl(st, CTL_B, s);
+    launch_ctl(st, CTL_B, s, c->geo.nprob, c->geo.pstride);
     Eval eb = e1;
     eb.g_out = c->gb;
     eb.fslot = &st->fb;
     eb.mslot = &st->mb;
     eb.gate = &st->gate_b;
     enqueue_eval(c, eb, s);
-    launch_ctl(st, CTL_FIT, s);
+    launch_ctl(st, CTL_FIT, s, c->geo.nprob, c->geo.pstride);
     Eval es = e1;
     es.g_out = c->gs;
     es.fslot = &st->fs;
     es.mslot = &st->ms;
     es.gate = &st->gate_s;
     enqueue_eval(c, es, s);
-    launch_ctl(st, CTL_ACCEPT, s);
-    launch_update(st, c->rho0, c->g0, c->gb, c->ga, c->gs, (long long)c->geo.S * c->geo.N, s);
-    launch_ctl(st, CTL_END, s);
+    launch_ctl(st, CTL_ACCEPT, s, c->geo.nprob, c->geo.pstride);
+    launch_update(st, c->rho0, c->g0, c->gb, c->ga, c->gs, (long long)c->geo.S * c->geo.N, s, c->geo.nprob,
+                  c->geo.pstride);
+    launch_ctl(st, CTL_END, s, c->geo.nprob, c->geo.pstride);
 }
 
 // FP64 evaluation at rho0 that also becomes the FP32-mixed reference (or plain prime).
-void enqueue_prime(dft_ctx *c, hipStream_t s) {
+// With `gated`, only the problems of a batch whose gate_refresh is set take part.
+void enqueue_prime(dft_ctx *c, hipStream_t s, bool gated = false) {
     DevState *st = c->st;
+    const int *gate = gated ? &st->gate_refresh : nullptr;
     Eval e;
+    e.gate = gate;
     e.trial = true;
     e.src = c->rho0;
     e.g0 = c->rho0;      // alpha = 0: rho_t = rho0 exactly
@@ -330,11 +334,11 @@ void enqueue_prime(dft_ctx *c, hipStream_t s) {
     e.mslot = &st->m0;
     e.fp64 = true;
     if (c->mixed) {
-        launch_copy(c->rho_ref, c->rho0, (long long)c->geo.S * c->geo.N, s);
+        launch_copy(c->rho_ref, c->rho0, (long long)c->geo.S * c->geo.N, s, c->geo.nprob, c->geo.pstride, gate);
         e.refresh = true;
     }
     enqueue_eval(c, e, s);
-    launch_ctl(st, CTL_PRIME, s);
+    launch_ctl(st, CTL_PRIME, s, c->geo.nprob, c->geo.pstride);
 }
 
 DevState read_state(dft_ctx *c) {
@@ -1059,6 +1063,232 @@ dft_status dft_adjoint(dft_ctx *ctx, const double *rho_star, const double *dO_dr
         }
         return DFT_OK;
     });
+}
+
+// ------------------------------------------------------------------ batches of state points
+struct dft_batch {
+    std::vector<dft_ctx *> members;   // caller order; each owns a slice of the batch workspace
+    struct Group {
+        std::vector<int> idx;         // members of one shape (n, S, precision)
+        dft_ctx *lead = nullptr;      // geometry covering the whole group (nprob, pstride)
+        long long stride = 0;
+    };
+    std::vector<Group> groups;
+    hipStream_t stream = nullptr;
+};
+
+namespace {
+
+bool same_shape(const dft_params &a, const dft_params &b) {
+    return a.n[0] == b.n[0] && a.n[1] == b.n[1] && a.n[2] == b.n[2] && a.nspecies == b.nspecies &&
+           a.precision == b.precision;
+}
+
+// Groups (first-seen order) and the byte offset of every member in the batch workspace.
+size_t batch_plan(const dft_params *params, int count, std::vector<dft_batch::Group> *groups,
+                  std::vector<size_t> *offsets) {
+    groups->clear();
+    offsets->assign(count, 0);
+    for (int i = 0; i < count; ++i) {
+        bool placed = false;
+        for (auto &g : *groups)
+            if (same_shape(params[g.idx[0]], params[i])) { g.idx.push_back(i); placed = true; break; }
+        if (!placed) {
+            dft_batch::Group g;
+            g.idx.push_back(i);
+            groups->push_back(g);
+        }
+    }
+    size_t off = 0;
+    for (auto &g : *groups) {
+        g.stride = (long long)make_layout(&params[g.idx[0]]).total;
+        for (size_t m = 0; m < g.idx.size(); ++m) (*offsets)[g.idx[m]] = off + m * (size_t)g.stride;
+        off += g.idx.size() * (size_t)g.stride;
+    }
+    return off;
+}
+
+}  // namespace
+
+dft_status dft_batch_workspace_size(const dft_params *params, int32_t count, size_t *bytes) {
+    if (!params || count < 1 || !bytes) return fail(DFT_E_INVALID_ARG, "params, count or bytes invalid");
+    std::string msg;
+    for (int i = 0; i < count; ++i) {
+        dft_status st = validate(&params[i], &msg);
+        if (st != DFT_OK) return fail(st, "state point " + std::to_string(i) + ": " + msg);
+    }
+    std::vector<dft_batch::Group> groups;
+    std::vector<size_t> offs;
+    *bytes = batch_plan(params, count, &groups, &offs);
+    return DFT_OK;
+}
+
+dft_status dft_setup_batch(const dft_params *params, int32_t count, const double *const *beta_vext,
+                           const double *const *fixed_charge, void *workspace, size_t ws_bytes, void *stream,
+                           dft_batch **out) {
+    if (!out) return fail(DFT_E_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    size_t need = 0;
+    dft_status st = dft_batch_workspace_size(params, count, &need);
+    if (st != DFT_OK) return st;
+    if (!workspace || ws_bytes < need || ((uintptr_t)workspace) % 256 != 0)
+        return fail(DFT_E_WORKSPACE, "batch workspace missing, misaligned or smaller than dft_batch_workspace_size");
+    dft_batch *b = new dft_batch();
+    b->stream = (hipStream_t)stream;
+    std::vector<size_t> offs;
+    batch_plan(params, count, &b->groups, &offs);
+    for (int i = 0; i < count; ++i) {
+        dft_ctx *c = nullptr;
+        st = dft_setup(&params[i], beta_vext ? beta_vext[i] : nullptr, fixed_charge ? fixed_charge[i] : nullptr,
+                       (char *)workspace + offs[i], ws_bytes - offs[i], stream, &c);
+        if (st != DFT_OK) {
+            std::string m = dft_last_error();
+            dft_batch_destroy(b);
+            return fail(st, "state point " + std::to_string(i) + ": " + m);
+        }
+        b->members.push_back(c);
+    }
+    for (auto &g : b->groups) {
+        dft_ctx *lead = new dft_ctx(*b->members[g.idx[0]]);
+        lead->graph = nullptr;
+        lead->gexec = nullptr;
+        lead->cap_stream = nullptr;
+        lead->geo.nprob = (int)g.idx.size();
+        lead->geo.pstride = g.stride;
+        g.lead = lead;
+    }
+    *out = b;
+    g_last_error.clear();
+    return DFT_OK;
+}
+
+dft_status dft_batch_member(dft_batch *batch, int32_t i, dft_ctx **out) {
+    if (!batch || !out || i < 0 || i >= (int)batch->members.size()) return fail(DFT_E_INVALID_ARG, "bad batch index");
+    *out = batch->members[i];
+    return DFT_OK;
+}
+
+dft_status dft_solve_batch(dft_batch *batch, double *const *rho_inout, double tol, int32_t max_iter,
+                           int32_t *iters_out, double *norm_out, int32_t *status_out) {
+    if (!batch || !rho_inout) return fail(DFT_E_INVALID_ARG, "batch or rho is NULL");
+    if (!(tol >= 0.0) || max_iter < 0) return fail(DFT_E_INVALID_ARG, "tol must be >= 0 and max_iter >= 0");
+    const int n = (int)batch->members.size();
+    for (int i = 0; i < n; ++i)
+        if (!rho_inout[i]) return fail(DFT_E_INVALID_ARG, "rho_inout has a NULL entry");
+    return guarded([&]() -> dft_status {
+        hipStream_t s = batch->stream;
+        std::vector<DevState> h(n);
+        std::vector<double> r_ref(n), r_prev(n);
+        std::vector<char> checked(n, 1), done(n, 0);
+        std::vector<int> stat(n, DFT_OK);
+        for (auto &g : batch->groups) {
+            for (int i : g.idx) {
+                dft_ctx *c = batch->members[i];
+                c->stream = s;
+                write_state(c, fresh_state(c, tol, max_iter));
+                launch_copy(c->rho0, rho_inout[i], (long long)c->geo.S * c->geo.N, s);
+                c->step_rho = nullptr;
+            }
+            g.lead->stream = s;
+            enqueue_prime(g.lead, s);
+            for (int i : g.idx)
+                if (batch->members[i]->mixed) batch->members[i]->refreshes += 1;
+            ensure_graph(g.lead);
+        }
+        for (int i = 0; i < n; ++i) {
+            h[i] = read_state(batch->members[i]);
+            r_ref[i] = r_prev[i] = h[i].r;
+        }
+        for (;;) {
+            // classify, and choose the members that need an FP64 (reference) evaluation
+            std::vector<char> refresh(n, 0);
+            bool any_active = false;
+            for (int i = 0; i < n; ++i) {
+                if (done[i]) continue;
+                const bool mixed = batch->members[i]->mixed;
+                if (h[i].status) { stat[i] = h[i].status; done[i] = 1; continue; }
+                if (h[i].converged) {
+                    if (checked[i]) { done[i] = 1; continue; }
+                    refresh[i] = 1;
+                } else if (h[i].iters >= max_iter || h[i].rejected >= 4 * (long long)max_iter + 16) {
+                    stat[i] = DFT_E_NOT_CONVERGED;
+                    done[i] = 1;
+                    continue;
+                } else if (mixed && !checked[i] && (h[i].r < 1e-3 * r_ref[i] || !(h[i].r < 0.99 * r_prev[i]))) {
+                    refresh[i] = 1;
+                }
+                any_active = true;
+            }
+            if (!any_active) break;
+            bool any_refresh = false;
+            for (auto &g : batch->groups) {
+                bool gr = false;
+                for (int i : g.idx) gr |= refresh[i] != 0;
+                if (!gr) continue;
+                any_refresh = true;
+                std::vector<int> flags(g.idx.size());
+                for (size_t m = 0; m < g.idx.size(); ++m) {
+                    flags[m] = refresh[g.idx[m]];
+                    HIPCHK(hipMemcpyAsync(&batch->members[g.idx[m]]->st->gate_refresh, &flags[m], sizeof(int),
+                                          hipMemcpyHostToDevice, s));
+                }
+                enqueue_prime(g.lead, s, true);
+                HIPCHK(hipStreamSynchronize(s));
+            }
+            if (any_refresh) {
+                for (int i = 0; i < n; ++i) {
+                    if (!refresh[i]) continue;
+                    h[i] = read_state(batch->members[i]);
+                    r_ref[i] = h[i].r;
+                    checked[i] = 1;
+                    batch->members[i]->refreshes += 1;
+                }
+                continue;
+            }
+            for (auto &g : batch->groups) {
+                bool active = false;
+                for (int i : g.idx) active |= !done[i];
+                if (!active) continue;
+                long long ntot = 0;
+                for (int i : g.idx) ntot += batch->members[i]->geo.N;
+                const int K = ntot >= (1LL << 22) ? 4 : 16;
+                for (int k = 0; k < K; ++k) HIPCHK(hipGraphLaunch(g.lead->gexec, s));
+            }
+            for (int i = 0; i < n; ++i) {
+                if (done[i]) continue;
+                r_prev[i] = h[i].r;
+                h[i] = read_state(batch->members[i]);
+                checked[i] = !batch->members[i]->mixed;
+            }
+        }
+        dft_status out = DFT_OK;
+        for (int i = 0; i < n; ++i) {
+            dft_ctx *c = batch->members[i];
+            launch_copy(rho_inout[i], c->rho0, (long long)c->geo.S * c->geo.N, s);
+            c->step_rho = rho_inout[i];
+            if (iters_out) iters_out[i] = (int32_t)h[i].iters;
+            if (norm_out) norm_out[i] = h[i].r;
+            if (status_out) status_out[i] = stat[i];
+            if (stat[i] != DFT_OK && out == DFT_OK) out = (dft_status)stat[i];
+        }
+        HIPCHK(hipStreamSynchronize(s));
+        if (out != DFT_OK) return fail(out, "at least one state point did not converge (see status_out)");
+        return DFT_OK;
+    });
+}
+
+dft_status dft_batch_destroy(dft_batch *batch) {
+    if (!batch) return DFT_OK;
+    for (auto &g : batch->groups) {
+        if (!g.lead) continue;
+        if (g.lead->gexec) (void)hipGraphExecDestroy(g.lead->gexec);
+        if (g.lead->graph) (void)hipGraphDestroy(g.lead->graph);
+        if (g.lead->cap_stream) (void)hipStreamDestroy(g.lead->cap_stream);
+        delete g.lead;
+    }
+    for (dft_ctx *c : batch->members) dft_destroy(c);
+    delete batch;
+    return DFT_OK;
 }
 
 dft_status dft_get_stats(dft_ctx *ctx, dft_stats *out) {

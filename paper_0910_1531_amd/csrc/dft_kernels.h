@@ -18,6 +18,7 @@ struct DevState {
     double best_f;
     long long iters, rejected, gevals, n3evals, max_iter;
     int gate_full1, gate_part1, gate_a, gate_b, gate_s, gate_upd, gate_run, gate_one;
+    int gate_refresh;       // batches: this problem takes the next FP64 reference evaluation
     int src;                // accepted sample: 0 = amax, 1 = amax/2, 2 = vertex
     int status;             // dft_status of the device loop (NONFINITE, PACKING)
     int converged;
@@ -32,6 +33,10 @@ struct Geo {
     const void *tw32[3];   // cx<float> tables per axis
     int nx, ny, nz, Kx, S;
     long long N, NC;
+    // Batches of identically shaped problems: the kernels of one launch cover nprob
+    // problems whose workspaces sit pstride bytes apart (blockIdx.z carries the problem).
+    int nprob = 1;
+    long long pstride = 0;
 };
 
 // Where the reductions of one residual evaluation go.
@@ -130,15 +135,15 @@ int x3_blocks(const Geo &g);
 // Reduction of the partials into state slots (single block, fixed order).
 // A non-finite evaluation stores +inf in its slots (the line search then rejects it).
 void launch_finalize(const RedBufs &r, int nf, int nm, double *fslot, double *mslot, DevState *st,
-                     int count_kind, const int *gate, hipStream_t s);
+                     int count_kind, const int *gate, hipStream_t s, int nprob = 1, long long pstride = 0);
 
-// Control kernels of the line search (single thread).
+// Control kernels of the line search (one thread per problem of a batch).
 enum CtlOp { CTL_BEGIN = 0, CTL_AMAX = 1, CTL_B = 2, CTL_FIT = 3, CTL_ACCEPT = 4, CTL_END = 5, CTL_PRIME = 6 };
-void launch_ctl(DevState *st, int op, hipStream_t s);
+void launch_ctl(DevState *st, int op, hipStream_t s, int nprob = 1, long long pstride = 0);
 
 // rho0 <- rho0 + alpha (G0 - rho0); G0 <- G_src (src chosen on device).
 void launch_update(DevState *st, double *rho0, double *g0, const double *gb, const double *ga, const double *gs,
-                   long long count, hipStream_t s);
+                   long long count, hipStream_t s, int nprob = 1, long long pstride = 0);
 
 // Setup helpers: base_k = mu_k - beta V_k - z_k phi_fixed (-inf where V = +inf), and
 // per-block counts of fluid nodes.
@@ -146,6 +151,7 @@ void launch_make_base(const Consts *cs, int S, long long N, const double *vext, 
                       double *base, const double *mu_host, const double *z_host, double *count_part, int nblk,
                       hipStream_t s);
 void launch_sum_to(const double *part, int n, double *dst, hipStream_t s);
-void launch_copy(double *dst, const double *src, long long count, hipStream_t s);
+void launch_copy(double *dst, const double *src, long long count, hipStream_t s, int nprob = 1,
+                 long long pstride = 0, const int *gate = nullptr);
 
 }  // namespace dft

@@ -21,6 +21,7 @@
 #include <cmath>
 #include <cstdio>
 #include <stdexcept>
+#include <type_traits>
 
 namespace dft {
 
@@ -43,6 +44,52 @@ template <> __device__ __forceinline__ const cx<float> *twp<float>(const Geo &g,
 }
 
 __device__ __forceinline__ bool gated_off(const int *gate) { return gate != nullptr && *gate == 0; }
+
+// ------------------------------------------------------------------ batches
+// Pointers of problem `prob` of a batch: every workspace pointer moves by prob * pstride.
+template <typename P>
+__device__ __forceinline__ P *shp(P *ptr, long long off) {
+    return ptr ? reinterpret_cast<P *>(reinterpret_cast<char *>(const_cast<typename std::remove_const<P>::type *>(ptr)) + off)
+               : nullptr;
+}
+__device__ __forceinline__ RedBufs shift(RedBufs r, long long o) {
+    r.fpart = shp(r.fpart, o); r.mpart = shp(r.mpart, o); r.fflag = shp(r.fflag, o); r.mflag = shp(r.mflag, o);
+    return r;
+}
+__device__ __forceinline__ XFwdArgs shift(XFwdArgs a, long long o) {
+    a.src = shp(a.src, o); a.g0 = shp(a.g0, o); a.alpha = shp(a.alpha, o); a.rho_t = shp(a.rho_t, o);
+    a.ref = shp(a.ref, o); a.spec = shp(a.spec, o); a.gate = shp(a.gate, o);
+    return a;
+}
+__device__ __forceinline__ YArgs shift(YArgs a, long long o) {
+    a.spec = shp(a.spec, o); a.gate = shp(a.gate, o);
+    return a;
+}
+__device__ __forceinline__ Z1Args shift(Z1Args a, long long o) {
+    a.specA = shp(a.specA, o); a.specB = shp(a.specB, o); a.gate = shp(a.gate, o);
+    return a;
+}
+__device__ __forceinline__ Z2Args shift(Z2Args a, long long o) {
+    a.specA = shp(a.specA, o); a.specB = shp(a.specB, o); a.gate = shp(a.gate, o);
+    return a;
+}
+__device__ __forceinline__ X2Args shift(X2Args a, long long o) {
+    a.specB = shp(a.specB, o); a.nref = shp(a.nref, o); a.nref_out = shp(a.nref_out, o);
+    a.n_out = shp(a.n_out, o); a.dphi_out = shp(a.dphi_out, o); a.nstar = shp(a.nstar, o);
+    a.t_out = shp(a.t_out, o); a.red = shift(a.red, o); a.gate = shp(a.gate, o);
+    return a;
+}
+__device__ __forceinline__ X3Args shift(X3Args a, long long o) {
+    a.specA = shp(a.specA, o); a.addend = shp(a.addend, o); a.raw_out = shp(a.raw_out, o);
+    a.base = shp(a.base, o); a.rho_t = shp(a.rho_t, o); a.g_out = shp(a.g_out, o); a.e_out = shp(a.e_out, o);
+    a.e_phi = shp(a.e_phi, o); a.lp_out = shp(a.lp_out, o); a.red = shift(a.red, o); a.gate = shp(a.gate, o);
+    return a;
+}
+// Geometry of problem `prob`: its constants move with its workspace; twiddles are shared.
+__device__ __forceinline__ Geo shift(Geo g, long long o) {
+    g.cs = shp(g.cs, o);
+    return g;
+}
 
 // Block coordinates with consecutive column chunks kept on one XCD: blocks are dispatched
 // round-robin over the 8 XCDs by linear id, so linear ids are regrouped into 8 contiguous
@@ -142,7 +189,14 @@ __device__ __forceinline__ void x_load_halves(cx<T> *tile, int L, int Kx, int Pa
 }
 
 template <typename T, int MAXE>
-__global__ __launch_bounds__(NT) void k_x_forward(Geo g, XFwdArgs a, int P) {
+__global__ __launch_bounds__(NT) void k_x_forward(Geo g_in, XFwdArgs a, int P) {
+    const int prob_ = (int)blockIdx.z / (1);
+    if (prob_ > 0) {
+        const long long off_ = (long long)prob_ * g_in.pstride;
+        g_in = shift(g_in, off_);
+        a = shift(a, off_);
+    }
+    const Geo &g = g_in;
     if (gated_off(a.gate)) return;
     extern __shared__ unsigned char smem_raw[];
     cx<T> *tile = reinterpret_cast<cx<T> *>(smem_raw);
@@ -183,7 +237,14 @@ __global__ __launch_bounds__(NT) void k_x_forward(Geo g, XFwdArgs a, int P) {
 
 // --------------------------------------------------------------------- y passes
 template <typename T, int MAXE>
-__global__ __launch_bounds__(NT) void k_y(Geo g, YArgs a, int W) {
+__global__ __launch_bounds__(NT) void k_y(Geo g_in, YArgs a, int W) {
+    const int prob_ = (int)blockIdx.z / (a.nfield);
+    if (prob_ > 0) {
+        const long long off_ = (long long)prob_ * g_in.pstride;
+        g_in = shift(g_in, off_);
+        a = shift(a, off_);
+    }
+    const Geo &g = g_in;
     if (gated_off(a.gate)) return;
     extern __shared__ unsigned char smem_raw[];
     cx<T> *tile = reinterpret_cast<cx<T> *>(smem_raw);
@@ -193,7 +254,7 @@ __global__ __launch_bounds__(NT) void k_y(Geo g, YArgs a, int W) {
     xcd_block(bx, o);
     const int kx0 = bx * W;
     const int Wact = min(W, Kx - kx0);
-    const int f = blockIdx.z;
+    const int f = (int)blockIdx.z % a.nfield;
     // y: rows of one z plane (stride Kx); z: one y line through every plane (stride ny Kx)
     const long long rs = zax ? (long long)g.ny * Kx : (long long)Kx;
     const long long ob = zax ? (long long)o * Kx : (long long)o * g.ny * Kx;
@@ -234,7 +295,14 @@ __device__ __forceinline__ void z_store(const cx<T> *tile, cx<T> *dst, int Wact,
 //       (eqs. muESexpansion, potentialSolution), written unnormalized over rho_hat in specA.
 // Spectral factors are evaluated in the transform precision T.
 template <typename T, int MAXE, int MAXS>
-__global__ __launch_bounds__(NT) void k_z1(Geo g, Z1Args a, int W) {
+__global__ __launch_bounds__(NT) void k_z1(Geo g_in, Z1Args a, int W) {
+    const int prob_ = (int)blockIdx.z / (1);
+    if (prob_ > 0) {
+        const long long off_ = (long long)prob_ * g_in.pstride;
+        g_in = shift(g_in, off_);
+        a = shift(a, off_);
+    }
+    const Geo &g = g_in;
     if (gated_off(a.gate)) return;
     extern __shared__ unsigned char smem_raw[];
     cx<T> *tile = reinterpret_cast<cx<T> *>(smem_raw);
@@ -369,7 +437,14 @@ __global__ __launch_bounds__(NT) void k_z1(Geo g, Z1Args a, int W) {
 // spectra Z1 left in specA, times 1/N, inverse z -> specA.  Z2_POISSON instead forms the
 // potential of weighted source spectra.
 template <typename T, int MAXE>
-__global__ __launch_bounds__(NT) void k_z2(Geo g, Z2Args a, int W) {
+__global__ __launch_bounds__(NT) void k_z2(Geo g_in, Z2Args a, int W) {
+    const int prob_ = (int)blockIdx.z / (1);
+    if (prob_ > 0) {
+        const long long off_ = (long long)prob_ * g_in.pstride;
+        g_in = shift(g_in, off_);
+        a = shift(a, off_);
+    }
+    const Geo &g = g_in;
     if (gated_off(a.gate)) return;
     extern __shared__ unsigned char smem_raw[];
     cx<T> *tile = reinterpret_cast<cx<T> *>(smem_raw);
@@ -490,7 +565,14 @@ __global__ __launch_bounds__(NT) void k_z2(Geo g, Z2Args a, int W) {
 
 // --------------------------------------------------------------------- X2: pointwise FMT
 template <typename T, int MAXE>
-__global__ __launch_bounds__(NT) void k_x2(Geo g, X2Args a, int P) {
+__global__ __launch_bounds__(NT) void k_x2(Geo g_in, X2Args a, int P) {
+    const int prob_ = (int)blockIdx.z / (1);
+    if (prob_ > 0) {
+        const long long off_ = (long long)prob_ * g_in.pstride;
+        g_in = shift(g_in, off_);
+        a = shift(a, off_);
+    }
+    const Geo &g = g_in;
     if (gated_off(a.gate)) return;
     extern __shared__ unsigned char smem_raw[];
     cx<T> *tile = reinterpret_cast<cx<T> *>(smem_raw);
@@ -601,7 +683,14 @@ __global__ __launch_bounds__(NT) void k_x2(Geo g, X2Args a, int P) {
 // direction is one FFT over the batch (one barrier pair per stage for all fields) and
 // the pointwise work reads and writes LDS instead of holding the fields in registers.
 template <typename T, int NTB, int MAXE>
-__global__ __launch_bounds__(NTB) void k_x2b(Geo g, X2Args a, int PB) {
+__global__ __launch_bounds__(NTB) void k_x2b(Geo g_in, X2Args a, int PB) {
+    const int prob_ = (int)blockIdx.z / (1);
+    if (prob_ > 0) {
+        const long long off_ = (long long)prob_ * g_in.pstride;
+        g_in = shift(g_in, off_);
+        a = shift(a, off_);
+    }
+    const Geo &g = g_in;
     if (gated_off(a.gate)) return;
     extern __shared__ unsigned char smem_raw[];
     cx<T> *tile = reinterpret_cast<cx<T> *>(smem_raw);
@@ -724,7 +813,14 @@ __global__ __launch_bounds__(NTB) void k_x2b(Geo g, X2Args a, int PB) {
 
 // --------------------------------------------------------------------- X3: Euler-Lagrange update
 template <typename T, int MAXE>
-__global__ __launch_bounds__(NT) void k_x3(Geo g, X3Args a, int P) {
+__global__ __launch_bounds__(NT) void k_x3(Geo g_in, X3Args a, int P) {
+    const int prob_ = (int)blockIdx.z / (1);
+    if (prob_ > 0) {
+        const long long off_ = (long long)prob_ * g_in.pstride;
+        g_in = shift(g_in, off_);
+        a = shift(a, off_);
+    }
+    const Geo &g = g_in;
     if (gated_off(a.gate)) return;
     extern __shared__ unsigned char smem_raw[];
     cx<T> *tile = reinterpret_cast<cx<T> *>(smem_raw);
@@ -806,7 +902,7 @@ void launch_x_forward(const Geo &g, const XFwdArgs &a, hipStream_t s) {
     constexpr int E = Cfg<T>::XE;
     const int P = x_pairs<T, E>(g);
     const long long npairs = ((long long)g.ny * g.nz + 1) / 2;
-    dim3 grid((unsigned)ceil_div(npairs, P), (unsigned)a.nfield);
+    dim3 grid((unsigned)ceil_div(npairs, P), (unsigned)a.nfield, (unsigned)g.nprob);
     const size_t sh = (size_t)P * g.nx * sizeof(cx<T>);
     hipLaunchKernelGGL((k_x_forward<T, E>), grid, dim3(NT), sh, s, g, a, P);
     check_launch("x_forward");
@@ -819,7 +915,7 @@ void launch_y(const Geo &g, const YArgs &a, hipStream_t s) {
     if (L == 1) return;   // a length-1 transform is the identity
     constexpr int E = Cfg<T>::YE;
     const int W = yz_width<T, E>(L, g.Kx);
-    dim3 grid((unsigned)ceil_div(g.Kx, W), (unsigned)(zax ? g.ny : g.nz), (unsigned)a.nfield);
+    dim3 grid((unsigned)ceil_div(g.Kx, W), (unsigned)(zax ? g.ny : g.nz), (unsigned)(a.nfield * g.nprob));
     const size_t sh = (size_t)W * L * sizeof(cx<T>);
     hipLaunchKernelGGL((k_y<T, E>), grid, dim3(NT), sh, s, g, a, W);
     check_launch("y");
@@ -829,7 +925,7 @@ template <typename T>
 void launch_z1(const Geo &g, const Z1Args &a, hipStream_t s) {
     constexpr int E = Cfg<T>::ZE;
     const int W = yz_width<T, E>(g.nz, g.Kx);
-    dim3 grid((unsigned)ceil_div(g.Kx, W), (unsigned)g.ny);
+    dim3 grid((unsigned)ceil_div(g.Kx, W), (unsigned)g.ny, (unsigned)g.nprob);
     const size_t sh = (size_t)W * g.nz * sizeof(cx<T>);
     if (g.S <= 4)
         hipLaunchKernelGGL((k_z1<T, E, 4>), grid, dim3(NT), sh, s, g, a, W);
@@ -842,7 +938,7 @@ template <typename T>
 void launch_z2(const Geo &g, const Z2Args &a, hipStream_t s) {
     constexpr int E = Cfg<T>::ZE;
     const int W = yz_width<T, E>(g.nz, g.Kx);
-    dim3 grid((unsigned)ceil_div(g.Kx, W), (unsigned)g.ny);
+    dim3 grid((unsigned)ceil_div(g.Kx, W), (unsigned)g.ny, (unsigned)g.nprob);
     const size_t sh = (size_t)W * g.nz * sizeof(cx<T>);
     hipLaunchKernelGGL((k_z2<T, E>), grid, dim3(NT), sh, s, g, a, W);
     check_launch("z2");
@@ -894,9 +990,11 @@ void launch_x2(const Geo &g, const X2Args &a, hipStream_t s) {
         if (nb > a.red.cap) throw std::runtime_error("x2: reduction buffer too small");
         const size_t sh = (size_t)DFT_NALPHA * pb * g.nx * sizeof(cx<T>);
         if (ntb == 256)
-            hipLaunchKernelGGL((k_x2b<T, 256, kX2bE>), dim3((unsigned)nb), dim3(256), sh, s, g, a, pb);
+            hipLaunchKernelGGL((k_x2b<T, 256, kX2bE>), dim3((unsigned)nb, 1, (unsigned)g.nprob), dim3(256), sh, s, g, a,
+                               pb);
         else
-            hipLaunchKernelGGL((k_x2b<T, 512, kX2bE>), dim3((unsigned)nb), dim3(512), sh, s, g, a, pb);
+            hipLaunchKernelGGL((k_x2b<T, 512, kX2bE>), dim3((unsigned)nb, 1, (unsigned)g.nprob), dim3(512), sh, s, g, a,
+                               pb);
         check_launch("x2b");
         return;
     }
@@ -906,7 +1004,7 @@ void launch_x2(const Geo &g, const X2Args &a, hipStream_t s) {
     const long long nb = ceil_div(npairs, P);
     if (nb > a.red.cap) throw std::runtime_error("x2: reduction buffer too small");
     const size_t sh = (size_t)P * g.nx * sizeof(cx<T>);
-    hipLaunchKernelGGL((k_x2<T, E>), dim3((unsigned)nb), dim3(NT), sh, s, g, a, P);
+    hipLaunchKernelGGL((k_x2<T, E>), dim3((unsigned)nb, 1, (unsigned)g.nprob), dim3(NT), sh, s, g, a, P);
     check_launch("x2");
 }
 
@@ -922,7 +1020,7 @@ void launch_x3(const Geo &g, const X3Args &a, hipStream_t s) {
     const long long npairs = ((long long)g.ny * g.nz + 1) / 2;
     const long long nb = ceil_div(npairs, P);
     if (!a.raw && nb * a.nfield > a.red.cap) throw std::runtime_error("x3: reduction buffer too small");
-    dim3 grid((unsigned)nb, (unsigned)a.nfield);
+    dim3 grid((unsigned)nb, (unsigned)a.nfield, (unsigned)g.nprob);
     const size_t sh = (size_t)P * g.nx * sizeof(cx<T>);
     hipLaunchKernelGGL((k_x3<T, E>), grid, dim3(NT), sh, s, g, a, P);
     check_launch("x3");
@@ -943,8 +1041,14 @@ template void launch_x3<float>(const Geo &, const X3Args &, hipStream_t);
 
 // --------------------------------------------------------------------- reductions, control
 __global__ __launch_bounds__(NT) void k_finalize(RedBufs r, int nf, int nm, double *fslot, double *mslot,
-                                                 DevState *st, int count_kind, const int *gate) {
+                                                 DevState *st, int count_kind, const int *gate, long long pstride) {
+    const long long off = (long long)blockIdx.x * pstride;
+    gate = shp(gate, off);
     if (gated_off(gate)) return;
+    r = shift(r, off);
+    fslot = shp(fslot, off);
+    mslot = shp(mslot, off);
+    st = shp(st, off);
     __shared__ double ss[NT], sm[NT];
     __shared__ int sf[NT];
     double a = 0.0, m = -INFINITY;
@@ -975,8 +1079,9 @@ __global__ __launch_bounds__(NT) void k_finalize(RedBufs r, int nf, int nm, doub
 }
 
 void launch_finalize(const RedBufs &r, int nf, int nm, double *fslot, double *mslot, DevState *st, int count_kind,
-                     const int *gate, hipStream_t s) {
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(NT), 0, s, r, nf, nm, fslot, mslot, st, count_kind, gate);
+                     const int *gate, hipStream_t s, int nprob, long long pstride) {
+    hipLaunchKernelGGL(k_finalize, dim3(nprob), dim3(NT), 0, s, r, nf, nm, fslot, mslot, st, count_kind, gate,
+                       pstride);
     check_launch("finalize");
 }
 
@@ -985,9 +1090,10 @@ constexpr double kCapFloor = 1.0 / 1024.0;
 // Line-search state machine (one thread).  The order of samples and the acceptance rule
 // follow the nonlinear-solver section as read in the oracle: samples at amax/2 and amax,
 // quadratic fit in t = alpha / amax, best evaluated point accepted if it lowers f.
-__global__ void k_ctl(DevState *st, int op) {
-    if (threadIdx.x != 0) return;
-    DevState &s = *st;
+__global__ void k_ctl(DevState *st, int op, int nprob, long long pstride) {
+    const int prob = blockIdx.x * blockDim.x + threadIdx.x;
+    if (prob >= nprob) return;
+    DevState &s = *shp(st, (long long)prob * pstride);
     switch (op) {
     case CTL_PRIME: {
         s.r = sqrt(s.f0 / s.nfluid);
@@ -1072,17 +1178,21 @@ __global__ void k_ctl(DevState *st, int op) {
     }
 }
 
-void launch_ctl(DevState *st, int op, hipStream_t s) {
-    hipLaunchKernelGGL(k_ctl, dim3(1), dim3(64), 0, s, st, op);
+void launch_ctl(DevState *st, int op, hipStream_t s, int nprob, long long pstride) {
+    hipLaunchKernelGGL(k_ctl, dim3((nprob + 63) / 64), dim3(64), 0, s, st, op, nprob, pstride);
     check_launch("ctl");
 }
 
 __global__ __launch_bounds__(NT) void k_update(const DevState *st, double *rho0, double *g0, const double *gb,
-                                               const double *ga, const double *gs, long long count) {
+                                               const double *ga, const double *gs, long long count, long long pstride) {
+    const long long off = (long long)blockIdx.y * pstride;
+    st = shp(st, off);
     if (!st->gate_upd) return;
+    rho0 = shp(rho0, off);
+    g0 = shp(g0, off);
     const double alpha = st->alpha_acc;
     const int src = st->src;
-    const double *gsrc = src == 0 ? gb : (src == 1 ? ga : gs);
+    const double *gsrc = shp(src == 0 ? gb : (src == 1 ? ga : gs), off);
     for (long long i = (long long)blockIdx.x * NT + threadIdx.x; i < count; i += (long long)gridDim.x * NT) {
         const double r = rho0[i];
         rho0[i] = fma(alpha, g0[i] - r, r);
@@ -1091,9 +1201,10 @@ __global__ __launch_bounds__(NT) void k_update(const DevState *st, double *rho0,
 }
 
 void launch_update(DevState *st, double *rho0, double *g0, const double *gb, const double *ga, const double *gs,
-                   long long count, hipStream_t s) {
+                   long long count, hipStream_t s, int nprob, long long pstride) {
     const long long nb = std::min<long long>(ceil_div(count, NT), 8192);
-    hipLaunchKernelGGL(k_update, dim3((unsigned)nb), dim3(NT), 0, s, st, rho0, g0, gb, ga, gs, count);
+    hipLaunchKernelGGL(k_update, dim3((unsigned)nb, (unsigned)nprob), dim3(NT), 0, s, st, rho0, g0, gb, ga, gs, count,
+                       pstride);
     check_launch("update");
 }
 
@@ -1158,13 +1269,19 @@ void launch_sum_to(const double *part, int n, double *dst, hipStream_t s) {
     check_launch("sum_to");
 }
 
-__global__ __launch_bounds__(NT) void k_copy(double *dst, const double *src, long long n) {
+__global__ __launch_bounds__(NT) void k_copy(double *dst, const double *src, long long n, long long pstride,
+                                             const int *gate) {
+    const long long off = (long long)blockIdx.y * pstride;
+    if (gated_off(shp(gate, off))) return;
+    dst = shp(dst, off);
+    src = shp(src, off);
     for (long long i = (long long)blockIdx.x * NT + threadIdx.x; i < n; i += (long long)gridDim.x * NT) dst[i] = src[i];
 }
 
-void launch_copy(double *dst, const double *src, long long count, hipStream_t s) {
+void launch_copy(double *dst, const double *src, long long count, hipStream_t s, int nprob, long long pstride,
+                 const int *gate) {
     const long long nb = std::min<long long>(ceil_div(count, NT), 8192);
-    hipLaunchKernelGGL(k_copy, dim3((unsigned)nb), dim3(NT), 0, s, dst, src, count);
+    hipLaunchKernelGGL(k_copy, dim3((unsigned)nb, (unsigned)nprob), dim3(NT), 0, s, dst, src, count, pstride, gate);
     check_launch("copy");
 }
 

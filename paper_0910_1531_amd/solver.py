@@ -191,3 +191,75 @@ def from_problem(prob, precision=_abi.DFT_FP64, device="cuda", flags=0):
     p = make_params(prob.n, prob.h, prob.radius, prob.valence, prob.rho_bulk, prob.bjerrum, prob.electrostatics,
                     precision, 0.0 if prob.eta_cap == 0.9 else prob.eta_cap, flags)
     return Solver(p, prob.beta_vext, prob.fixed_charge, device=device)
+
+
+class Batch:
+    """dft_setup_batch ... dft_batch_destroy: many state points solved together."""
+
+    def __init__(self, problems, precision=_abi.DFT_FP64, device="cuda", flags=0, stream=None):
+        self.lib = _abi.load()
+        self.device = torch.device(device)
+        if self.device.type == "cuda" and self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        n = len(problems)
+        self.count = n
+        self.params = (_abi.Params * n)()
+        self.shapes = []
+        self._keep = []
+        vext = (ctypes.c_void_p * n)()
+        qfix = (ctypes.c_void_p * n)()
+        for i, prob in enumerate(problems):
+            p = make_params(prob.n, prob.h, prob.radius, prob.valence, prob.rho_bulk, prob.bjerrum,
+                            prob.electrostatics, precision, 0.0 if prob.eta_cap == 0.9 else prob.eta_cap, flags)
+            self.params[i] = p
+            nx, ny, nz = prob.n
+            shape = (len(prob.radius), nz, ny, nx)
+            self.shapes.append(shape)
+            v = _dev(prob.beta_vext, shape, self.device)
+            q = _dev(prob.fixed_charge, (nz, ny, nx), self.device)
+            self._keep += [v, q]
+            vext[i] = v.data_ptr() if v is not None else None
+            qfix[i] = q.data_ptr() if q is not None else None
+        nbytes = ctypes.c_size_t()
+        _abi.check(self.lib.dft_batch_workspace_size(self.params, n, ctypes.byref(nbytes)), "dft_batch_workspace_size")
+        self.ws = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        _abi.check(self.lib.dft_setup_batch(self.params, n, vext, qfix, _ptr(self.ws), self.ws.numel(),
+                                            ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)),
+                   "dft_setup_batch")
+        self.handle = h
+
+    def solve(self, rhos, tol, max_iter=10000, raise_on_fail=False):
+        """dft_solve_batch: in place; returns (iters, norms, statuses) lists."""
+        n = self.count
+        for rho, shape in zip(rhos, self.shapes):
+            if rho.dtype != torch.float64 or rho.device != self.device or not rho.is_contiguous() \
+                    or tuple(rho.shape) != shape:
+                raise ValueError("each rho must be a contiguous float64 device tensor of its point's shape")
+        ptrs = (ctypes.c_void_p * n)(*[r.data_ptr() for r in rhos])
+        it = (ctypes.c_int32 * n)()
+        nr = (ctypes.c_double * n)()
+        st = (ctypes.c_int32 * n)()
+        s = self.lib.dft_solve_batch(self.handle, ptrs, float(tol), int(max_iter), it, nr, st)
+        if raise_on_fail:
+            _abi.check(s, "dft_solve_batch")
+        return list(it), list(nr), list(st)
+
+    def stats(self, i):
+        c = ctypes.c_void_p()
+        _abi.check(self.lib.dft_batch_member(self.handle, int(i), ctypes.byref(c)), "dft_batch_member")
+        s = _abi.Stats()
+        _abi.check(self.lib.dft_get_stats(c, ctypes.byref(s)), "dft_get_stats")
+        return {k: getattr(s, k) for k, _ in _abi.Stats._fields_}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.dft_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
