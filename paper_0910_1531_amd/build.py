@@ -16,7 +16,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libdftpicard.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
-SOURCES = ["dft_host.cpp", "dft_kernels.hip", "dft_adjoint.hip", "dft_api.hip"]
+SOURCES = ["dft_host.cpp", "dft_kernels.hip", "dft_kernels_ct.hip", "dft_adjoint.hip", "dft_api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

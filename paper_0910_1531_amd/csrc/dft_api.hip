@@ -483,6 +483,7 @@ dft_status dft_setup(const dft_params *params, const double *beta_vext, const do
         g.nz = params->n[2];
         g.Kx = c->hc.Kx;
         g.S = params->nspecies;
+        g.es = c->hc.es;
         g.N = c->hc.N;
         g.NC = c->hc.NC;
         DevPlan *dp[3] = {&g.px, &g.py, &g.pz};

@@ -218,10 +218,11 @@ __device__ __forceinline__ void sincos_r(double y, double *s, double *c) { sinco
 __device__ __forceinline__ void sincos_r(float y, float *s, float *c) { sincosf(y, s, c); }
 
 // Weight transforms of a sphere of radius R at |k| (Appendix B):
-//   w2 = 4 pi R sin(kR) / k,   w3 = 4 pi (sin kR - kR cos kR) / k^3.
+//   w2 = 4 pi R sin(kR) / k,   w3 = 4 pi (sin kR - kR cos kR) / k^3,
+// given s = sin(kR) and c = cos(kR) (used only for kR >= 1; the series covers kR < 1).
 // R is the arithmetic type (double for FP64 evaluations, float for FP32 differences).
 template <typename R>
-__device__ __forceinline__ void weight_w2_w3(R k, R Rad, R &w2, R &w3) {
+__device__ __forceinline__ void weight_w2_w3_sc(R k, R Rad, R s, R c, R &w2, R &w3) {
     const R y = k * Rad;
     const R R2 = Rad * Rad;
     if (y < R(1)) {
@@ -231,18 +232,24 @@ __device__ __forceinline__ void weight_w2_w3(R k, R Rad, R &w2, R &w3) {
         w2 = R(kFourPi) * R2 * horner_y2<R>(s0, y2);
         w3 = R(kFourPi) * R2 * Rad * horner_y2<R>(s3, y2);
     } else {
-        R s, c;
-        sincos_r(y, &s, &c);
         const R iy = R(1) / y;
         w2 = R(kFourPi) * R2 * s * iy;
         w3 = R(kFourPi) * R2 * Rad * (s - y * c) * iy * iy * iy;
     }
 }
 
-// Bulk-fluid kernel transform for one pair: c1 F1 + c0 F0 + cm1 Fm1 with
-// F_m = integral over |r| <= Rc of r^m exp(-i k.r) = (4 pi / k) I_m(Rc, k).
 template <typename R>
-__device__ __forceinline__ R screening_hat(R k, R Rc, R c1, R c0, R cm1) {
+__device__ __forceinline__ void weight_w2_w3(R k, R Rad, R &w2, R &w3) {
+    R s = R(0), c = R(1);
+    if (k * Rad >= R(1)) sincos_r(k * Rad, &s, &c);
+    weight_w2_w3_sc<R>(k, Rad, s, c, w2, w3);
+}
+
+// Bulk-fluid kernel transform for one pair: c1 F1 + c0 F0 + cm1 Fm1 with
+// F_m = integral over |r| <= Rc of r^m exp(-i k.r) = (4 pi / k) I_m(Rc, k),
+// given s = sin(k Rc), c = cos(k Rc) (used for k Rc >= 1).
+template <typename R>
+__device__ __forceinline__ R screening_hat_sc(R k, R Rc, R s, R c, R c1, R c0, R cm1) {
     const R y = k * Rc;
     const R R2 = Rc * Rc;
     R Fm1, F0, F1;
@@ -255,8 +262,6 @@ __device__ __forceinline__ R screening_hat(R k, R Rc, R c1, R c0, R cm1) {
         F0 = R(kFourPi) * R2 * Rc * horner_y2<R>(s0, y2);
         F1 = R(kFourPi) * R2 * R2 * horner_y2<R>(s1, y2);
     } else {
-        R s, c;
-        sincos_r(y, &s, &c);
         const R omc = (c > R(0)) ? s * s / (R(1) + c) : R(1) - c;   // 1 - cos y without cancellation
         const R iy = R(1) / y, iy2 = iy * iy;
         Fm1 = R(kFourPi) * R2 * omc * iy2;
@@ -264,6 +269,19 @@ __device__ __forceinline__ R screening_hat(R k, R Rc, R c1, R c0, R cm1) {
         F1 = R(kFourPi) * R2 * R2 * (-c * iy2 + R(2) * s * iy2 * iy - R(2) * omc * iy2 * iy2);
     }
     return c1 * F1 + c0 * F0 + cm1 * Fm1;
+}
+
+template <typename R>
+__device__ __forceinline__ R screening_hat(R k, R Rc, R c1, R c0, R cm1) {
+    R s = R(0), c = R(1);
+    if (k * Rc >= R(1)) sincos_r(k * Rc, &s, &c);
+    return screening_hat_sc<R>(k, Rc, s, c, c1, c0, cm1);
+}
+
+// 2 (1 - cos t) = 4 sin^2(t / 2) from (cos t, +-sin t) without cancellation.
+template <typename R>
+__device__ __forceinline__ R two_omc(R c, R s) {
+    return (c > R(0)) ? R(2) * s * s / (R(1) + c) : R(2) * (R(1) - c);
 }
 
 // Eigenvalue of minus the 7-point Laplacian for wavenumber components kd.

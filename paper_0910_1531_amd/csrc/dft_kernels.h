@@ -32,6 +32,7 @@ struct Geo {
     const void *tw64[3];   // cx<double> tables per axis
     const void *tw32[3];   // cx<float> tables per axis
     int nx, ny, nz, Kx, S;
+    int es;                // electrostatics on (mirrors Consts::es for launch choices)
     long long N, NC;
     // Batches of identically shaped problems: the kernels of one launch cover nprob
     // problems whose workspaces sit pstride bytes apart (blockIdx.z carries the problem).
@@ -122,6 +123,10 @@ struct X3Args {
 // Launchers (precision T = double or float of the transforms).
 template <typename T> void launch_x_forward(const Geo &g, const XFwdArgs &a, hipStream_t s);
 template <typename T> void launch_y(const Geo &g, const YArgs &a, hipStream_t s);
+// Compiled-length variants (dft_kernels_ct.hip); false when the length has none.
+template <typename T> bool launch_y_ct(const Geo &g, const YArgs &a, hipStream_t s);
+template <typename T> bool launch_z1_ct(const Geo &g, const Z1Args &a, int es, hipStream_t s);
+template <typename T> bool launch_z2_ct(const Geo &g, const Z2Args &a, hipStream_t s);
 template <typename T> void launch_z1(const Geo &g, const Z1Args &a, hipStream_t s);
 template <typename T> void launch_z2(const Geo &g, const Z2Args &a, hipStream_t s);
 template <typename T> void launch_x2(const Geo &g, const X2Args &a, hipStream_t s);

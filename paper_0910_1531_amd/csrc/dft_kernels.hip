@@ -17,6 +17,7 @@
 // applied in the z passes.  Transforms are LDS-staged mixed-radix Stockham FFTs over
 // tiles of pencils whose global accesses are contiguous along x.
 #include "dft_kernels.h"
+#include "pass_util.h"
 
 #include <cmath>
 #include <cstdio>
@@ -34,75 +35,6 @@ template <> struct Cfg<double> {
 template <> struct Cfg<float> {
     static constexpr int XE = 16, X2E = 4, YE = 16, ZE = 4, WMAX = 16;
 };
-
-template <typename T> __device__ __forceinline__ const cx<T> *twp(const Geo &g, int axis);
-template <> __device__ __forceinline__ const cx<double> *twp<double>(const Geo &g, int axis) {
-    return reinterpret_cast<const cx<double> *>(g.tw64[axis]);
-}
-template <> __device__ __forceinline__ const cx<float> *twp<float>(const Geo &g, int axis) {
-    return reinterpret_cast<const cx<float> *>(g.tw32[axis]);
-}
-
-__device__ __forceinline__ bool gated_off(const int *gate) { return gate != nullptr && *gate == 0; }
-
-// ------------------------------------------------------------------ batches
-// Pointers of problem `prob` of a batch: every workspace pointer moves by prob * pstride.
-template <typename P>
-__device__ __forceinline__ P *shp(P *ptr, long long off) {
-    return ptr ? reinterpret_cast<P *>(reinterpret_cast<char *>(const_cast<typename std::remove_const<P>::type *>(ptr)) + off)
-               : nullptr;
-}
-__device__ __forceinline__ RedBufs shift(RedBufs r, long long o) {
-    r.fpart = shp(r.fpart, o); r.mpart = shp(r.mpart, o); r.fflag = shp(r.fflag, o); r.mflag = shp(r.mflag, o);
-    return r;
-}
-__device__ __forceinline__ XFwdArgs shift(XFwdArgs a, long long o) {
-    a.src = shp(a.src, o); a.g0 = shp(a.g0, o); a.alpha = shp(a.alpha, o); a.rho_t = shp(a.rho_t, o);
-    a.ref = shp(a.ref, o); a.spec = shp(a.spec, o); a.gate = shp(a.gate, o);
-    return a;
-}
-__device__ __forceinline__ YArgs shift(YArgs a, long long o) {
-    a.spec = shp(a.spec, o); a.gate = shp(a.gate, o);
-    return a;
-}
-__device__ __forceinline__ Z1Args shift(Z1Args a, long long o) {
-    a.specA = shp(a.specA, o); a.specB = shp(a.specB, o); a.gate = shp(a.gate, o);
-    return a;
-}
-__device__ __forceinline__ Z2Args shift(Z2Args a, long long o) {
-    a.specA = shp(a.specA, o); a.specB = shp(a.specB, o); a.gate = shp(a.gate, o);
-    return a;
-}
-__device__ __forceinline__ X2Args shift(X2Args a, long long o) {
-    a.specB = shp(a.specB, o); a.nref = shp(a.nref, o); a.nref_out = shp(a.nref_out, o);
-    a.n_out = shp(a.n_out, o); a.dphi_out = shp(a.dphi_out, o); a.nstar = shp(a.nstar, o);
-    a.t_out = shp(a.t_out, o); a.red = shift(a.red, o); a.gate = shp(a.gate, o);
-    return a;
-}
-__device__ __forceinline__ X3Args shift(X3Args a, long long o) {
-    a.specA = shp(a.specA, o); a.addend = shp(a.addend, o); a.raw_out = shp(a.raw_out, o);
-    a.base = shp(a.base, o); a.rho_t = shp(a.rho_t, o); a.g_out = shp(a.g_out, o); a.e_out = shp(a.e_out, o);
-    a.e_phi = shp(a.e_phi, o); a.lp_out = shp(a.lp_out, o); a.red = shift(a.red, o); a.gate = shp(a.gate, o);
-    return a;
-}
-// Geometry of problem `prob`: its constants move with its workspace; twiddles are shared.
-__device__ __forceinline__ Geo shift(Geo g, long long o) {
-    g.cs = shp(g.cs, o);
-    return g;
-}
-
-// Block coordinates with consecutive column chunks kept on one XCD: blocks are dispatched
-// round-robin over the 8 XCDs by linear id, so linear ids are regrouped into 8 contiguous
-// runs (when the grid divides evenly) and neighbouring chunks share an L2.
-__device__ __forceinline__ void xcd_block(int &bx, int &by) {
-    const int gx = gridDim.x, gy = gridDim.y;
-    const int B = gx * gy;
-    int l = blockIdx.x + gx * blockIdx.y;
-    if ((B & 7) == 0) l = (l & 7) * (B >> 3) + (l >> 3);
-    bx = l % gx;
-    by = l / gx;
-}
-
 
 // --------------------------------------------------------------------- block reductions
 __device__ __forceinline__ double wave_sum(double v) {
@@ -913,6 +845,7 @@ void launch_y(const Geo &g, const YArgs &a, hipStream_t s) {
     const bool zax = a.axis == 2;
     const int L = zax ? g.nz : g.ny;
     if (L == 1) return;   // a length-1 transform is the identity
+    if (launch_y_ct<T>(g, a, s)) return;
     constexpr int E = Cfg<T>::YE;
     const int W = yz_width<T, E>(L, g.Kx);
     dim3 grid((unsigned)ceil_div(g.Kx, W), (unsigned)(zax ? g.ny : g.nz), (unsigned)(a.nfield * g.nprob));
@@ -923,6 +856,7 @@ void launch_y(const Geo &g, const YArgs &a, hipStream_t s) {
 
 template <typename T>
 void launch_z1(const Geo &g, const Z1Args &a, hipStream_t s) {
+    if (launch_z1_ct<T>(g, a, g.es && !a.n3only, s)) return;
     constexpr int E = Cfg<T>::ZE;
     const int W = yz_width<T, E>(g.nz, g.Kx);
     dim3 grid((unsigned)ceil_div(g.Kx, W), (unsigned)g.ny, (unsigned)g.nprob);
@@ -936,6 +870,7 @@ void launch_z1(const Geo &g, const Z1Args &a, hipStream_t s) {
 
 template <typename T>
 void launch_z2(const Geo &g, const Z2Args &a, hipStream_t s) {
+    if (launch_z2_ct<T>(g, a, s)) return;
     constexpr int E = Cfg<T>::ZE;
     const int W = yz_width<T, E>(g.nz, g.Kx);
     dim3 grid((unsigned)ceil_div(g.Kx, W), (unsigned)g.ny, (unsigned)g.nprob);

@@ -1,0 +1,513 @@
+// Pass kernels with the transform length fixed at compile time (fft_ct.h), for the
+// lengths listed in ct::Plan.  They compute the same transforms as the run-time-length
+// kernels with the same radix order, so results agree to rounding.
+#include "dft_kernels.h"
+#include "fft_ct.h"
+#include "pass_util.h"
+
+#include <stdexcept>
+#include <string>
+#include <type_traits>
+
+namespace dft {
+
+namespace {
+
+void check(const char *what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) throw std::runtime_error(std::string(what) + ": " + hipGetErrorString(e));
+}
+
+long long cdiv(long long a, long long b) { return (a + b - 1) / b; }
+
+}  // namespace
+
+// Threads per block: a power of two in [64, cap] near L P / per (per = values per thread).
+constexpr int fit_threads(int L, int P, int per, int cap) {
+    int t = 64;
+    while (2 * t <= cap && 2 * t * per <= L * P) t *= 2;
+    return t;
+}
+
+
+// ------------------------------------------------------------------ y / z plain transforms
+// One block transforms P adjacent columns (kx) of one field along y (one z plane) or z
+// (one y line); the pencils' elements sit rs apart in HBM and P columns are contiguous.
+template <typename T, int L, int P, int NTB, int NB>
+__global__ __launch_bounds__(NTB) void k_yc(Geo g_in, YArgs a) {
+    using F = ct::Fft<T, typename ct::Plan<L>::type, P, NTB, false, NB>;
+    const int prob = (int)blockIdx.z / a.nfield;
+    if (prob > 0) {
+        const long long off = (long long)prob * g_in.pstride;
+        g_in = shift(g_in, off);
+        a = shift(a, off);
+    }
+    const Geo &g = g_in;
+    if (gated_off(a.gate)) return;
+    __shared__ cx<T> lds[F::LDS_ELEMS];
+    const bool zax = a.axis == 2;
+    const int Kx = g.Kx;
+    int bx, o;
+    xcd_block(bx, o);
+    const int kx0 = bx * P;
+    const int Pact = min(P, Kx - kx0);
+    const int f = (int)blockIdx.z % a.nfield;
+    const long long rs = zax ? (long long)g.ny * Kx : (long long)Kx;
+    const long long ob = zax ? (long long)o * Kx : (long long)o * g.ny * Kx;
+    cx<T> *base = reinterpret_cast<cx<T> *>(a.spec) + (long long)f * g.NC + ob + kx0;
+    const cx<T> *tw = twp<T>(g, zax ? 2 : 1);
+    cx<T> v[F::V];
+    int ph = 0;
+    auto body = [&](auto dirc) {
+        constexpr int DIR = decltype(dirc)::value;
+#pragma unroll
+        for (int i = 0; i < F::template nin<DIR>(); ++i) {
+            int p, e;
+            const bool ok = F::template in_pos<DIR>(i, p, e);
+            v[i] = (ok && p < Pact) ? ct::gld(base + e * rs + p) : mk<T>(T(0), T(0));
+        }
+        F::template run<DIR>(v, lds, ph, tw);
+#pragma unroll
+        for (int i = 0; i < F::template nout<DIR>(); ++i) {
+            int p, e;
+            const bool ok = F::template out_pos<DIR>(i, p, e);
+            if (ok && p < Pact) ct::gst(base + e * rs + p, v[i]);
+        }
+    };
+    if (a.dir < 0) body(std::integral_constant<int, -1>());
+    else body(std::integral_constant<int, 1>());
+}
+
+// ------------------------------------------------------------------ z passes
+// Wavenumbers of the elements of one z tile: columns kx0 + p of the y row `y`, z index e.
+template <typename T>
+struct ZWave {
+    T dkx, dkz, ky;
+    int jx0, nx, nz;
+    bool yzero, ynyq;
+    __device__ ZWave(const Consts &c, int kx0, int y) {
+        dkx = T(c.dk[0]);
+        dkz = T(c.dk[2]);
+        const int my = signed_mode(y, c.ny);
+        ky = T(my) * T(c.dk[1]);
+        jx0 = kx0;
+        nx = c.nx;
+        nz = c.nz;
+        yzero = y == 0;
+        ynyq = (c.ny % 2 == 0) && (2 * y == c.ny);
+    }
+    __device__ T kx(int p) const { return T(jx0 + p) * dkx; }
+    __device__ T kz(int e) const { return T(signed_mode(e, nz)) * dkz; }
+    __device__ T kmag(int p, int e) const {
+        const T a = kx(p), b = kz(e);
+        return sqrt(a * a + ky * ky + b * b);
+    }
+    __device__ bool zero(int p, int e) const { return yzero && jx0 + p == 0 && e == 0; }
+    // component d of k, zero on the Nyquist plane of axis d
+    __device__ T comp(int p, int e, int d) const {
+        if (d == 0) return ((nx % 2 == 0) && 2 * (jx0 + p) == nx) ? T(0) : kx(p);
+        if (d == 1) return ynyq ? T(0) : ky;
+        return ((nz % 2 == 0) && 2 * e == nz) ? T(0) : kz(e);
+    }
+};
+
+// Eigenvalue of minus the 7-point Laplacian, sum_d 4 sin^2(k_d h_d / 2) / h_d^2, from the
+// twiddle tables: k_d h_d = 2 pi j_d / n_d, and tw_d[j] = exp(-2 pi i j / n_d).
+template <typename T>
+struct Poisson {
+    const cx<T> *tx, *tz;
+    T ih2x, ih2z, dy;
+    __device__ Poisson(const Geo &g, const Consts &c, int y) {
+        tx = twp<T>(g, 0);
+        tz = twp<T>(g, 2);
+        ih2x = T(1.0 / (c.h[0] * c.h[0]));
+        ih2z = T(1.0 / (c.h[2] * c.h[2]));
+        const cx<T> wy = ct::gld(twp<T>(g, 1) + y);
+        dy = two_omc<T>(wy.x, wy.y) * T(1.0 / (c.h[1] * c.h[1]));
+    }
+    __device__ T denom(int jx, int e) const {
+        const cx<T> wx = ct::gld(tx + jx), wz = ct::gld(tz + e);
+        return two_omc<T>(wx.x, wx.y) * ih2x + dy + two_omc<T>(wz.x, wz.y) * ih2z;
+    }
+};
+
+// Z1: forward z transform of every species, then per element
+//   (a) the five weighted sums of Appendix B spectra giving the ten n_alpha spectra (the
+//       vector spectra are -i k times a w3 sum), each inverse z transformed into specB;
+//   (b) with electrostatics (MS > 0 bounds S), per species i the linear electrostatic part
+//       of the exponent sum_j [C_ij(k) - z_i z_j 4 pi l_B / D(k)] (rho_hat_j - N rho_b_j
+//       delta_k0) (eqs. muESexpansion, potentialSolution), written unnormalized over
+//       rho_hat in specA (z spectral order).
+// The spectral products act on registers between the forward and inverse transforms.
+template <typename T, int L, int P, int NTB, int MS>
+__global__ __launch_bounds__(NTB) void k_z1c(Geo g_in, Z1Args a) {
+    using F = ct::Fft<T, typename ct::Plan<L>::type, P, NTB, false, 2>;
+    constexpr int NO = F::template nout<-1>();
+    static_assert(NO == F::template nin<1>(), "inverse must start where the forward ends");
+    constexpr int ME = MS > 0 ? MS : 1;
+    const int prob = (int)blockIdx.z;
+    if (prob > 0) {
+        const long long o = (long long)prob * g_in.pstride;
+        g_in = shift(g_in, o);
+        a = shift(a, o);
+    }
+    const Geo &g = g_in;
+    if (gated_off(a.gate)) return;
+    __shared__ cx<T> lds[F::LDS_ELEMS];
+    const Consts &c = *g.cs;
+    const int Kx = g.Kx, S = g.S;
+    int bx, y;
+    xcd_block(bx, y);
+    const int kx0 = bx * P;
+    const int Pact = min(P, Kx - kx0);
+    const long long rs = (long long)g.ny * Kx;
+    const long long off = (long long)y * Kx + kx0;
+    const cx<T> *tw = twp<T>(g, 2);
+    const bool es = MS > 0 && c.es && !a.n3only;
+    const ZWave<T> kw(c, kx0, y);
+    int pp[NO], ee[NO];
+    bool okk[NO];
+    T kmag[NO], invD[NO];
+    constexpr int MSC = MS > 0 ? MS : 1;
+    T sn[MSC][NO], cs[MSC][NO];   // sin, cos of k R_s (electrostatic kernels only)
+    {
+        const Poisson<T> pd(g, c, y);
+#pragma unroll
+        for (int i = 0; i < NO; ++i) {
+            okk[i] = F::template out_pos<-1>(i, pp[i], ee[i]) && pp[i] < Pact;
+            kmag[i] = kw.kmag(pp[i], ee[i]);
+            invD[i] = T(0);
+            if constexpr (MS > 0) {
+                if (es && !kw.zero(pp[i], ee[i])) invD[i] = T(c.four_pi_lB) / pd.denom(kx0 + pp[i], ee[i]);
+#pragma unroll
+                for (int is = 0; is < MS; ++is) {
+                    sn[is][i] = T(0);
+                    cs[is][i] = T(1);
+                    if (is < S) sincos_r(kmag[i] * T(c.R[is]), &sn[is][i], &cs[is][i]);
+                }
+            }
+        }
+    }
+    cx<T> acc[5][NO];
+    cx<T> esa[ME][NO];
+#pragma unroll
+    for (int i = 0; i < NO; ++i) {
+#pragma unroll
+        for (int m = 0; m < 5; ++m) acc[m][i] = mk<T>(T(0), T(0));
+#pragma unroll
+        for (int m = 0; m < ME; ++m) esa[m][i] = mk<T>(T(0), T(0));
+    }
+    cx<T> v[F::V];
+    int ph = 0;
+    for (int jsp = 0; jsp < S; ++jsp) {
+        const cx<T> *src = reinterpret_cast<const cx<T> *>(a.specA) + (long long)jsp * g.NC + off;
+#pragma unroll
+        for (int i = 0; i < F::template nin<-1>(); ++i) {
+            int p, e;
+            const bool ok = F::template in_pos<-1>(i, p, e);
+            v[i] = (ok && p < Pact) ? ct::gld(src + e * rs + p) : mk<T>(T(0), T(0));
+        }
+        F::template run<-1>(v, lds, ph, tw);
+        const T Rj = T(c.R[jsp]), a0 = T(c.i4piR2[jsp]), a1 = T(c.i4piR[jsp]);
+        const T bath = T((double)c.N * c.rho_b[jsp]);
+#pragma unroll
+        for (int i = 0; i < NO; ++i) {
+            const cx<T> u = v[i];
+            T w2, w3;
+            if constexpr (MS > 0) {
+                // sin, cos of k R_j picked with constant register indices
+                T sj = sn[0][i], cj = cs[0][i];
+#pragma unroll
+                for (int is = 1; is < MS; ++is)
+                    if (is == jsp) { sj = sn[is][i]; cj = cs[is][i]; }
+                weight_w2_w3_sc<T>(kmag[i], Rj, sj, cj, w2, w3);
+                if (es) {
+                    T ux = u.x;
+                    if (!a.diff && kw.zero(pp[i], ee[i])) ux -= bath;
+#pragma unroll
+                    for (int is = 0; is < MS; ++is) {
+                        if (is < S) {
+                            // sin, cos of k (R_i + R_j) by the addition theorem
+                            const T sp = sn[is][i] * cj + cs[is][i] * sj;
+                            const T cp = cs[is][i] * cj - sn[is][i] * sj;
+                            const int ij = is * DFT_MAX_SPECIES + jsp;
+                            const T C = screening_hat_sc<T>(kmag[i], T(c.sc_R[ij]), sp, cp, T(c.sc_c1[ij]),
+                                                            T(c.sc_c0[ij]), T(c.sc_cm1[ij]));
+                            const T Pz = invD[i] * T(c.z[is] * c.z[jsp]);
+                            esa[is][i].x += C * ux - Pz * u.x;
+                            esa[is][i].y += (C - Pz) * u.y;
+                        }
+                    }
+                }
+            } else {
+                weight_w2_w3<T>(kmag[i], Rj, w2, w3);
+            }
+            const T m0 = w2 * a0, m1 = w2 * a1, m4 = w3 * a1;
+            acc[0][i].x += u.x * m0; acc[0][i].y += u.y * m0;
+            acc[1][i].x += u.x * m1; acc[1][i].y += u.y * m1;
+            acc[2][i].x += u.x * w2; acc[2][i].y += u.y * w2;
+            acc[3][i].x += u.x * w3; acc[3][i].y += u.y * w3;
+            acc[4][i].x += u.x * m4; acc[4][i].y += u.y * m4;
+        }
+    }
+    if constexpr (MS > 0) {
+        if (es) {
+#pragma unroll
+            for (int is = 0; is < MS; ++is) {
+                if (is >= S) break;
+                cx<T> *dst = reinterpret_cast<cx<T> *>(a.specA) + (long long)is * g.NC + off;
+#pragma unroll
+                for (int i = 0; i < NO; ++i)
+                    if (okk[i]) ct::gst(dst + ee[i] * rs + pp[i], esa[is][i]);
+            }
+        }
+    }
+    const int nout = a.n3only ? 1 : DFT_NALPHA;
+    const T invN = T(c.invN);
+    for (int o = 0; o < nout; ++o) {
+        const int alpha = a.n3only ? 3 : o;
+#pragma unroll
+        for (int i = 0; i < NO; ++i) {
+            // source sum selected with compile-time register indices
+            cx<T> s = acc[3][i];
+#pragma unroll
+            for (int m = 0; m < 5; ++m) {
+                const bool pick = (alpha < 4) ? (m == alpha) : (m == (alpha < 7 ? 4 : 3));
+                if (pick) s = acc[m][i];
+            }
+            cx<T> r = s;
+            if (alpha >= 4) {
+                const int d = (alpha - 4) % 3;
+                const T kd = kw.comp(pp[i], ee[i], d);
+                r = mk<T>(kd * s.y, -kd * s.x);   // -i k_d s
+            }
+            v[i] = mk<T>(r.x * invN, r.y * invN);
+        }
+        F::template run<1>(v, lds, ph, tw);
+        cx<T> *dst = reinterpret_cast<cx<T> *>(a.specB) + (long long)o * g.NC + off;
+#pragma unroll
+        for (int i = 0; i < F::template nout<1>(); ++i) {
+            int p, e;
+            const bool ok = F::template out_pos<1>(i, p, e);
+            if (ok && p < Pact) ct::gst(dst + e * rs + p, v[i]);
+        }
+    }
+}
+
+// Z2: forward z transform of the ten dPhi/dn spectra, back-convolution with conj(w_hat)
+// (eq. muHS; the vector parts enter as +i k_d times a w3 weight), plus the electrostatic
+// spectra Z1 left in specA, times 1/N, inverse z -> specA.  Z2_POISSON instead forms the
+// potential of weighted source spectra.
+template <typename T, int L, int P, int NTB>
+__global__ __launch_bounds__(NTB) void k_z2c(Geo g_in, Z2Args a) {
+    using F = ct::Fft<T, typename ct::Plan<L>::type, P, NTB, false, 2>;
+    constexpr int NO = F::template nout<-1>();
+    static_assert(NO == F::template nin<1>(), "inverse must start where the forward ends");
+    const int prob = (int)blockIdx.z;
+    if (prob > 0) {
+        const long long o = (long long)prob * g_in.pstride;
+        g_in = shift(g_in, o);
+        a = shift(a, o);
+    }
+    const Geo &g = g_in;
+    if (gated_off(a.gate)) return;
+    __shared__ cx<T> lds[F::LDS_ELEMS];
+    const Consts &c = *g.cs;
+    const int Kx = g.Kx, S = g.S;
+    int bx, y;
+    xcd_block(bx, y);
+    const int kx0 = bx * P;
+    const int Pact = min(P, Kx - kx0);
+    const long long rs = (long long)g.ny * Kx;
+    const long long off = (long long)y * Kx + kx0;
+    const cx<T> *tw = twp<T>(g, 2);
+    const ZWave<T> kw(c, kx0, y);
+    int pp[NO], ee[NO];
+    bool okk[NO];
+#pragma unroll
+    for (int i = 0; i < NO; ++i) okk[i] = F::template out_pos<-1>(i, pp[i], ee[i]) && pp[i] < Pact;
+    cx<T> v[F::V];
+    int ph = 0;
+    auto load_fwd = [&](const cx<T> *src) {
+#pragma unroll
+        for (int i = 0; i < F::template nin<-1>(); ++i) {
+            int p, e;
+            const bool ok = F::template in_pos<-1>(i, p, e);
+            v[i] = (ok && p < Pact) ? ct::gld(src + e * rs + p) : mk<T>(T(0), T(0));
+        }
+        F::template run<-1>(v, lds, ph, tw);
+    };
+    auto inv_store = [&](cx<T> *dst) {
+        F::template run<1>(v, lds, ph, tw);
+#pragma unroll
+        for (int i = 0; i < F::template nout<1>(); ++i) {
+            int p, e;
+            const bool ok = F::template out_pos<1>(i, p, e);
+            if (ok && p < Pact) ct::gst(dst + e * rs + p, v[i]);
+        }
+    };
+
+    if (a.mode == Z2_POISSON) {
+        // phi_hat = 4 pi l_B (sum_j w_j src_j) / D(k), zero mode 0; x invN; output in specA[0].
+        double acc[NO][2];
+#pragma unroll
+        for (int i = 0; i < NO; ++i) acc[i][0] = acc[i][1] = 0.0;
+        for (int is = 0; is < a.nsrc; ++is) {
+            load_fwd(reinterpret_cast<const cx<T> *>(a.specA) + (long long)is * g.NC + off);
+            double wj = 0.0;   // a.wsrc[is] read with constant indices (no scratch copy of the arguments)
+#pragma unroll
+            for (int k = 0; k < DFT_MAX_SPECIES; ++k)
+                if (k == is) wj = a.wsrc[k];
+#pragma unroll
+            for (int i = 0; i < NO; ++i) {
+                acc[i][0] += wj * (double)v[i].x;
+                acc[i][1] += wj * (double)v[i].y;
+            }
+        }
+        const Poisson<double> pd(g, c, y);
+#pragma unroll
+        for (int i = 0; i < NO; ++i) {
+            double m = 0.0;
+            if (!kw.zero(pp[i], ee[i])) m = c.four_pi_lB / pd.denom(kx0 + pp[i], ee[i]) * c.invN;
+            v[i] = mk<T>(T(acc[i][0] * m), T(acc[i][1] * m));
+        }
+        inv_store(reinterpret_cast<cx<T> *>(a.specA) + off);
+        return;
+    }
+
+    // six sums of the derivative spectra: u0..u3 and v1 = sum_d i k_d dPhi_V1,d, v2 likewise
+    cx<T> u[6][NO];
+#pragma unroll
+    for (int m = 0; m < 6; ++m)
+#pragma unroll
+        for (int i = 0; i < NO; ++i) u[m][i] = mk<T>(T(0), T(0));
+    for (int al = 0; al < DFT_NALPHA; ++al) {
+        load_fwd(reinterpret_cast<const cx<T> *>(a.specB) + (long long)al * g.NC + off);
+        const int m = al < 4 ? al : (al < 7 ? 4 : 5);
+        const int d = al < 4 ? 0 : (al - 4) % 3;
+#pragma unroll
+        for (int i = 0; i < NO; ++i) {
+            cx<T> t = v[i];
+            if (al >= 4) {
+                const T kd = kw.comp(pp[i], ee[i], d);
+                t = mk<T>(-kd * t.y, kd * t.x);   // + i k_d t
+            }
+#pragma unroll
+            for (int mm = 0; mm < 6; ++mm)
+                if (mm == m) { u[mm][i].x += t.x; u[mm][i].y += t.y; }
+        }
+    }
+    const T invN = T(c.invN);
+    T kmag[NO];
+#pragma unroll
+    for (int i = 0; i < NO; ++i) kmag[i] = kw.kmag(pp[i], ee[i]);
+    for (int is = 0; is < S; ++is) {
+        const T Ri = T(c.R[is]), a0 = T(c.i4piR2[is]), a1 = T(c.i4piR[is]);
+        const cx<T> *esrc = reinterpret_cast<const cx<T> *>(a.specA) + (long long)is * g.NC + off;
+#pragma unroll
+        for (int i = 0; i < NO; ++i) {
+            T w2, w3;
+            weight_w2_w3<T>(kmag[i], Ri, w2, w3);
+            const T s2x = u[0][i].x * a0 + u[1][i].x * a1 + u[2][i].x;
+            const T s2y = u[0][i].y * a0 + u[1][i].y * a1 + u[2][i].y;
+            const T s3x = u[3][i].x + u[4][i].x * a1 + u[5][i].x;
+            const T s3y = u[3][i].y + u[4][i].y * a1 + u[5][i].y;
+            T ex = -(s2x * w2 + s3x * w3);
+            T ey = -(s2y * w2 + s3y * w3);
+            if (c.es && okk[i]) {
+                const cx<T> ev = ct::gld(esrc + ee[i] * rs + pp[i]);
+                ex += ev.x;
+                ey += ev.y;
+            }
+            v[i] = mk<T>(ex * invN, ey * invN);
+        }
+        inv_store(reinterpret_cast<cx<T> *>(a.specA) + (long long)is * g.NC + off);
+    }
+}
+
+// Launch shapes: P columns per tile, NTB threads.
+template <typename T> struct ZShape;
+template <> struct ZShape<float> { static constexpr int P = 8, CAP = 512; };
+template <> struct ZShape<double> { static constexpr int P = 4, CAP = 256; };
+
+template <typename T, int L>
+static void launch_z1c_len(const Geo &g, const Z1Args &a, int es, hipStream_t s) {
+    constexpr int P = ZShape<T>::P, NTB = fit_threads(L, P, 4, ZShape<T>::CAP);
+    dim3 grid((unsigned)cdiv(g.Kx, P), (unsigned)g.ny, (unsigned)g.nprob);
+    if (!es) hipLaunchKernelGGL((k_z1c<T, L, P, NTB, 0>), grid, dim3(NTB), 0, s, g, a);
+    else {
+        bool done = false;
+        if constexpr (std::is_same<T, float>::value) {
+            if (g.S <= 2) {
+                hipLaunchKernelGGL((k_z1c<T, L, P, NTB, 2>), grid, dim3(NTB), 0, s, g, a);
+                done = true;
+            }
+        }
+        if (!done) hipLaunchKernelGGL((k_z1c<T, L, P, NTB, 4>), grid, dim3(NTB), 0, s, g, a);
+    }
+    check("z1 (compiled length)");
+}
+
+template <typename T, int L>
+static void launch_z2c_len(const Geo &g, const Z2Args &a, hipStream_t s) {
+    constexpr int P = ZShape<T>::P, NTB = fit_threads(L, P, 4, ZShape<T>::CAP);
+    dim3 grid((unsigned)cdiv(g.Kx, P), (unsigned)g.ny, (unsigned)g.nprob);
+    hipLaunchKernelGGL((k_z2c<T, L, P, NTB>), grid, dim3(NTB), 0, s, g, a);
+    check("z2 (compiled length)");
+}
+
+#define DFT_CT_LENGTHS(X) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384)
+
+template <typename T>
+bool launch_z1_ct(const Geo &g, const Z1Args &a, int es, hipStream_t s) {
+    if (es && g.S > 4) return false;   // electrostatic sums of more species: run-time-length kernel
+    switch (g.nz) {
+#define DFT_CASE(n) case n: launch_z1c_len<T, n>(g, a, es, s); return true;
+        DFT_CT_LENGTHS(DFT_CASE)
+#undef DFT_CASE
+        default: return false;
+    }
+}
+
+template <typename T>
+bool launch_z2_ct(const Geo &g, const Z2Args &a, hipStream_t s) {
+    switch (g.nz) {
+#define DFT_CASE(n) case n: launch_z2c_len<T, n>(g, a, s); return true;
+        DFT_CT_LENGTHS(DFT_CASE)
+#undef DFT_CASE
+        default: return false;
+    }
+}
+
+template bool launch_z1_ct<double>(const Geo &, const Z1Args &, int, hipStream_t);
+template bool launch_z1_ct<float>(const Geo &, const Z1Args &, int, hipStream_t);
+template bool launch_z2_ct<double>(const Geo &, const Z2Args &, hipStream_t);
+template bool launch_z2_ct<float>(const Geo &, const Z2Args &, hipStream_t);
+
+template <typename T> struct YShape;
+template <> struct YShape<float> { static constexpr int P = 16, CAP = 256, NB = 2; };
+template <> struct YShape<double> { static constexpr int P = 8, CAP = 256, NB = 2; };
+
+template <typename T, int L>
+static void launch_yc_len(const Geo &g, const YArgs &a, hipStream_t s) {
+    constexpr int P = YShape<T>::P, NB = YShape<T>::NB, NTB = fit_threads(L, P, 8, YShape<T>::CAP);
+    const bool zax = a.axis == 2;
+    dim3 grid((unsigned)cdiv(g.Kx, P), (unsigned)(zax ? g.ny : g.nz), (unsigned)(a.nfield * g.nprob));
+    hipLaunchKernelGGL((k_yc<T, L, P, NTB, NB>), grid, dim3(NTB), 0, s, g, a);
+    check("y (compiled length)");
+}
+
+template <typename T>
+bool launch_y_ct(const Geo &g, const YArgs &a, hipStream_t s) {
+    switch (a.axis == 2 ? g.nz : g.ny) {
+#define DFT_CASE(n) case n: launch_yc_len<T, n>(g, a, s); return true;
+        DFT_CT_LENGTHS(DFT_CASE)
+#undef DFT_CASE
+        default: return false;
+    }
+}
+
+template bool launch_y_ct<double>(const Geo &, const YArgs &, hipStream_t);
+template bool launch_y_ct<float>(const Geo &, const YArgs &, hipStream_t);
+
+}  // namespace dft

@@ -1,0 +1,220 @@
+// Compile-time-length Stockham FFT over LDS tiles of pencils, for gfx950.
+//
+// A tile holds P pencils of length L.  Each thread owns whole butterflies: the stage of
+// radix R has L P / R butterflies spread over the NT threads of the block, and a thread
+// keeps the R values of each of its butterflies in registers.  Between stages the values
+// go through one of two LDS buffers used in turn, so each exchange needs one barrier.
+// The first stage takes its inputs from registers that the caller filled (straight from
+// HBM) and the last stage leaves its outputs in registers (stored straight to HBM), so a
+// transform costs (stages - 1) LDS round trips.  The inverse transform runs the radices
+// in reverse order: the positions a thread holds after the last forward stage are then the
+// positions the first inverse stage needs, and a kernel can apply a spectral product in
+// registers between a forward and an inverse transform.
+//
+// With L, P, NT and the radices fixed at compile time every index is a constant or a
+// shift, and the stage loop unrolls completely (no run-time plan, no scratch memory).
+#pragma once
+
+#include "dft_device.h"
+
+namespace dft {
+namespace ct {
+
+// ---------------------------------------------------------------- global-memory access
+// Loads and stores through the global address space (not flat), so LDS waits never wait
+// for HBM traffic.
+template <typename T> struct V2 { typedef T type __attribute__((ext_vector_type(2))); };
+
+template <typename T>
+__device__ __forceinline__ cx<T> gld(const cx<T> *p) {
+    typedef __attribute__((address_space(1))) const typename V2<T>::type *GP;
+    const typename V2<T>::type r = *(GP)p;
+    return mk<T>(r.x, r.y);
+}
+template <typename T>
+__device__ __forceinline__ void gst(cx<T> *p, cx<T> v) {
+    typedef __attribute__((address_space(1))) typename V2<T>::type *GP;
+    typename V2<T>::type r;
+    r.x = v.x;
+    r.y = v.y;
+    *(GP)p = r;
+}
+template <typename T>
+__device__ __forceinline__ T gld(const T *p) {
+    return *(__attribute__((address_space(1))) const T *)p;
+}
+template <typename T>
+__device__ __forceinline__ void gst(T *p, T v) {
+    *(__attribute__((address_space(1))) T *)p = v;
+}
+
+// ---------------------------------------------------------------- radix schedules
+// Radices in the order the forward transform runs them.
+template <int... Rs>
+struct Sched {
+    static constexpr int n = sizeof...(Rs);
+    static constexpr int L = (1 * ... * Rs);
+    static constexpr int r(int s) {
+        constexpr int a[] = {Rs...};
+        return a[s];
+    }
+};
+
+// ---------------------------------------------------------------- the engine
+// BF = false: the pencil index varies fastest over threads and in LDS (y and z tiles,
+// whose pencils are adjacent columns in HBM).  BF = true: the element index varies fastest
+// (x tiles, whose pencils are rows); PAD pads each pencil in LDS against bank conflicts.
+// NB = 2 alternates two LDS buffers (one barrier per exchange); NB = 1 uses one buffer and
+// a second barrier before each write.
+template <typename T, class SC, int P, int NT, bool BF, int NB = 2, int PAD = 0>
+struct Fft {
+    static constexpr int L = SC::L;
+    static constexpr int NSTG = SC::n;
+    static constexpr int LS = BF ? L + PAD : L;
+    static constexpr int TILE = BF ? P * (L + PAD) : L * P;   // LDS elements per buffer
+    static constexpr int LDS_ELEMS = NB * TILE;
+
+    template <int DIR>
+    static constexpr int rad(int s) { return DIR < 0 ? SC::r(s) : SC::r(NSTG - 1 - s); }
+    // product of the radices before stage s
+    template <int DIR>
+    static constexpr int span(int s) {
+        int m = 1;
+        for (int i = 0; i < s; ++i) m *= rad<DIR>(i);
+        return m;
+    }
+    static constexpr int items(int R) { return L * P / R; }
+    static constexpr int iters(int R) { return (items(R) + NT - 1) / NT; }
+    static constexpr bool exact(int R) { return items(R) % NT == 0; }
+    static constexpr int regs(int R) { return iters(R) * R; }
+    static constexpr int vmax() {
+        int m = 0;
+        for (int s = 0; s < NSTG; ++s) m = regs(SC::r(s)) > m ? regs(SC::r(s)) : m;
+        return m;
+    }
+    static constexpr int V = vmax();   // registers (complex values) per thread
+    template <int DIR> static constexpr int nin() { return regs(rad<DIR>(0)); }
+    template <int DIR> static constexpr int nout() { return regs(rad<DIR>(NSTG - 1)); }
+
+    // butterfly j of a radix-R stage -> pencil p and butterfly index b within the pencil
+    template <int R>
+    __device__ static __forceinline__ void decode(int j, int &p, int &b) {
+        constexpr int nb = L / R;
+        if constexpr (BF) {
+            p = j / nb;
+            b = j - p * nb;
+        } else {
+            b = j / P;
+            p = j - b * P;
+        }
+    }
+    __device__ static __forceinline__ int lidx(int p, int e) { return BF ? p * LS + e : e * P + p; }
+
+    // Pencil p and element e that register i holds as an input of a first stage (or an
+    // output of a last stage) of radix R; false for registers of idle butterflies.
+    template <int R>
+    __device__ static __forceinline__ bool pos(int i, int &p, int &e) {
+        const int it = i / R, q = i - (i / R) * R;
+        const int j = (int)threadIdx.x + it * NT;
+        int b;
+        decode<R>(j, p, b);
+        e = b + q * (L / R);
+        return exact(R) || j < items(R);
+    }
+    template <int DIR>
+    __device__ static __forceinline__ bool in_pos(int i, int &p, int &e) { return pos<rad<DIR>(0)>(i, p, e); }
+    template <int DIR>
+    __device__ static __forceinline__ bool out_pos(int i, int &p, int &e) {
+        return pos<rad<DIR>(NSTG - 1)>(i, p, e);
+    }
+
+    // Twiddles exp(DIR 2 pi i q k / (NS R)), k = b mod NS, then the radix-R butterflies.
+    // tw[m] = exp(-2 pi i m / L).
+    template <int DIR, int R, int NS>
+    __device__ static __forceinline__ void butterflies(cx<T> *v, const cx<T> *__restrict__ tw) {
+#pragma unroll
+        for (int it = 0; it < iters(R); ++it) {
+            cx<T> *u = v + it * R;
+            if constexpr (NS > 1) {
+                int p, b;
+                decode<R>((int)threadIdx.x + it * NT, p, b);
+                const int k = b % NS;
+                constexpr int ts = L / (NS * R);
+#pragma unroll
+                for (int q = 1; q < R; ++q) {
+                    cx<T> w = gld(tw + q * k * ts);
+                    if (DIR > 0) w.y = -w.y;
+                    u[q] = mul(u[q], w);
+                }
+            }
+            bfly<T, DIR, R>(u);
+        }
+    }
+
+    // Outputs of a radix-R stage with span NS to the buffer (Stockham order).
+    template <int R, int NS>
+    __device__ static __forceinline__ void put(const cx<T> *v, cx<T> *buf) {
+#pragma unroll
+        for (int it = 0; it < iters(R); ++it) {
+            const int j = (int)threadIdx.x + it * NT;
+            if (!exact(R) && j >= items(R)) continue;
+            int p, b;
+            decode<R>(j, p, b);
+            const int k = b % NS;
+            const int o = (b - k) * R + k;
+#pragma unroll
+            for (int q = 0; q < R; ++q) buf[lidx(p, o + q * NS)] = v[it * R + q];
+        }
+    }
+    // Inputs of a radix-R stage from the buffer.
+    template <int R>
+    __device__ static __forceinline__ void get(cx<T> *v, const cx<T> *buf) {
+#pragma unroll
+        for (int it = 0; it < iters(R); ++it) {
+            const int j = (int)threadIdx.x + it * NT;
+            if (!exact(R) && j >= items(R)) continue;
+            int p, b;
+            decode<R>(j, p, b);
+#pragma unroll
+            for (int q = 0; q < R; ++q) v[it * R + q] = buf[lidx(p, b + q * (L / R))];
+        }
+    }
+
+    // Whole transform (unnormalized; DIR = -1 forward, +1 inverse) of the values in v, which
+    // hold the first stage's inputs (in_pos) and end holding the outputs (out_pos).  ph is the
+    // caller's buffer phase; it must start at 0 and be passed to every call of the block.
+    template <int DIR, int S = 0>
+    __device__ static __forceinline__ void run(cx<T> *v, cx<T> *lds, int &ph, const cx<T> *__restrict__ tw) {
+        constexpr int R = rad<DIR>(S), NS = span<DIR>(S);
+        butterflies<DIR, R, NS>(v, tw);
+        if constexpr (S + 1 < NSTG) {
+            cx<T> *buf = lds;
+            if constexpr (NB == 2) {
+                buf = lds + (ph ? TILE : 0);
+                ph ^= 1;
+            } else {
+                __syncthreads();
+            }
+            put<R, NS>(v, buf);
+            __syncthreads();
+            get<rad<DIR>(S + 1)>(v, buf);
+            run<DIR, S + 1>(v, lds, ph, tw);
+        }
+    }
+};
+
+// Radix schedules of the lengths with compiled kernels (forward order).
+template <int L> struct Plan;
+template <> struct Plan<16> { using type = Sched<4, 4>; };
+template <> struct Plan<24> { using type = Sched<8, 3>; };
+template <> struct Plan<32> { using type = Sched<8, 4>; };
+template <> struct Plan<48> { using type = Sched<4, 4, 3>; };
+template <> struct Plan<64> { using type = Sched<8, 8>; };
+template <> struct Plan<96> { using type = Sched<8, 4, 3>; };
+template <> struct Plan<128> { using type = Sched<8, 4, 4>; };
+template <> struct Plan<192> { using type = Sched<8, 8, 3>; };
+template <> struct Plan<256> { using type = Sched<8, 8, 4>; };
+template <> struct Plan<384> { using type = Sched<8, 4, 4, 3>; };
+
+}  // namespace ct
+}  // namespace dft
