@@ -127,6 +127,8 @@ template <typename T> void launch_y(const Geo &g, const YArgs &a, hipStream_t s)
 template <typename T> bool launch_y_ct(const Geo &g, const YArgs &a, hipStream_t s);
 template <typename T> bool launch_z1_ct(const Geo &g, const Z1Args &a, int es, hipStream_t s);
 template <typename T> bool launch_z2_ct(const Geo &g, const Z2Args &a, hipStream_t s);
+template <typename T> bool launch_x2_ct(const Geo &g, const X2Args &a, hipStream_t s);
+int x_ct_pairs(int nx);   // row pairs per block of the compiled-length x kernels, 0 if none
 template <typename T> void launch_z1(const Geo &g, const Z1Args &a, hipStream_t s);
 template <typename T> void launch_z2(const Geo &g, const Z2Args &a, hipStream_t s);
 template <typename T> void launch_x2(const Geo &g, const X2Args &a, hipStream_t s);

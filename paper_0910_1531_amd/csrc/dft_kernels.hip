@@ -36,42 +36,6 @@ template <> struct Cfg<float> {
     static constexpr int XE = 16, X2E = 4, YE = 16, ZE = 4, WMAX = 16;
 };
 
-// --------------------------------------------------------------------- block reductions
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
-    return v;
-}
-__device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_down(v, o, 64));
-    return v;
-}
-__device__ __forceinline__ int wave_or(int v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v |= __shfl_down(v, o, 64);
-    return v;
-}
-
-// Fixed-order block reduction (sum or max) of one double and an OR of one int.
-template <bool MAX, int NTB>
-__device__ __forceinline__ void block_reduce_nt(double v, int fl, double *dst, int *fdst) {
-    __shared__ double sv[NTB / 64];
-    __shared__ int sf[NTB / 64];
-    v = MAX ? wave_max(v) : wave_sum(v);
-    fl = wave_or(fl);
-    const int w = threadIdx.x / 64, l = threadIdx.x % 64;
-    if (l == 0) { sv[w] = v; sf[w] = fl; }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double a = sv[0];
-        int f = sf[0];
-        for (int i = 1; i < NTB / 64; ++i) { a = MAX ? fmax(a, sv[i]) : a + sv[i]; f |= sf[i]; }
-        *dst = a;
-        *fdst = f;
-    }
-}
-
 template <bool MAX>
 __device__ __forceinline__ void block_reduce(double v, int fl, double *dst, int *fdst) {
     block_reduce_nt<MAX, NT>(v, fl, dst, fdst);
@@ -910,6 +874,7 @@ static bool x2b_geometry(const Geo &g, int *ntb, int *pb) {
 template <typename T>
 int x2_nblocks(const Geo &g) {
     const long long npairs = ((long long)g.ny * g.nz + 1) / 2;
+    if (const int pb = x_ct_pairs(g.nx)) return (int)ceil_div(npairs, pb);
     int ntb, pb;
     if (x2b_geometry<T>(g, &ntb, &pb)) return (int)ceil_div(npairs, pb);
     const int P = x_pairs<T, Cfg<T>::X2E>(g);
@@ -918,6 +883,7 @@ int x2_nblocks(const Geo &g) {
 
 template <typename T>
 void launch_x2(const Geo &g, const X2Args &a, hipStream_t s) {
+    if (launch_x2_ct<T>(g, a, s)) return;
     const long long npairs = ((long long)g.ny * g.nz + 1) / 2;
     int ntb, pb;
     if (x2b_geometry<T>(g, &ntb, &pb)) {

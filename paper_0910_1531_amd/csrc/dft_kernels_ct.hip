@@ -425,6 +425,149 @@ __global__ __launch_bounds__(NTB) void k_z2c(Geo g_in, Z2Args a) {
     }
 }
 
+// ------------------------------------------------------------------ x passes
+// Two real rows (r0, r0 + 1) travel as the real and imaginary parts of one complex row:
+// the forward transform C of c = a + i b gives A_k = (C_k + conj C_{L-k}) / 2 and
+// B_k = (C_k - conj C_{L-k}) / (2i); the inverse rebuilds C from the Hermitian halves.
+// A tile holds PB such row pairs; the block has PB L / 4 threads, and with the x schedules
+// (radices <= 4, forward starting with 4) each thread ends an inverse transform holding
+// the same four columns of its pencil for every field, so the nodewise work of X2 runs on
+// registers.
+template <int L>
+struct XTile {
+    static constexpr int PB = (L % 3 == 0) ? 768 / L : 1024 / L;
+    static constexpr int NTB = PB * L / 4;
+    static constexpr int KX = L / 2 + 1;
+    static constexpr int PAD = 1;
+};
+
+// Element e of the full spectrum of a real row from its half spectrum (Hermitian).
+template <typename T, int L>
+__device__ __forceinline__ cx<T> half_at(const cx<T> *row, int e) {
+    constexpr int KX = L / 2 + 1;
+    cx<T> v;
+    if (e < KX) {
+        v = ct::gld(row + e);
+        if (e == 0 || 2 * e == L) v.y = T(0);
+    } else {
+        v = conjg(ct::gld(row + (L - e)));
+    }
+    return v;
+}
+
+// X2: ten weighted-density spectra after the y inverse -> inverse x -> pointwise dPhi/dn
+// (eq. Phi) -> forward x -> half spectra, in place in specB.
+template <typename T, int L>
+__global__ __launch_bounds__(XTile<L>::NTB) void k_x2c(Geo g_in, X2Args a) {
+    using XT = XTile<L>;
+    constexpr int PB = XT::PB, NTB = XT::NTB, KX = XT::KX;
+    using F = ct::Fft<T, typename ct::XPlan<L>::type, PB, NTB, true, 2, XT::PAD>;
+    constexpr int NO = F::template nout<1>();
+    static_assert(NO == F::template nin<-1>(), "forward must start where the inverse ends");
+    const int prob = (int)blockIdx.z;
+    if (prob > 0) {
+        const long long o = (long long)prob * g_in.pstride;
+        g_in = shift(g_in, o);
+        a = shift(a, o);
+    }
+    const Geo &g = g_in;
+    if (gated_off(a.gate)) return;
+    __shared__ cx<T> lds[F::LDS_ELEMS + F::TILE];
+    cx<T> *split = lds + F::LDS_ELEMS;
+    const long long N = g.N, NC = g.NC;
+    const long long rows = (long long)g.ny * g.nz;
+    const long long npairs = (rows + 1) / 2;
+    const long long pair0 = (long long)blockIdx.x * PB;
+    const int Pact = (int)min((long long)PB, npairs - pair0);
+    const cx<T> *tw = twp<T>(g, 0);
+    const bool n3only = a.mode == X2_N3_ONLY;
+    const int nf = n3only ? 1 : DFT_NALPHA;
+    cx<T> vals[DFT_NALPHA][NO];
+    cx<T> v[F::V];
+    int ph = 0;
+#pragma unroll
+    for (int f = 0; f < DFT_NALPHA; ++f) {
+        if (f >= nf) continue;
+        const cx<T> *in = reinterpret_cast<const cx<T> *>(a.specB) + (long long)f * NC;
+#pragma unroll
+        for (int i = 0; i < F::template nin<1>(); ++i) {
+            int p, e;
+            const bool ok = F::template in_pos<1>(i, p, e) && p < Pact;
+            cx<T> c = mk<T>(T(0), T(0));
+            if (ok) {
+                const long long r0 = 2 * (pair0 + p);
+                const cx<T> A = half_at<T, L>(in + r0 * KX, e);
+                cx<T> B = mk<T>(T(0), T(0));
+                if (r0 + 1 < rows) B = half_at<T, L>(in + (r0 + 1) * KX, e);
+                c = mk<T>(A.x - B.y, A.y + B.x);
+            }
+            v[i] = c;
+        }
+        F::template run<1>(v, lds, ph, tw);
+#pragma unroll
+        for (int i = 0; i < NO; ++i) vals[f][i] = v[i];
+    }
+    double mloc = -INFINITY;
+    int flag = 0;
+#pragma unroll
+    for (int i = 0; i < NO; ++i) {
+        int p, e;
+        if (!(F::template out_pos<1>(i, p, e) && p < Pact)) continue;
+        const long long r0 = 2 * (pair0 + p);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const long long r = r0 + h;
+            if (r >= rows) break;
+            const long long idx = r * L + e;
+            if (n3only) {
+                double n3 = h == 0 ? (double)vals[0][i].x : (double)vals[0][i].y;
+                if (a.nref) n3 += (double)a.nref[3 * N + idx];
+                if (!isfinite(n3)) flag |= 1;
+                mloc = fmax(mloc, n3);
+                continue;
+            }
+            double n[DFT_NALPHA], d[DFT_NALPHA];
+#pragma unroll
+            for (int f = 0; f < DFT_NALPHA; ++f) n[f] = h == 0 ? (double)vals[f][i].x : (double)vals[f][i].y;
+            x2_node(a, N, idx, n, d, mloc, flag);
+#pragma unroll
+            for (int f = 0; f < DFT_NALPHA; ++f) {
+                if (h == 0) vals[f][i].x = T(d[f]);
+                else vals[f][i].y = T(d[f]);
+            }
+        }
+        if (!n3only && r0 + 1 >= rows) {
+            // the missing partner row transforms as zero
+#pragma unroll
+            for (int f = 0; f < DFT_NALPHA; ++f) vals[f][i].y = T(0);
+        }
+    }
+    if (flag & 1) mloc = INFINITY;
+    block_reduce_nt<true, NTB>(mloc, flag, a.red.mpart + blockIdx.x, a.red.mflag + blockIdx.x);
+    if (n3only) return;
+#pragma unroll
+    for (int f = 0; f < DFT_NALPHA; ++f) {
+#pragma unroll
+        for (int i = 0; i < NO; ++i) v[i] = vals[f][i];
+        F::template run<-1>(v, lds, ph, tw);
+#pragma unroll
+        for (int i = 0; i < F::template nout<-1>(); ++i) {
+            int p, e;
+            if (F::template out_pos<-1>(i, p, e)) split[F::lidx(p, e)] = v[i];
+        }
+        __syncthreads();
+        cx<T> *out = reinterpret_cast<cx<T> *>(a.specB) + (long long)f * NC;
+        for (int j = threadIdx.x; j < Pact * KX; j += NTB) {
+            const int p = j / KX, k = j - (j / KX) * KX;
+            const cx<T> ck = split[F::lidx(p, k)];
+            const cx<T> cm = split[F::lidx(p, k == 0 ? 0 : L - k)];
+            const long long r0 = 2 * (pair0 + p);
+            ct::gst(out + r0 * KX + k, mk<T>(T(0.5) * (ck.x + cm.x), T(0.5) * (ck.y - cm.y)));
+            if (r0 + 1 < rows) ct::gst(out + (r0 + 1) * KX + k, mk<T>(T(0.5) * (ck.y + cm.y), T(-0.5) * (ck.x - cm.x)));
+        }
+    }
+}
+
 // Launch shapes: P columns per tile, NTB threads.
 template <typename T> struct ZShape;
 template <> struct ZShape<float> { static constexpr int P = 8, CAP = 512; };
@@ -507,6 +650,37 @@ bool launch_y_ct(const Geo &g, const YArgs &a, hipStream_t s) {
     }
 }
 
+template <typename T, int L>
+static void launch_x2c_len(const Geo &g, const X2Args &a, hipStream_t s) {
+    const long long npairs = ((long long)g.ny * g.nz + 1) / 2;
+    const long long nb = cdiv(npairs, XTile<L>::PB);
+    if (nb > a.red.cap) throw std::runtime_error("x2: reduction buffer too small");
+    hipLaunchKernelGGL((k_x2c<T, L>), dim3((unsigned)nb, 1, (unsigned)g.nprob), dim3(XTile<L>::NTB), 0, s, g, a);
+    check("x2 (compiled length)");
+}
+
+template <typename T>
+bool launch_x2_ct(const Geo &g, const X2Args &a, hipStream_t s) {
+    switch (g.nx) {
+#define DFT_CASE(n) case n: launch_x2c_len<T, n>(g, a, s); return true;
+        DFT_CT_LENGTHS(DFT_CASE)
+#undef DFT_CASE
+        default: return false;
+    }
+}
+
+// Row pairs per block of the compiled-length x kernels (0: the length has none).
+int x_ct_pairs(int nx) {
+    switch (nx) {
+#define DFT_CASE(n) case n: return XTile<n>::PB;
+        DFT_CT_LENGTHS(DFT_CASE)
+#undef DFT_CASE
+        default: return 0;
+    }
+}
+
+template bool launch_x2_ct<double>(const Geo &, const X2Args &, hipStream_t);
+template bool launch_x2_ct<float>(const Geo &, const X2Args &, hipStream_t);
 template bool launch_y_ct<double>(const Geo &, const YArgs &, hipStream_t);
 template bool launch_y_ct<float>(const Geo &, const YArgs &, hipStream_t);
 

@@ -216,5 +216,20 @@ template <> struct Plan<192> { using type = Sched<8, 8, 3>; };
 template <> struct Plan<256> { using type = Sched<8, 8, 4>; };
 template <> struct Plan<384> { using type = Sched<8, 4, 4, 3>; };
 
+// Schedules of the x passes: radices of at most 4, the first (forward) being 4, so a
+// block of L P / 4 threads holds four values of every pencil-element column it owns and
+// the values of several fields at one node stay in one thread.
+template <int L> struct XPlan;
+template <> struct XPlan<16> { using type = Sched<4, 4>; };
+template <> struct XPlan<24> { using type = Sched<4, 3, 2>; };
+template <> struct XPlan<32> { using type = Sched<4, 4, 2>; };
+template <> struct XPlan<48> { using type = Sched<4, 4, 3>; };
+template <> struct XPlan<64> { using type = Sched<4, 4, 4>; };
+template <> struct XPlan<96> { using type = Sched<4, 4, 3, 2>; };
+template <> struct XPlan<128> { using type = Sched<4, 4, 4, 2>; };
+template <> struct XPlan<192> { using type = Sched<4, 4, 4, 3>; };
+template <> struct XPlan<256> { using type = Sched<4, 4, 4, 4>; };
+template <> struct XPlan<384> { using type = Sched<4, 4, 4, 3, 2>; };
+
 }  // namespace ct
 }  // namespace dft

@@ -80,4 +80,93 @@ __device__ __forceinline__ void xcd_block(int &bx, int &by) {
     by = l / gx;
 }
 
+// ------------------------------------------------------------------ block reductions
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_down(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ int wave_or(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v |= __shfl_down(v, o, 64);
+    return v;
+}
+
+// Fixed-order block reduction (sum or max) of one double and an OR of one int.
+template <bool MAX, int NTB>
+__device__ __forceinline__ void block_reduce_nt(double v, int fl, double *dst, int *fdst) {
+    __shared__ double sv[NTB / 64];
+    __shared__ int sf[NTB / 64];
+    v = MAX ? wave_max(v) : wave_sum(v);
+    fl = wave_or(fl);
+    const int w = threadIdx.x / 64, l = threadIdx.x % 64;
+    if (l == 0) { sv[w] = v; sf[w] = fl; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = sv[0];
+        int f = sf[0];
+        for (int i = 1; i < NTB / 64; ++i) { a = MAX ? fmax(a, sv[i]) : a + sv[i]; f |= sf[i]; }
+        *dst = a;
+        *fdst = f;
+    }
+}
+
+// ------------------------------------------------------------------ X2 node work
+// Pointwise work of X2 at one real node idx (of N): the ten weighted densities n in
+// (FP32-mixed: differences from the reference nref), dPhi/dn of eq. (Phi) out in d
+// (FP32-mixed: the difference from dPhi/dn at the reference; X2_HESS: the product
+// Phi''(nstar) n).  Updates the running maximum of n3 and the flags (1: non-finite,
+// 2: xi^2 clamped) and writes the optional FP64 / FP32 copies.
+__device__ __forceinline__ void x2_node(const X2Args &a, long long N, long long idx, const double (&nin)[DFT_NALPHA],
+                                        double (&d)[DFT_NALPHA], double &mloc, int &flag) {
+    double n[DFT_NALPHA];
+#pragma unroll
+    for (int f = 0; f < DFT_NALPHA; ++f) n[f] = nin[f];
+    bool clamped = false;
+    if (a.mode == X2_HESS) {
+        Dual nd[DFT_NALPHA], dd[DFT_NALPHA];
+#pragma unroll
+        for (int f = 0; f < DFT_NALPHA; ++f) nd[f] = Dual{a.nstar[f * N + idx], n[f]};
+        fmt_dphi<Dual>(nd, dd, clamped);
+        bool bad = false;
+#pragma unroll
+        for (int f = 0; f < DFT_NALPHA; ++f) {
+            d[f] = dd[f].d;
+            bad |= !isfinite(d[f]);
+            if (a.t_out) a.t_out[f * N + idx] = d[f];
+        }
+        if (bad) flag |= 1;
+        return;
+    }
+    if (a.nref) {
+        double nr[DFT_NALPHA], dr[DFT_NALPHA];
+#pragma unroll
+        for (int f = 0; f < DFT_NALPHA; ++f) {
+            nr[f] = (double)a.nref[f * N + idx];
+            n[f] += nr[f];
+        }
+        bool c2;
+        fmt_dphi<double>(n, d, clamped);
+        fmt_dphi<double>(nr, dr, c2);
+#pragma unroll
+        for (int f = 0; f < DFT_NALPHA; ++f) d[f] -= dr[f];
+    } else {
+        fmt_dphi<double>(n, d, clamped);
+    }
+    if (clamped) flag |= 2;
+    if (!isfinite(n[3]) || !isfinite(d[0]) || !isfinite(d[3])) flag |= 1;
+    mloc = fmax(mloc, n[3]);
+#pragma unroll
+    for (int f = 0; f < DFT_NALPHA; ++f) {
+        if (a.nref_out) a.nref_out[f * N + idx] = (float)n[f];
+        if (a.n_out) a.n_out[f * N + idx] = n[f];
+        if (a.dphi_out) a.dphi_out[f * N + idx] = d[f];
+    }
+}
+
 }  // namespace dft
