@@ -123,28 +123,6 @@ struct dft_ctx {
 
 namespace {
 
-template <typename T> int x3_parts(const Geo &g);
-
-int x_pairs_host(const Geo &g, int E) {
-    long long P = (256LL * E) / g.nx;
-    const long long npairs = ((long long)g.ny * g.nz + 1) / 2;
-    if (P > npairs) P = npairs;
-    if (P < 1) P = 1;
-    return (int)P;
-}
-
-int nparts_x3(const Geo &g, bool fp32) {
-    const int P = x_pairs_host(g, fp32 ? 16 : 8);
-    const long long npairs = ((long long)g.ny * g.nz + 1) / 2;
-    return (int)((npairs + P - 1) / P) * g.S;
-}
-
-int nparts_x2(const Geo &g) {
-    const int P = x_pairs_host(g, 4);
-    const long long npairs = ((long long)g.ny * g.nz + 1) / 2;
-    return (int)((npairs + P - 1) / P);
-}
-
 // Options of one residual evaluation.
 struct Eval {
     bool trial = false;            // rho_t = rho0 + alpha (g0 - rho0)
@@ -233,7 +211,7 @@ void enqueue_eval_t(dft_ctx *c, const Eval &ev, hipStream_t s) {
     x3.gate = ev.gate;
     launch_x3<T>(g, x3, s);
     mark(ev, 9, s);
-    launch_finalize(c->red, nparts_x3(g, sizeof(T) == 4), x2_nblocks<T>(g), ev.fslot, ev.mslot, c->st,
+    launch_finalize(c->red, x3_nparts<T>(g), x2_nblocks<T>(g), ev.fslot, ev.mslot, c->st,
                     ev.count_kind, ev.gate, s, g.nprob, g.pstride);
     mark(ev, 10, s);
 }

@@ -128,6 +128,8 @@ template <typename T> bool launch_y_ct(const Geo &g, const YArgs &a, hipStream_t
 template <typename T> bool launch_z1_ct(const Geo &g, const Z1Args &a, int es, hipStream_t s);
 template <typename T> bool launch_z2_ct(const Geo &g, const Z2Args &a, hipStream_t s);
 template <typename T> bool launch_x2_ct(const Geo &g, const X2Args &a, hipStream_t s);
+template <typename T> bool launch_x1_ct(const Geo &g, const XFwdArgs &a, hipStream_t s);
+template <typename T> bool launch_x3_ct(const Geo &g, const X3Args &a, hipStream_t s);
 int x_ct_pairs(int nx);   // row pairs per block of the compiled-length x kernels, 0 if none
 template <typename T> void launch_z1(const Geo &g, const Z1Args &a, hipStream_t s);
 template <typename T> void launch_z2(const Geo &g, const Z2Args &a, hipStream_t s);
@@ -138,6 +140,7 @@ template <typename T> void launch_x3(const Geo &g, const X3Args &a, hipStream_t 
 int x2_blocks(const Geo &g);
 template <typename T> int x2_nblocks(const Geo &g);   // partials written by launch_x2<T>
 int x3_blocks(const Geo &g);
+template <typename T> int x3_nparts(const Geo &g);   // partials written by launch_x3<T> (all species)
 
 // Reduction of the partials into state slots (single block, fixed order).
 // A non-finite evaluation stores +inf in its slots (the line search then rejects it).

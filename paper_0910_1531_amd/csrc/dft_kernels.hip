@@ -795,6 +795,7 @@ static long long ceil_div(long long a, long long b) { return (a + b - 1) / b; }
 
 template <typename T>
 void launch_x_forward(const Geo &g, const XFwdArgs &a, hipStream_t s) {
+    if (launch_x1_ct<T>(g, a, s)) return;
     constexpr int E = Cfg<T>::XE;
     const int P = x_pairs<T, E>(g);
     const long long npairs = ((long long)g.ny * g.nz + 1) / 2;
@@ -843,14 +844,19 @@ void launch_z2(const Geo &g, const Z2Args &a, hipStream_t s) {
     check_launch("z2");
 }
 
-int x3_blocks(const Geo &g) {
-    // the larger of the two precisions' block counts
+template <typename T>
+int x3_nparts(const Geo &g) {
     const long long npairs = ((long long)g.ny * g.nz + 1) / 2;
-    long long P = (NT * Cfg<double>::XE) / g.nx;
+    if (const int pb = x_ct_pairs(g.nx)) return (int)ceil_div(npairs, pb) * g.S;
+    long long P = (NT * Cfg<T>::XE) / g.nx;
     if (P < 1) P = 1;
     if (P > npairs) P = npairs;
     return (int)ceil_div(npairs, P) * g.S;
 }
+template int x3_nparts<double>(const Geo &);
+template int x3_nparts<float>(const Geo &);
+
+int x3_blocks(const Geo &g) { return std::max(x3_nparts<double>(g), x3_nparts<float>(g)); }
 
 // Batched x_fmt geometry: NTB threads, PB row pairs per block (10 PB nx <= NTB * 12),
 // LDS of at most 64 KiB.  Returns false when the row is too long for it.
@@ -916,6 +922,7 @@ int x2_blocks(const Geo &g) { return std::max(x2_nblocks<double>(g), x2_nblocks<
 
 template <typename T>
 void launch_x3(const Geo &g, const X3Args &a, hipStream_t s) {
+    if (launch_x3_ct<T>(g, a, s)) return;
     constexpr int E = Cfg<T>::XE;
     const int P = x_pairs<T, E>(g);
     const long long npairs = ((long long)g.ny * g.nz + 1) / 2;

@@ -568,6 +568,159 @@ __global__ __launch_bounds__(XTile<L>::NTB) void k_x2c(Geo g_in, X2Args a) {
     }
 }
 
+// X1: real rows of field blockIdx.y (plain, or the line-search trial point
+// rho0 + alpha (g0 - rho0), written out; FP32-mixed: minus the reference) -> forward x ->
+// half spectra.
+template <typename T, int L>
+__global__ __launch_bounds__(XTile<L>::NTB) void k_x1c(Geo g_in, XFwdArgs a) {
+    using XT = XTile<L>;
+    constexpr int PB = XT::PB, NTB = XT::NTB, KX = XT::KX;
+    using F = ct::Fft<T, typename ct::XPlan<L>::type, PB, NTB, true, 2, XT::PAD>;
+    const int prob = (int)blockIdx.z;
+    if (prob > 0) {
+        const long long o = (long long)prob * g_in.pstride;
+        g_in = shift(g_in, o);
+        a = shift(a, o);
+    }
+    const Geo &g = g_in;
+    if (gated_off(a.gate)) return;
+    __shared__ cx<T> lds[F::LDS_ELEMS + F::TILE];
+    cx<T> *split = lds + F::LDS_ELEMS;
+    const int f = blockIdx.y;
+    const long long rows = (long long)g.ny * g.nz;
+    const long long npairs = (rows + 1) / 2;
+    const long long pair0 = (long long)blockIdx.x * PB;
+    const int Pact = (int)min((long long)PB, npairs - pair0);
+    const long long foff = (long long)f * g.N;
+    const bool trial = a.mode == XF_TRIAL;
+    const double alpha = trial ? *a.alpha : 0.0;
+    cx<T> v[F::V];
+#pragma unroll
+    for (int i = 0; i < F::template nin<-1>(); ++i) {
+        int p, e;
+        const bool ok = F::template in_pos<-1>(i, p, e) && p < Pact;
+        double x[2] = {0.0, 0.0};
+        if (ok) {
+            const long long r0 = 2 * (pair0 + p);
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const long long r = r0 + h;
+                if (r >= rows) break;
+                const long long idx = foff + r * L + e;
+                double xv;
+                if (trial) {
+                    const double r0v = ct::gld(a.src + idx);
+                    xv = fma(alpha, ct::gld(a.g0 + idx) - r0v, r0v);
+                    if (a.rho_t) ct::gst(a.rho_t + idx, xv);
+                } else {
+                    xv = ct::gld(a.src + idx);
+                }
+                if (a.ref) xv -= ct::gld(a.ref + idx);
+                x[h] = xv;
+            }
+        }
+        v[i] = mk<T>(T(x[0]), T(x[1]));
+    }
+    int ph = 0;
+    F::template run<-1>(v, lds, ph, twp<T>(g, 0));
+#pragma unroll
+    for (int i = 0; i < F::template nout<-1>(); ++i) {
+        int p, e;
+        if (F::template out_pos<-1>(i, p, e)) split[F::lidx(p, e)] = v[i];
+    }
+    __syncthreads();
+    cx<T> *out = reinterpret_cast<cx<T> *>(a.spec) + (long long)f * g.NC;
+    for (int j = threadIdx.x; j < Pact * KX; j += NTB) {
+        const int p = j / KX, k = j - (j / KX) * KX;
+        const cx<T> ck = split[F::lidx(p, k)];
+        const cx<T> cm = split[F::lidx(p, k == 0 ? 0 : L - k)];
+        const long long r0 = 2 * (pair0 + p);
+        ct::gst(out + r0 * KX + k, mk<T>(T(0.5) * (ck.x + cm.x), T(0.5) * (ck.y - cm.y)));
+        if (r0 + 1 < rows) ct::gst(out + (r0 + 1) * KX + k, mk<T>(T(0.5) * (ck.y + cm.y), T(-0.5) * (ck.x - cm.x)));
+    }
+}
+
+// X3: half spectra of E_k (species blockIdx.y) -> inverse x -> Euler-Lagrange update
+// G = rho_b exp(base + E) (eq. rhoEquation) and the weighted residual sums; raw mode
+// writes E (+ addend) only.
+template <typename T, int L>
+__global__ __launch_bounds__(XTile<L>::NTB) void k_x3c(Geo g_in, X3Args a) {
+    using XT = XTile<L>;
+    constexpr int PB = XT::PB, NTB = XT::NTB, KX = XT::KX;
+    using F = ct::Fft<T, typename ct::XPlan<L>::type, PB, NTB, true, 2, XT::PAD>;
+    const int prob = (int)blockIdx.z;
+    if (prob > 0) {
+        const long long o = (long long)prob * g_in.pstride;
+        g_in = shift(g_in, o);
+        a = shift(a, o);
+    }
+    const Geo &g = g_in;
+    if (gated_off(a.gate)) return;
+    __shared__ cx<T> lds[F::LDS_ELEMS];
+    const Consts &c = *g.cs;
+    const int sp = blockIdx.y;
+    const long long N = g.N;
+    const long long rows = (long long)g.ny * g.nz;
+    const long long npairs = (rows + 1) / 2;
+    const long long pair0 = (long long)blockIdx.x * PB;
+    const int Pact = (int)min((long long)PB, npairs - pair0);
+    const cx<T> *in = reinterpret_cast<const cx<T> *>(a.specA) + (long long)sp * g.NC;
+    cx<T> v[F::V];
+#pragma unroll
+    for (int i = 0; i < F::template nin<1>(); ++i) {
+        int p, e;
+        const bool ok = F::template in_pos<1>(i, p, e) && p < Pact;
+        cx<T> cv = mk<T>(T(0), T(0));
+        if (ok) {
+            const long long r0 = 2 * (pair0 + p);
+            const cx<T> A = half_at<T, L>(in + r0 * KX, e);
+            cx<T> B = mk<T>(T(0), T(0));
+            if (r0 + 1 < rows) B = half_at<T, L>(in + (r0 + 1) * KX, e);
+            cv = mk<T>(A.x - B.y, A.y + B.x);
+        }
+        v[i] = cv;
+    }
+    int ph = 0;
+    F::template run<1>(v, lds, ph, twp<T>(g, 0));
+    double acc = 0.0;
+    int flag = 0;
+    const double rb = c.rho_b[sp], irb = c.inv_rho_b[sp], zs = c.z[sp];
+#pragma unroll
+    for (int i = 0; i < F::template nout<1>(); ++i) {
+        int p, e;
+        if (!(F::template out_pos<1>(i, p, e) && p < Pact)) continue;
+        const long long r0 = 2 * (pair0 + p);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const long long r = r0 + h;
+            if (r >= rows) break;
+            const double E = h == 0 ? (double)v[i].x : (double)v[i].y;
+            const long long node = r * L + e;
+            const long long idx = (long long)sp * N + node;
+            if (a.raw) {
+                double o = E;
+                if (a.addend) o += ct::gld(a.addend + node);
+                ct::gst(a.raw_out + idx, o);
+                continue;
+            }
+            const double b = ct::gld(a.base + idx);
+            const bool fluid = b > -INFINITY;
+            const double G = fluid ? rb * exp(b + E) : 0.0;
+            if (a.g_out) ct::gst(a.g_out + idx, G);
+            if (a.e_out) ct::gst(a.e_out + idx, a.e_phi ? E - zs * ct::gld(a.e_phi + node) : E);
+            if (a.lp_out) ct::gst(a.lp_out + idx, fluid ? b + E : -INFINITY);
+            if (fluid) {
+                const double dlt = (ct::gld(a.rho_t + idx) - G) * irb;
+                acc += dlt * dlt;
+                if (!isfinite(G)) flag |= 1;
+            }
+        }
+    }
+    if (a.raw) return;
+    const long long slot = (long long)blockIdx.y * gridDim.x + blockIdx.x;
+    block_reduce_nt<false, NTB>(acc, flag, a.red.fpart + slot, a.red.fflag + slot);
+}
+
 // Launch shapes: P columns per tile, NTB threads.
 template <typename T> struct ZShape;
 template <> struct ZShape<float> { static constexpr int P = 8, CAP = 512; };
@@ -679,6 +832,48 @@ int x_ct_pairs(int nx) {
     }
 }
 
+template <typename T, int L>
+static void launch_x1c_len(const Geo &g, const XFwdArgs &a, hipStream_t s) {
+    const long long npairs = ((long long)g.ny * g.nz + 1) / 2;
+    dim3 grid((unsigned)cdiv(npairs, XTile<L>::PB), (unsigned)a.nfield, (unsigned)g.nprob);
+    hipLaunchKernelGGL((k_x1c<T, L>), grid, dim3(XTile<L>::NTB), 0, s, g, a);
+    check("x1 (compiled length)");
+}
+
+template <typename T, int L>
+static void launch_x3c_len(const Geo &g, const X3Args &a, hipStream_t s) {
+    const long long npairs = ((long long)g.ny * g.nz + 1) / 2;
+    const long long nb = cdiv(npairs, XTile<L>::PB);
+    if (!a.raw && nb * a.nfield > a.red.cap) throw std::runtime_error("x3: reduction buffer too small");
+    dim3 grid((unsigned)nb, (unsigned)a.nfield, (unsigned)g.nprob);
+    hipLaunchKernelGGL((k_x3c<T, L>), grid, dim3(XTile<L>::NTB), 0, s, g, a);
+    check("x3 (compiled length)");
+}
+
+template <typename T>
+bool launch_x1_ct(const Geo &g, const XFwdArgs &a, hipStream_t s) {
+    switch (g.nx) {
+#define DFT_CASE(n) case n: launch_x1c_len<T, n>(g, a, s); return true;
+        DFT_CT_LENGTHS(DFT_CASE)
+#undef DFT_CASE
+        default: return false;
+    }
+}
+
+template <typename T>
+bool launch_x3_ct(const Geo &g, const X3Args &a, hipStream_t s) {
+    switch (g.nx) {
+#define DFT_CASE(n) case n: launch_x3c_len<T, n>(g, a, s); return true;
+        DFT_CT_LENGTHS(DFT_CASE)
+#undef DFT_CASE
+        default: return false;
+    }
+}
+
+template bool launch_x1_ct<double>(const Geo &, const XFwdArgs &, hipStream_t);
+template bool launch_x1_ct<float>(const Geo &, const XFwdArgs &, hipStream_t);
+template bool launch_x3_ct<double>(const Geo &, const X3Args &, hipStream_t);
+template bool launch_x3_ct<float>(const Geo &, const X3Args &, hipStream_t);
 template bool launch_x2_ct<double>(const Geo &, const X2Args &, hipStream_t);
 template bool launch_x2_ct<float>(const Geo &, const X2Args &, hipStream_t);
 template bool launch_y_ct<double>(const Geo &, const YArgs &, hipStream_t);
