@@ -92,6 +92,7 @@ def gpu_leg(prob, precision, steps, warmup, solve_tol, profile_reps):
     out["ms_per_step"] = 1e3 * (t1 - t0) / steps
     out["its"] = steps / (t1 - t0)
     out["profile_ms"] = sol.profile(x, reps=profile_reps)
+    out["schedule"] = sol.schedule()
     sol.close()
     return out
 
@@ -209,6 +210,9 @@ def main():
         "eval_ms": round(eval_ms, 4),
         "eval_GBs": round(eval_gbs, 1),
         "cpu_baseline": cpu,
+        "fft_schedule": {"shapes": {k: {"fp64": v[0], "fp32": v[1]} for k, v in head["schedule"].items()},
+                         "legend": "autotuned tile shape per pass; y: 0/1/2 = 16/8/32 (FP32) or 8/4/16 (FP64) "
+                                   "columns per tile; z: 0/1 = 8/4 (FP32) or 4/2 (FP64) columns per tile"},
     }
     print(json.dumps(line), flush=True)
 

@@ -70,6 +70,7 @@ typedef enum dft_precision {
 /* Flags for dft_params.flags */
 #define DFT_FLAG_ALLOW_NON_NEUTRAL 1   /* accept a non-neutral bulk (finite-difference probes) */
 #define DFT_FLAG_CUTOFF_LAMBDA     2   /* cut the screening kernel at lambda_i + lambda_j, not R_i + R_j */
+#define DFT_FLAG_NO_AUTOTUNE       4   /* skip the launch-shape autotuner at setup (default shapes) */
 
 /*
  * Problem statement (theory section; Appendix A for the bath).  Inline arrays keep
@@ -285,6 +286,20 @@ dft_status dft_batch_destroy(dft_batch *batch);
 
 /* Counters of the ctx (host out). */
 dft_status dft_get_stats(dft_ctx *ctx, dft_stats *out);
+
+/*
+ * Launch shapes of the FFT pass kernels (batched FFT schedules, Section 4's many
+ * transforms per step): for each pass in {y, plain z, z weighted densities, z
+ * back-convolution} and each transform precision {FP64, FP32}, the index of the tile
+ * shape in use, as DFT_SCHEDULE_LEN int32 laid out [pass][precision].  dft_setup picks
+ * them by timing every shape on the device (the autotuner; DFT_FLAG_NO_AUTOTUNE keeps
+ * shape 0).  Every shape of a pass performs the same arithmetic in the same order, so the
+ * shapes change run time only, never results.  dft_set_schedule validates each index
+ * (DFT_E_INVALID_ARG if out of range) and drops the ctx's captured step graph.
+ */
+#define DFT_SCHEDULE_LEN 8
+dft_status dft_get_schedule(const dft_ctx *ctx, int32_t *shapes_out);
+dft_status dft_set_schedule(dft_ctx *ctx, const int32_t *shapes);
 
 /* Free the ctx and its graph; caller memory is untouched.  NULL is accepted. */
 dft_status dft_destroy(dft_ctx *ctx);

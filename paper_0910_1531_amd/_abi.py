@@ -19,6 +19,9 @@ DFT_FP64 = 0
 DFT_FP32_MIXED = 1
 FLAG_ALLOW_NON_NEUTRAL = 1
 FLAG_CUTOFF_LAMBDA = 2
+FLAG_NO_AUTOTUNE = 4
+SCHEDULE_LEN = 8
+TUNE_PASSES = ["y", "z_plain", "z_weights", "z_back"]
 
 D8 = ctypes.c_double * MAX_SPECIES
 
@@ -75,6 +78,8 @@ SIGNATURES = [
                          ctypes.POINTER(ctypes.c_int32)]),
     ("dft_batch_destroy", [_vp]),
     ("dft_get_stats", [_vp, ctypes.POINTER(Stats)]),
+    ("dft_get_schedule", [_vp, ctypes.POINTER(ctypes.c_int32)]),
+    ("dft_set_schedule", [_vp, ctypes.POINTER(ctypes.c_int32)]),
     ("dft_destroy", [_vp]),
 ]
 

@@ -16,13 +16,14 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libdftpicard.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
-SOURCES = ["dft_host.cpp", "dft_kernels.hip", "dft_kernels_ct.hip", "dft_adjoint.hip", "dft_api.hip"]
+SOURCES = ["dft_host.cpp", "dft_kernels.hip", "ct_launch_x.hip", "ct_launch_y.hip", "ct_launch_z1_f32.hip",
+           "ct_launch_z1_f64.hip", "ct_launch_z2.hip", "dft_tune.hip", "dft_adjoint.hip", "dft_api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function", "-I", CSRC, "-I", INCLUDE]
 DEVICE = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-          "-munsafe-fp-atomics", "-ffp-contract=fast"]
+          "-munsafe-fp-atomics", "-ffp-contract=on"]
 
 
 def _compile(src):

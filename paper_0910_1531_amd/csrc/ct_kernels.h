@@ -1,26 +1,18 @@
-// Pass kernels with the transform length fixed at compile time (fft_ct.h), for the
-// lengths listed in ct::Plan.  They compute the same transforms as the run-time-length
-// kernels with the same radix order, so results agree to rounding.
-#include "dft_kernels.h"
-#include "fft_ct.h"
-#include "pass_util.h"
+// Pass kernels with the transform length fixed at compile time (fft_ct.h).  They compute
+// the same transforms as the run-time-length kernels, and every launch shape of one length
+// (tile width, threads, LDS buffering) performs the same arithmetic in the same order, so
+// the choice among shapes never changes a result.
+#pragma once
 
 #include <stdexcept>
 #include <string>
 #include <type_traits>
 
+#include "dft_kernels.h"
+#include "fft_ct.h"
+#include "pass_util.h"
+
 namespace dft {
-
-namespace {
-
-void check(const char *what) {
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) throw std::runtime_error(std::string(what) + ": " + hipGetErrorString(e));
-}
-
-long long cdiv(long long a, long long b) { return (a + b - 1) / b; }
-
-}  // namespace
 
 // Threads per block: a power of two in [64, cap] near L P / per (per = values per thread).
 constexpr int fit_threads(int L, int P, int per, int cap) {
@@ -29,6 +21,14 @@ constexpr int fit_threads(int L, int P, int per, int cap) {
     return t;
 }
 
+inline void ct_check(const char *what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) throw std::runtime_error(std::string(what) + ": " + hipGetErrorString(e));
+}
+
+inline long long ct_cdiv(long long a, long long b) { return (a + b - 1) / b; }
+
+#define DFT_CT_LENGTHS(X) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384)
 
 // ------------------------------------------------------------------ y / z plain transforms
 // One block transforms P adjacent columns (kx) of one field along y (one z plane) or z
@@ -720,163 +720,5 @@ __global__ __launch_bounds__(XTile<L>::NTB) void k_x3c(Geo g_in, X3Args a) {
     const long long slot = (long long)blockIdx.y * gridDim.x + blockIdx.x;
     block_reduce_nt<false, NTB>(acc, flag, a.red.fpart + slot, a.red.fflag + slot);
 }
-
-// Launch shapes: P columns per tile, NTB threads.
-template <typename T> struct ZShape;
-template <> struct ZShape<float> { static constexpr int P = 8, CAP = 512; };
-template <> struct ZShape<double> { static constexpr int P = 4, CAP = 256; };
-
-template <typename T, int L>
-static void launch_z1c_len(const Geo &g, const Z1Args &a, int es, hipStream_t s) {
-    constexpr int P = ZShape<T>::P, NTB = fit_threads(L, P, 4, ZShape<T>::CAP);
-    dim3 grid((unsigned)cdiv(g.Kx, P), (unsigned)g.ny, (unsigned)g.nprob);
-    if (!es) hipLaunchKernelGGL((k_z1c<T, L, P, NTB, 0>), grid, dim3(NTB), 0, s, g, a);
-    else {
-        bool done = false;
-        if constexpr (std::is_same<T, float>::value) {
-            if (g.S <= 2) {
-                hipLaunchKernelGGL((k_z1c<T, L, P, NTB, 2>), grid, dim3(NTB), 0, s, g, a);
-                done = true;
-            }
-        }
-        if (!done) hipLaunchKernelGGL((k_z1c<T, L, P, NTB, 4>), grid, dim3(NTB), 0, s, g, a);
-    }
-    check("z1 (compiled length)");
-}
-
-template <typename T, int L>
-static void launch_z2c_len(const Geo &g, const Z2Args &a, hipStream_t s) {
-    constexpr int P = ZShape<T>::P, NTB = fit_threads(L, P, 4, ZShape<T>::CAP);
-    dim3 grid((unsigned)cdiv(g.Kx, P), (unsigned)g.ny, (unsigned)g.nprob);
-    hipLaunchKernelGGL((k_z2c<T, L, P, NTB>), grid, dim3(NTB), 0, s, g, a);
-    check("z2 (compiled length)");
-}
-
-#define DFT_CT_LENGTHS(X) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384)
-
-template <typename T>
-bool launch_z1_ct(const Geo &g, const Z1Args &a, int es, hipStream_t s) {
-    if (es && g.S > 4) return false;   // electrostatic sums of more species: run-time-length kernel
-    switch (g.nz) {
-#define DFT_CASE(n) case n: launch_z1c_len<T, n>(g, a, es, s); return true;
-        DFT_CT_LENGTHS(DFT_CASE)
-#undef DFT_CASE
-        default: return false;
-    }
-}
-
-template <typename T>
-bool launch_z2_ct(const Geo &g, const Z2Args &a, hipStream_t s) {
-    switch (g.nz) {
-#define DFT_CASE(n) case n: launch_z2c_len<T, n>(g, a, s); return true;
-        DFT_CT_LENGTHS(DFT_CASE)
-#undef DFT_CASE
-        default: return false;
-    }
-}
-
-template bool launch_z1_ct<double>(const Geo &, const Z1Args &, int, hipStream_t);
-template bool launch_z1_ct<float>(const Geo &, const Z1Args &, int, hipStream_t);
-template bool launch_z2_ct<double>(const Geo &, const Z2Args &, hipStream_t);
-template bool launch_z2_ct<float>(const Geo &, const Z2Args &, hipStream_t);
-
-template <typename T> struct YShape;
-template <> struct YShape<float> { static constexpr int P = 16, CAP = 256, NB = 2; };
-template <> struct YShape<double> { static constexpr int P = 8, CAP = 256, NB = 2; };
-
-template <typename T, int L>
-static void launch_yc_len(const Geo &g, const YArgs &a, hipStream_t s) {
-    constexpr int P = YShape<T>::P, NB = YShape<T>::NB, NTB = fit_threads(L, P, 8, YShape<T>::CAP);
-    const bool zax = a.axis == 2;
-    dim3 grid((unsigned)cdiv(g.Kx, P), (unsigned)(zax ? g.ny : g.nz), (unsigned)(a.nfield * g.nprob));
-    hipLaunchKernelGGL((k_yc<T, L, P, NTB, NB>), grid, dim3(NTB), 0, s, g, a);
-    check("y (compiled length)");
-}
-
-template <typename T>
-bool launch_y_ct(const Geo &g, const YArgs &a, hipStream_t s) {
-    switch (a.axis == 2 ? g.nz : g.ny) {
-#define DFT_CASE(n) case n: launch_yc_len<T, n>(g, a, s); return true;
-        DFT_CT_LENGTHS(DFT_CASE)
-#undef DFT_CASE
-        default: return false;
-    }
-}
-
-template <typename T, int L>
-static void launch_x2c_len(const Geo &g, const X2Args &a, hipStream_t s) {
-    const long long npairs = ((long long)g.ny * g.nz + 1) / 2;
-    const long long nb = cdiv(npairs, XTile<L>::PB);
-    if (nb > a.red.cap) throw std::runtime_error("x2: reduction buffer too small");
-    hipLaunchKernelGGL((k_x2c<T, L>), dim3((unsigned)nb, 1, (unsigned)g.nprob), dim3(XTile<L>::NTB), 0, s, g, a);
-    check("x2 (compiled length)");
-}
-
-template <typename T>
-bool launch_x2_ct(const Geo &g, const X2Args &a, hipStream_t s) {
-    switch (g.nx) {
-#define DFT_CASE(n) case n: launch_x2c_len<T, n>(g, a, s); return true;
-        DFT_CT_LENGTHS(DFT_CASE)
-#undef DFT_CASE
-        default: return false;
-    }
-}
-
-// Row pairs per block of the compiled-length x kernels (0: the length has none).
-int x_ct_pairs(int nx) {
-    switch (nx) {
-#define DFT_CASE(n) case n: return XTile<n>::PB;
-        DFT_CT_LENGTHS(DFT_CASE)
-#undef DFT_CASE
-        default: return 0;
-    }
-}
-
-template <typename T, int L>
-static void launch_x1c_len(const Geo &g, const XFwdArgs &a, hipStream_t s) {
-    const long long npairs = ((long long)g.ny * g.nz + 1) / 2;
-    dim3 grid((unsigned)cdiv(npairs, XTile<L>::PB), (unsigned)a.nfield, (unsigned)g.nprob);
-    hipLaunchKernelGGL((k_x1c<T, L>), grid, dim3(XTile<L>::NTB), 0, s, g, a);
-    check("x1 (compiled length)");
-}
-
-template <typename T, int L>
-static void launch_x3c_len(const Geo &g, const X3Args &a, hipStream_t s) {
-    const long long npairs = ((long long)g.ny * g.nz + 1) / 2;
-    const long long nb = cdiv(npairs, XTile<L>::PB);
-    if (!a.raw && nb * a.nfield > a.red.cap) throw std::runtime_error("x3: reduction buffer too small");
-    dim3 grid((unsigned)nb, (unsigned)a.nfield, (unsigned)g.nprob);
-    hipLaunchKernelGGL((k_x3c<T, L>), grid, dim3(XTile<L>::NTB), 0, s, g, a);
-    check("x3 (compiled length)");
-}
-
-template <typename T>
-bool launch_x1_ct(const Geo &g, const XFwdArgs &a, hipStream_t s) {
-    switch (g.nx) {
-#define DFT_CASE(n) case n: launch_x1c_len<T, n>(g, a, s); return true;
-        DFT_CT_LENGTHS(DFT_CASE)
-#undef DFT_CASE
-        default: return false;
-    }
-}
-
-template <typename T>
-bool launch_x3_ct(const Geo &g, const X3Args &a, hipStream_t s) {
-    switch (g.nx) {
-#define DFT_CASE(n) case n: launch_x3c_len<T, n>(g, a, s); return true;
-        DFT_CT_LENGTHS(DFT_CASE)
-#undef DFT_CASE
-        default: return false;
-    }
-}
-
-template bool launch_x1_ct<double>(const Geo &, const XFwdArgs &, hipStream_t);
-template bool launch_x1_ct<float>(const Geo &, const XFwdArgs &, hipStream_t);
-template bool launch_x3_ct<double>(const Geo &, const X3Args &, hipStream_t);
-template bool launch_x3_ct<float>(const Geo &, const X3Args &, hipStream_t);
-template bool launch_x2_ct<double>(const Geo &, const X2Args &, hipStream_t);
-template bool launch_x2_ct<float>(const Geo &, const X2Args &, hipStream_t);
-template bool launch_y_ct<double>(const Geo &, const YArgs &, hipStream_t);
-template bool launch_y_ct<float>(const Geo &, const YArgs &, hipStream_t);
 
 }  // namespace dft

@@ -1,0 +1,80 @@
+// Launchers of the compiled-length x passes (X1, X2, X3).
+#include "ct_kernels.h"
+
+namespace dft {
+
+template <typename T, int L>
+static void launch_x2c_len(const Geo &g, const X2Args &a, hipStream_t s) {
+    const long long npairs = ((long long)g.ny * g.nz + 1) / 2;
+    const long long nb = ct_cdiv(npairs, XTile<L>::PB);
+    if (nb > a.red.cap) throw std::runtime_error("x2: reduction buffer too small");
+    hipLaunchKernelGGL((k_x2c<T, L>), dim3((unsigned)nb, 1, (unsigned)g.nprob), dim3(XTile<L>::NTB), 0, s, g, a);
+    ct_check("x2 (compiled length)");
+}
+
+template <typename T, int L>
+static void launch_x1c_len(const Geo &g, const XFwdArgs &a, hipStream_t s) {
+    const long long npairs = ((long long)g.ny * g.nz + 1) / 2;
+    dim3 grid((unsigned)ct_cdiv(npairs, XTile<L>::PB), (unsigned)a.nfield, (unsigned)g.nprob);
+    hipLaunchKernelGGL((k_x1c<T, L>), grid, dim3(XTile<L>::NTB), 0, s, g, a);
+    ct_check("x1 (compiled length)");
+}
+
+template <typename T, int L>
+static void launch_x3c_len(const Geo &g, const X3Args &a, hipStream_t s) {
+    const long long npairs = ((long long)g.ny * g.nz + 1) / 2;
+    const long long nb = ct_cdiv(npairs, XTile<L>::PB);
+    if (!a.raw && nb * a.nfield > a.red.cap) throw std::runtime_error("x3: reduction buffer too small");
+    dim3 grid((unsigned)nb, (unsigned)a.nfield, (unsigned)g.nprob);
+    hipLaunchKernelGGL((k_x3c<T, L>), grid, dim3(XTile<L>::NTB), 0, s, g, a);
+    ct_check("x3 (compiled length)");
+}
+
+template <typename T>
+bool launch_x2_ct(const Geo &g, const X2Args &a, hipStream_t s) {
+    switch (g.nx) {
+#define DFT_CASE(n) case n: launch_x2c_len<T, n>(g, a, s); return true;
+        DFT_CT_LENGTHS(DFT_CASE)
+#undef DFT_CASE
+        default: return false;
+    }
+}
+
+template <typename T>
+bool launch_x1_ct(const Geo &g, const XFwdArgs &a, hipStream_t s) {
+    switch (g.nx) {
+#define DFT_CASE(n) case n: launch_x1c_len<T, n>(g, a, s); return true;
+        DFT_CT_LENGTHS(DFT_CASE)
+#undef DFT_CASE
+        default: return false;
+    }
+}
+
+template <typename T>
+bool launch_x3_ct(const Geo &g, const X3Args &a, hipStream_t s) {
+    switch (g.nx) {
+#define DFT_CASE(n) case n: launch_x3c_len<T, n>(g, a, s); return true;
+        DFT_CT_LENGTHS(DFT_CASE)
+#undef DFT_CASE
+        default: return false;
+    }
+}
+
+// Row pairs per block of the compiled-length x kernels (0: the length has none).
+int x_ct_pairs(int nx) {
+    switch (nx) {
+#define DFT_CASE(n) case n: return XTile<n>::PB;
+        DFT_CT_LENGTHS(DFT_CASE)
+#undef DFT_CASE
+        default: return 0;
+    }
+}
+
+template bool launch_x1_ct<double>(const Geo &, const XFwdArgs &, hipStream_t);
+template bool launch_x1_ct<float>(const Geo &, const XFwdArgs &, hipStream_t);
+template bool launch_x2_ct<double>(const Geo &, const X2Args &, hipStream_t);
+template bool launch_x2_ct<float>(const Geo &, const X2Args &, hipStream_t);
+template bool launch_x3_ct<double>(const Geo &, const X3Args &, hipStream_t);
+template bool launch_x3_ct<float>(const Geo &, const X3Args &, hipStream_t);
+
+}  // namespace dft

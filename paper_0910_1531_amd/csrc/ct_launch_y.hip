@@ -1,0 +1,74 @@
+// Launchers of the compiled-length y passes (and plain z transforms), with the launch
+// shapes the autotuner chooses among: P adjacent columns per tile (P complex values are
+// contiguous in HBM) and one or two LDS exchange buffers.
+#include "ct_kernels.h"
+
+namespace dft {
+
+// Shape v of the y kernel for precision T: tile width.
+template <typename T> constexpr int y_width(int v);
+template <> constexpr int y_width<float>(int v) { return v == 0 ? 16 : v == 1 ? 8 : 32; }
+template <> constexpr int y_width<double>(int v) { return v == 0 ? 8 : v == 1 ? 4 : 16; }
+constexpr int kYVariants = 3;
+constexpr int kLdsCap = 65536;
+
+// LDS buffers of shape (T, L, P): 2 when two tiles fit, else 1, 0 when not even one does.
+template <typename T, int L, int P>
+constexpr int y_buffers() {
+    constexpr int tile = L * P * (int)sizeof(cx<T>);
+    return 2 * tile <= kLdsCap ? 2 : (tile <= kLdsCap ? 1 : 0);
+}
+
+template <typename T, int L, int V>
+static bool launch_yc_var(const Geo &g, const YArgs &a, hipStream_t s) {
+    constexpr int P = y_width<T>(V);
+    constexpr int NB = y_buffers<T, L, P>();
+    if constexpr (NB == 0) {
+        return false;
+    } else {
+        constexpr int NTB = fit_threads(L, P, 8, 256);
+        const bool zax = a.axis == 2;
+        dim3 grid((unsigned)ct_cdiv(g.Kx, P), (unsigned)(zax ? g.ny : g.nz), (unsigned)(a.nfield * g.nprob));
+        hipLaunchKernelGGL((k_yc<T, L, P, NTB, NB>), grid, dim3(NTB), 0, s, g, a);
+        ct_check("y (compiled length)");
+        return true;
+    }
+}
+
+template <typename T, int L>
+static bool launch_yc_len(const Geo &g, const YArgs &a, hipStream_t s, int v) {
+    switch (v) {
+        case 1: if (launch_yc_var<T, L, 1>(g, a, s)) return true; break;
+        case 2: if (launch_yc_var<T, L, 2>(g, a, s)) return true; break;
+        default: break;
+    }
+    return launch_yc_var<T, L, 0>(g, a, s);
+}
+
+template <typename T>
+bool launch_y_ct(const Geo &g, const YArgs &a, hipStream_t s) {
+    const int pass = a.axis == 2 ? TUNE_YZ : TUNE_Y;
+    const int v = g.tune[pass][std::is_same<T, float>::value ? 1 : 0];
+    switch (a.axis == 2 ? g.nz : g.ny) {
+#define DFT_CASE(n) case n: return launch_yc_len<T, n>(g, a, s, v);
+        DFT_CT_LENGTHS(DFT_CASE)
+#undef DFT_CASE
+        default: return false;
+    }
+}
+
+// Number of y shapes for a length (0: no compiled kernel).  A shape whose tile does not
+// fit the LDS runs as shape 0.
+int y_ct_variants(int L, bool) {
+    switch (L) {
+#define DFT_CASE(n) case n: return kYVariants;
+        DFT_CT_LENGTHS(DFT_CASE)
+#undef DFT_CASE
+        default: return 0;
+    }
+}
+
+template bool launch_y_ct<double>(const Geo &, const YArgs &, hipStream_t);
+template bool launch_y_ct<float>(const Geo &, const YArgs &, hipStream_t);
+
+}  // namespace dft

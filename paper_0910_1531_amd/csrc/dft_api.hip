@@ -14,6 +14,7 @@
 #include "dft_adjoint.h"
 #include "dft_host.h"
 #include "dft_kernels.h"
+#include "dft_tune.h"
 
 using namespace dft;
 
@@ -482,6 +483,11 @@ dft_status dft_setup(const dft_params *params, const double *beta_vext, const do
         }
         HIPCHK(hipMemcpyAsync(c->cs, &c->hc, sizeof(Consts), hipMemcpyHostToDevice, c->stream));
         HIPCHK(hipStreamSynchronize(c->stream));
+        if (!(params->flags & DFT_FLAG_NO_AUTOTUNE)) {
+            TuneBufs tb{c->specA, 2 * sizeof(double) * (size_t)g.NC * g.S, c->specB,
+                        2 * sizeof(double) * (size_t)g.NC * DFT_NALPHA};
+            autotune(g, tb, true, c->mixed, c->stream);
+        }
         // potential of the fixed charges (Poisson source only), FP64
         const double *phi = nullptr;
         if (fixed_charge && params->electrostatics) {
@@ -1136,6 +1142,20 @@ dft_status dft_setup_batch(const dft_params *params, int32_t count, const double
         lead->geo.pstride = g.stride;
         g.lead = lead;
     }
+    // launch shapes for the whole group (the members' spectra are scratch here)
+    st = guarded([&]() -> dft_status {
+        for (auto &g : b->groups) {
+            dft_ctx *lead = g.lead;
+            if (lead->geo.nprob > 1 && !(lead->p.flags & DFT_FLAG_NO_AUTOTUNE))
+                autotune(lead->geo, TuneBufs{lead->specA, 0, lead->specB, 0}, true, lead->mixed, lead->stream);
+        }
+        return DFT_OK;
+    });
+    if (st != DFT_OK) {
+        std::string m = dft_last_error();
+        dft_batch_destroy(b);
+        return fail(st, m);
+    }
     *out = b;
     g_last_error.clear();
     return DFT_OK;
@@ -1283,6 +1303,39 @@ dft_status dft_get_stats(dft_ctx *ctx, dft_stats *out) {
         out->alpha = h.alpha_acc;
         out->max_n3 = h.m0;
         out->step_cap = h.cap;
+        return DFT_OK;
+    });
+}
+
+dft_status dft_get_schedule(const dft_ctx *ctx, int32_t *shapes_out) {
+    if (!ctx || !shapes_out) return fail(DFT_E_INVALID_ARG, "ctx or shapes_out is NULL");
+    for (int p = 0; p < 4; ++p)
+        for (int t = 0; t < 2; ++t) shapes_out[2 * p + t] = ctx->geo.tune[p][t];
+    return DFT_OK;
+}
+
+dft_status dft_set_schedule(dft_ctx *ctx, const int32_t *shapes) {
+    if (!ctx || !shapes) return fail(DFT_E_INVALID_ARG, "ctx or shapes is NULL");
+    const Geo &g = ctx->geo;
+    const int nv[4] = {g.ny > 1 ? y_ct_variants(g.ny, false) : 0, g.nz > 1 ? y_ct_variants(g.nz, false) : 0,
+                       z_ct_variants(g.nz), z_ct_variants(g.nz)};
+    for (int p = 0; p < 4; ++p)
+        for (int t = 0; t < 2; ++t) {
+            const int v = shapes[2 * p + t];
+            if (v < 0 || v >= std::max(nv[p], 1)) {
+                char buf[120];
+                snprintf(buf, sizeof buf, "shape %d of pass %d outside 0..%d", v, p, std::max(nv[p], 1) - 1);
+                return fail(DFT_E_INVALID_ARG, buf);
+            }
+        }
+    return guarded([&]() -> dft_status {
+        for (int p = 0; p < 4; ++p)
+            for (int t = 0; t < 2; ++t) ctx->geo.tune[p][t] = shapes[2 * p + t];
+        // the captured step graph holds the old launches
+        if (ctx->gexec) HIPCHK(hipGraphExecDestroy(ctx->gexec));
+        if (ctx->graph) HIPCHK(hipGraphDestroy(ctx->graph));
+        ctx->gexec = nullptr;
+        ctx->graph = nullptr;
         return DFT_OK;
     });
 }

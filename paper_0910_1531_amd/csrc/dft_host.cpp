@@ -58,7 +58,7 @@ dft_status validate(const dft_params *p, std::string *msg) {
         *msg = "electrostatics must be 0 or 1";
         return DFT_E_INVALID_ARG;
     }
-    if (p->flags & ~(DFT_FLAG_ALLOW_NON_NEUTRAL | DFT_FLAG_CUTOFF_LAMBDA)) {
+    if (p->flags & ~(DFT_FLAG_ALLOW_NON_NEUTRAL | DFT_FLAG_CUTOFF_LAMBDA | DFT_FLAG_NO_AUTOTUNE)) {
         *msg = "unknown bits in flags";
         return DFT_E_INVALID_ARG;
     }

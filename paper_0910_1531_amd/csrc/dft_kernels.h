@@ -38,7 +38,13 @@ struct Geo {
     // problems whose workspaces sit pstride bytes apart (blockIdx.z carries the problem).
     int nprob = 1;
     long long pstride = 0;
+    // Launch shape of the compiled-length kernels per tunable pass and precision
+    // ([pass][0] FP64, [pass][1] FP32); 0 is the default shape.
+    int tune[4][2] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
 };
+
+// Passes whose launch shape the autotuner picks.
+enum TunePass { TUNE_Y = 0, TUNE_YZ = 1, TUNE_Z1 = 2, TUNE_Z2 = 3 };
 
 // Where the reductions of one residual evaluation go.
 struct RedBufs {
@@ -123,7 +129,7 @@ struct X3Args {
 // Launchers (precision T = double or float of the transforms).
 template <typename T> void launch_x_forward(const Geo &g, const XFwdArgs &a, hipStream_t s);
 template <typename T> void launch_y(const Geo &g, const YArgs &a, hipStream_t s);
-// Compiled-length variants (dft_kernels_ct.hip); false when the length has none.
+// Compiled-length kernels (ct_launch_*.hip); false when the length has none.
 template <typename T> bool launch_y_ct(const Geo &g, const YArgs &a, hipStream_t s);
 template <typename T> bool launch_z1_ct(const Geo &g, const Z1Args &a, int es, hipStream_t s);
 template <typename T> bool launch_z2_ct(const Geo &g, const Z2Args &a, hipStream_t s);
@@ -131,6 +137,8 @@ template <typename T> bool launch_x2_ct(const Geo &g, const X2Args &a, hipStream
 template <typename T> bool launch_x1_ct(const Geo &g, const XFwdArgs &a, hipStream_t s);
 template <typename T> bool launch_x3_ct(const Geo &g, const X3Args &a, hipStream_t s);
 int x_ct_pairs(int nx);   // row pairs per block of the compiled-length x kernels, 0 if none
+int y_ct_variants(int L, bool fp32);   // launch shapes of the y kernels of length L (0: none)
+int z_ct_variants(int L);              // launch shapes of the z kernels of length L (0: none)
 template <typename T> void launch_z1(const Geo &g, const Z1Args &a, hipStream_t s);
 template <typename T> void launch_z2(const Geo &g, const Z2Args &a, hipStream_t s);
 template <typename T> void launch_x2(const Geo &g, const X2Args &a, hipStream_t s);

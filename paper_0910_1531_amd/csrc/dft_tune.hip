@@ -1,0 +1,141 @@
+// Autotuner of the launch shapes of the compiled-length kernels.
+//
+// For every tunable pass (y, plain z, Z1, Z2) and precision a context uses, each launch
+// shape is timed with HIP events on the context's own spectral buffers (scratch during
+// setup) and the fastest kept.  Choices are cached per process by problem shape, so a
+// shape is tuned once.  All shapes of a pass perform the same arithmetic in the same
+// order, so the choice affects time only, never results.
+#include "dft_tune.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <stdexcept>
+#include <string>
+#include <tuple>
+
+namespace dft {
+
+namespace {
+
+void hipchk(hipError_t e, const char *what) {
+    if (e != hipSuccess) throw std::runtime_error(std::string(what) + ": " + hipGetErrorString(e));
+}
+
+using Key = std::tuple<int, int, int, int, int, int, int, int>;   // pass, fp32, nx, ny, nz, S, es, nprob
+std::map<Key, int> g_cache;
+std::mutex g_mu;
+
+int variants_of(const Geo &g, int pass) {
+    switch (pass) {
+        case TUNE_Y: return g.ny > 1 ? y_ct_variants(g.ny, false) : 0;
+        case TUNE_YZ: return g.nz > 1 ? y_ct_variants(g.nz, false) : 0;
+        default: return z_ct_variants(g.nz);
+    }
+}
+
+template <typename T>
+void launch_pass(const Geo &g, const TuneBufs &b, int pass, hipStream_t s) {
+    const bool fp32 = sizeof(T) == 4;
+    switch (pass) {
+        case TUNE_Y: {
+            YArgs a{b.specA, g.S, -1, nullptr};
+            launch_y<T>(g, a, s);
+            break;
+        }
+        case TUNE_YZ: {
+            YArgs a{b.specA, 1, -1, nullptr};
+            a.axis = 2;
+            launch_y<T>(g, a, s);
+            break;
+        }
+        case TUNE_Z1: {
+            Z1Args a{b.specA, b.specB, 0, fp32 ? 1 : 0, nullptr};
+            launch_z1<T>(g, a, s);
+            break;
+        }
+        default: {
+            Z2Args a{};
+            a.specB = b.specB;
+            a.specA = b.specA;
+            a.mode = Z2_EL;
+            launch_z2<T>(g, a, s);
+            break;
+        }
+    }
+}
+
+// Mean time of one launch of the pass with its current shape (best of a few repeats).
+template <typename T>
+float time_pass(const Geo &g, const TuneBufs &b, int pass, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    constexpr int kReps = 3, kLaunches = 2;
+    launch_pass<T>(g, b, pass, s);   // warm-up (code object load, caches)
+    float best = 1e30f;
+    for (int r = 0; r < kReps; ++r) {
+        hipchk(hipEventRecord(e0, s), "event");
+        for (int k = 0; k < kLaunches; ++k) launch_pass<T>(g, b, pass, s);
+        hipchk(hipEventRecord(e1, s), "event");
+        hipchk(hipEventSynchronize(e1), "event sync");
+        float ms = 0.0f;
+        hipchk(hipEventElapsedTime(&ms, e0, e1), "event time");
+        best = std::min(best, ms / kLaunches);
+    }
+    return best;
+}
+
+template <typename T>
+void tune_precision(Geo &g, const TuneBufs &b, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    const int t = sizeof(T) == 4 ? 1 : 0;
+    for (int pass = 0; pass < 4; ++pass) {
+        const int nv = variants_of(g, pass);
+        g.tune[pass][t] = 0;
+        if (nv <= 1) continue;
+        const Key key{pass, t, g.nx, g.ny, g.nz, g.S, g.es, g.nprob};
+        {
+            std::lock_guard<std::mutex> lk(g_mu);
+            auto it = g_cache.find(key);
+            if (it != g_cache.end()) {
+                g.tune[pass][t] = it->second;
+                continue;
+            }
+        }
+        int best_v = 0;
+        float best_ms = 1e30f;
+        for (int v = 0; v < nv; ++v) {
+            g.tune[pass][t] = v;
+            const float ms = time_pass<T>(g, b, pass, s, e0, e1);
+            if (ms < 0.98f * best_ms) {   // a later shape must win clearly
+                best_ms = ms;
+                best_v = v;
+            }
+        }
+        g.tune[pass][t] = best_v;
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_cache[key] = best_v;
+    }
+}
+
+}  // namespace
+
+void autotune(Geo &g, const TuneBufs &b, bool fp64, bool fp32, hipStream_t s) {
+    hipEvent_t e0, e1;
+    hipchk(hipEventCreate(&e0), "event");
+    hipchk(hipEventCreate(&e1), "event");
+    try {
+        if (b.bytesA) hipchk(hipMemsetAsync(b.specA, 0, b.bytesA, s), "memset");
+        if (b.bytesB) hipchk(hipMemsetAsync(b.specB, 0, b.bytesB, s), "memset");
+        if (fp64) tune_precision<double>(g, b, s, e0, e1);
+        if (fp32) tune_precision<float>(g, b, s, e0, e1);
+        hipchk(hipStreamSynchronize(s), "sync");
+    } catch (...) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        throw;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+}
+
+}  // namespace dft

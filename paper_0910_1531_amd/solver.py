@@ -174,6 +174,21 @@ class Solver:
         _abi.check(self.lib.dft_get_stats(self.ctx, ctypes.byref(s)), "dft_get_stats")
         return {k: getattr(s, k) for k, _ in _abi.Stats._fields_}
 
+    def schedule(self):
+        """Launch shape per tunable pass: {pass: (fp64 shape, fp32 shape)}."""
+        buf = (ctypes.c_int32 * _abi.SCHEDULE_LEN)()
+        _abi.check(self.lib.dft_get_schedule(self.ctx, buf), "dft_get_schedule")
+        return {name: (buf[2 * i], buf[2 * i + 1]) for i, name in enumerate(_abi.TUNE_PASSES)}
+
+    def set_schedule(self, sched):
+        """Force launch shapes ({pass: (fp64 shape, fp32 shape)}, missing passes keep theirs)."""
+        cur = self.schedule()
+        cur.update(sched)
+        buf = (ctypes.c_int32 * _abi.SCHEDULE_LEN)()
+        for i, name in enumerate(_abi.TUNE_PASSES):
+            buf[2 * i], buf[2 * i + 1] = cur[name]
+        _abi.check(self.lib.dft_set_schedule(self.ctx, buf), "dft_set_schedule")
+
     def close(self):
         if getattr(self, "ctx", None):
             self.lib.dft_destroy(self.ctx)
