@@ -438,7 +438,7 @@ struct XTile {
     static constexpr int PB = (L % 3 == 0) ? 768 / L : 1024 / L;
     static constexpr int NTB = PB * L / 4;
     static constexpr int KX = L / 2 + 1;
-    static constexpr int PAD = 1;
+    static constexpr int PAD = 0;
 };
 
 // Element e of the full spectrum of a real row from its half spectrum (Hermitian).
@@ -485,12 +485,14 @@ __global__ __launch_bounds__(XTile<L>::NTB) void k_x2c(Geo g_in, X2Args a) {
     cx<T> vals[DFT_NALPHA][NO];
     cx<T> v[F::V];
     int ph = 0;
+    // all loads first (every field's inputs in flight together), then the transforms
+    static_assert(NO == F::template nin<1>(), "inputs and outputs share registers");
 #pragma unroll
     for (int f = 0; f < DFT_NALPHA; ++f) {
         if (f >= nf) continue;
         const cx<T> *in = reinterpret_cast<const cx<T> *>(a.specB) + (long long)f * NC;
 #pragma unroll
-        for (int i = 0; i < F::template nin<1>(); ++i) {
+        for (int i = 0; i < NO; ++i) {
             int p, e;
             const bool ok = F::template in_pos<1>(i, p, e) && p < Pact;
             cx<T> c = mk<T>(T(0), T(0));
@@ -501,8 +503,14 @@ __global__ __launch_bounds__(XTile<L>::NTB) void k_x2c(Geo g_in, X2Args a) {
                 if (r0 + 1 < rows) B = half_at<T, L>(in + (r0 + 1) * KX, e);
                 c = mk<T>(A.x - B.y, A.y + B.x);
             }
-            v[i] = c;
+            vals[f][i] = c;
         }
+    }
+#pragma unroll
+    for (int f = 0; f < DFT_NALPHA; ++f) {
+        if (f >= nf) continue;
+#pragma unroll
+        for (int i = 0; i < NO; ++i) v[i] = vals[f][i];
         F::template run<1>(v, lds, ph, tw);
 #pragma unroll
         for (int i = 0; i < NO; ++i) vals[f][i] = v[i];

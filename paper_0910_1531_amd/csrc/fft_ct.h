@@ -61,9 +61,30 @@ struct Sched {
 };
 
 // ---------------------------------------------------------------- the engine
+// XOR swizzle of the element index within an x pencil in LDS.  The radix-4 Stockham
+// writes of the first stages go to elements 4 l + q and 16 (b / 4) + b % 4 + 4 q for lanes
+// l, b; mixing bits above the bank-group width (128 bytes = 16 complex floats or 8 complex
+// doubles) into the low bits gives the lanes of one LDS access cycle distinct bank groups,
+// while contiguous reads stay contiguous.  The map is a bijection on each aligned block.
+template <typename T>
+__host__ __device__ constexpr int xswz(int e) {
+    if constexpr (sizeof(T) == 4) {
+        const int h = (e >> 4) & 3;
+        return e ^ (h | (h << 2));
+    } else {
+        return e ^ (((e >> 3) & 3) | (((e >> 4) & 1) << 2));
+    }
+}
+template <typename T>
+constexpr bool xswz_fits(int L) {
+    for (int e = 0; e < L; ++e)
+        if (xswz<T>(e) >= L) return false;
+    return true;
+}
+
 // BF = false: the pencil index varies fastest over threads and in LDS (y and z tiles,
 // whose pencils are adjacent columns in HBM).  BF = true: the element index varies fastest
-// (x tiles, whose pencils are rows); PAD pads each pencil in LDS against bank conflicts.
+// (x tiles, whose pencils are rows); elements are swizzled (xswz) against bank conflicts.
 // NB = 2 alternates two LDS buffers (one barrier per exchange); NB = 1 uses one buffer and
 // a second barrier before each write.
 template <typename T, class SC, int P, int NT, bool BF, int NB = 2, int PAD = 0>
@@ -108,7 +129,8 @@ struct Fft {
             p = j - b * P;
         }
     }
-    __device__ static __forceinline__ int lidx(int p, int e) { return BF ? p * LS + e : e * P + p; }
+    static_assert(!BF || xswz_fits<T>(L), "swizzle leaves the pencil");
+    __device__ static __forceinline__ int lidx(int p, int e) { return BF ? p * LS + xswz<T>(e) : e * P + p; }
 
     // Pencil p and element e that register i holds as an input of a first stage (or an
     // output of a last stage) of radix R; false for registers of idle butterflies.
@@ -216,18 +238,19 @@ template <> struct Plan<192> { using type = Sched<8, 8, 3>; };
 template <> struct Plan<256> { using type = Sched<8, 8, 4>; };
 template <> struct Plan<384> { using type = Sched<8, 4, 4, 3>; };
 
-// Schedules of the x passes: radices of at most 4, the first (forward) being 4, so a
-// block of L P / 4 threads holds four values of every pencil-element column it owns and
-// the values of several fields at one node stay in one thread.
+// Schedules of the x passes: radices of at most 4, the first (forward) being 4 and the
+// last 4 or 2, so a block of L P / 4 threads holds four values of every pencil-element
+// column it owns, the values of several fields at one node stay in one thread, and an
+// inverse transform starts from as many registers as it ends with.
 template <int L> struct XPlan;
 template <> struct XPlan<16> { using type = Sched<4, 4>; };
 template <> struct XPlan<24> { using type = Sched<4, 3, 2>; };
 template <> struct XPlan<32> { using type = Sched<4, 4, 2>; };
-template <> struct XPlan<48> { using type = Sched<4, 4, 3>; };
+template <> struct XPlan<48> { using type = Sched<4, 3, 4>; };
 template <> struct XPlan<64> { using type = Sched<4, 4, 4>; };
 template <> struct XPlan<96> { using type = Sched<4, 4, 3, 2>; };
 template <> struct XPlan<128> { using type = Sched<4, 4, 4, 2>; };
-template <> struct XPlan<192> { using type = Sched<4, 4, 4, 3>; };
+template <> struct XPlan<192> { using type = Sched<4, 4, 3, 4>; };
 template <> struct XPlan<256> { using type = Sched<4, 4, 4, 4>; };
 template <> struct XPlan<384> { using type = Sched<4, 4, 4, 3, 2>; };
 
