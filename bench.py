@@ -212,7 +212,7 @@ def main():
         "cpu_baseline": cpu,
         "fft_schedule": {"shapes": {k: {"fp64": v[0], "fp32": v[1]} for k, v in head["schedule"].items()},
                          "legend": "autotuned tile shape per pass; y: 0/1/2 = 16/8/32 (FP32) or 8/4/16 (FP64) "
-                                   "columns per tile; z: 0/1 = 8/4 (FP32) or 4/2 (FP64) columns per tile"},
+                                   "columns per tile; z: 0/1/2 = 8/4/16 (FP32) or 4/2/8 (FP64) columns per tile"},
     }
     print(json.dumps(line), flush=True)
 

@@ -131,19 +131,30 @@ struct Poisson {
     }
 };
 
+// Pair row of the spectral table (rows [row][z][y][kx], see Geo::tab64): K_ij, i <= j.
+__device__ __forceinline__ int pair_row(int S, int i, int j) {
+    const int a = min(i, j), b = max(i, j);
+    return 2 * S + a * S - (a * (a - 1)) / 2 + (b - a);
+}
+
 // Z1: forward z transform of every species, then per element
 //   (a) the five weighted sums of Appendix B spectra giving the ten n_alpha spectra (the
 //       vector spectra are -i k times a w3 sum), each inverse z transformed into specB;
 //   (b) with electrostatics (MS > 0 bounds S), per species i the linear electrostatic part
-//       of the exponent sum_j [C_ij(k) - z_i z_j 4 pi l_B / D(k)] (rho_hat_j - N rho_b_j
-//       delta_k0) (eqs. muESexpansion, potentialSolution), written unnormalized over
-//       rho_hat in specA (z spectral order).
-// The spectral products act on registers between the forward and inverse transforms.
+//       of the exponent sum_j K_ij(k) (rho_hat_j - N rho_b_j delta_k0), K_ij = C_ij(k) -
+//       z_i z_j 4 pi l_B / D(k) (eqs. muESexpansion, potentialSolution), written
+//       unnormalized over rho_hat in specA (z spectral order).
+// FP64 takes the spectral factors from the setup-time tables; FP32 (differences from the
+// reference) evaluates them on the fly: sin and cos of k R once per species, the pair
+// terms by the addition theorem, the Poisson denominator from the twiddle tables — in
+// FP32 that is cheaper than moving the tables.  The products act on registers between
+// the forward and inverse transforms.
 template <typename T, int L, int P, int NTB, int MS>
 __global__ __launch_bounds__(NTB) void k_z1c(Geo g_in, Z1Args a) {
     using F = ct::Fft<T, typename ct::Plan<L>::type, P, NTB, false, 2>;
     constexpr int NO = F::template nout<-1>();
     static_assert(NO == F::template nin<1>(), "inverse must start where the forward ends");
+    constexpr bool TAB = std::is_same<T, double>::value;
     constexpr int ME = MS > 0 ? MS : 1;
     const int prob = (int)blockIdx.z;
     if (prob > 0) {
@@ -156,6 +167,7 @@ __global__ __launch_bounds__(NTB) void k_z1c(Geo g_in, Z1Args a) {
     __shared__ cx<T> lds[F::LDS_ELEMS];
     const Consts &c = *g.cs;
     const int Kx = g.Kx, S = g.S;
+    const long long NC = g.NC;
     int bx, y;
     xcd_block(bx, y);
     const int kx0 = bx * P;
@@ -167,14 +179,19 @@ __global__ __launch_bounds__(NTB) void k_z1c(Geo g_in, Z1Args a) {
     const ZWave<T> kw(c, kx0, y);
     int pp[NO], ee[NO];
     bool okk[NO];
-    T kmag[NO], invD[NO];
-    constexpr int MSC = MS > 0 ? MS : 1;
-    T sn[MSC][NO], cs[MSC][NO];   // sin, cos of k R_s (electrostatic kernels only)
-    {
+    long long ti[NO];   // element offsets in a table row / spectrum
+    constexpr int NOF = TAB ? 1 : NO;             // on-the-fly factors (FP32 only)
+    constexpr int MSF = (TAB || MS == 0) ? 1 : MS;
+    T kmag[NOF], invD[NOF], sn[MSF][NOF], cs[MSF][NOF];
+#pragma unroll
+    for (int i = 0; i < NO; ++i) {
+        okk[i] = F::template out_pos<-1>(i, pp[i], ee[i]) && pp[i] < Pact;
+        ti[i] = okk[i] ? ee[i] * rs + pp[i] : 0;
+    }
+    if constexpr (!TAB) {
         const Poisson<T> pd(g, c, y);
 #pragma unroll
         for (int i = 0; i < NO; ++i) {
-            okk[i] = F::template out_pos<-1>(i, pp[i], ee[i]) && pp[i] < Pact;
             kmag[i] = kw.kmag(pp[i], ee[i]);
             invD[i] = T(0);
             if constexpr (MS > 0) {
@@ -200,12 +217,29 @@ __global__ __launch_bounds__(NTB) void k_z1c(Geo g_in, Z1Args a) {
     cx<T> v[F::V];
     int ph = 0;
     for (int jsp = 0; jsp < S; ++jsp) {
-        const cx<T> *src = reinterpret_cast<const cx<T> *>(a.specA) + (long long)jsp * g.NC + off;
+        const cx<T> *src = reinterpret_cast<const cx<T> *>(a.specA) + (long long)jsp * NC + off;
 #pragma unroll
         for (int i = 0; i < F::template nin<-1>(); ++i) {
             int p, e;
             const bool ok = F::template in_pos<-1>(i, p, e);
             v[i] = (ok && p < Pact) ? ct::gld(src + e * rs + p) : mk<T>(T(0), T(0));
+        }
+        // FP64: this species' table values, fetched before the transform hides their latency
+        constexpr int NOT = TAB ? NO : 1;
+        T w2r[NOT], w3r[NOT], kr[ME][NOT];
+        if constexpr (TAB) {
+            const double *tab = g.tab64 + off;
+            const double *t2 = tab + (long long)jsp * NC, *t3 = tab + (long long)(S + jsp) * NC;
+#pragma unroll
+            for (int i = 0; i < NO; ++i) {
+                w2r[i] = ct::gld(t2 + ti[i]);
+                w3r[i] = ct::gld(t3 + ti[i]);
+#pragma unroll
+                for (int is = 0; is < ME; ++is) {
+                    kr[is][i] = T(0);
+                    if (MS > 0 && es && is < S) kr[is][i] = ct::gld(tab + (long long)pair_row(S, is, jsp) * NC + ti[i]);
+                }
+            }
         }
         F::template run<-1>(v, lds, ph, tw);
         const T Rj = T(c.R[jsp]), a0 = T(c.i4piR2[jsp]), a1 = T(c.i4piR[jsp]);
@@ -214,7 +248,23 @@ __global__ __launch_bounds__(NTB) void k_z1c(Geo g_in, Z1Args a) {
         for (int i = 0; i < NO; ++i) {
             const cx<T> u = v[i];
             T w2, w3;
-            if constexpr (MS > 0) {
+            T ux = u.x;
+            if (MS > 0 && es && !a.diff && kw.zero(pp[i], ee[i])) ux -= bath;
+            if constexpr (TAB) {
+                w2 = w2r[i];
+                w3 = w3r[i];
+                if constexpr (MS > 0) {
+                    if (es) {
+#pragma unroll
+                        for (int is = 0; is < MS; ++is) {
+                            if (is < S) {
+                                esa[is][i].x += kr[is][i] * ux;
+                                esa[is][i].y += kr[is][i] * u.y;
+                            }
+                        }
+                    }
+                }
+            } else if constexpr (MS > 0) {
                 // sin, cos of k R_j picked with constant register indices
                 T sj = sn[0][i], cj = cs[0][i];
 #pragma unroll
@@ -222,8 +272,6 @@ __global__ __launch_bounds__(NTB) void k_z1c(Geo g_in, Z1Args a) {
                     if (is == jsp) { sj = sn[is][i]; cj = cs[is][i]; }
                 weight_w2_w3_sc<T>(kmag[i], Rj, sj, cj, w2, w3);
                 if (es) {
-                    T ux = u.x;
-                    if (!a.diff && kw.zero(pp[i], ee[i])) ux -= bath;
 #pragma unroll
                     for (int is = 0; is < MS; ++is) {
                         if (is < S) {
@@ -255,10 +303,10 @@ __global__ __launch_bounds__(NTB) void k_z1c(Geo g_in, Z1Args a) {
 #pragma unroll
             for (int is = 0; is < MS; ++is) {
                 if (is >= S) break;
-                cx<T> *dst = reinterpret_cast<cx<T> *>(a.specA) + (long long)is * g.NC + off;
+                cx<T> *dst = reinterpret_cast<cx<T> *>(a.specA) + (long long)is * NC + off;
 #pragma unroll
                 for (int i = 0; i < NO; ++i)
-                    if (okk[i]) ct::gst(dst + ee[i] * rs + pp[i], esa[is][i]);
+                    if (okk[i]) ct::gst(dst + ti[i], esa[is][i]);
             }
         }
     }
@@ -284,7 +332,7 @@ __global__ __launch_bounds__(NTB) void k_z1c(Geo g_in, Z1Args a) {
             v[i] = mk<T>(r.x * invN, r.y * invN);
         }
         F::template run<1>(v, lds, ph, tw);
-        cx<T> *dst = reinterpret_cast<cx<T> *>(a.specB) + (long long)o * g.NC + off;
+        cx<T> *dst = reinterpret_cast<cx<T> *>(a.specB) + (long long)o * NC + off;
 #pragma unroll
         for (int i = 0; i < F::template nout<1>(); ++i) {
             int p, e;
@@ -297,12 +345,13 @@ __global__ __launch_bounds__(NTB) void k_z1c(Geo g_in, Z1Args a) {
 // Z2: forward z transform of the ten dPhi/dn spectra, back-convolution with conj(w_hat)
 // (eq. muHS; the vector parts enter as +i k_d times a w3 weight), plus the electrostatic
 // spectra Z1 left in specA, times 1/N, inverse z -> specA.  Z2_POISSON instead forms the
-// potential of weighted source spectra.
+// potential of weighted source spectra.  Weights: tables in FP64, on the fly in FP32.
 template <typename T, int L, int P, int NTB>
 __global__ __launch_bounds__(NTB) void k_z2c(Geo g_in, Z2Args a) {
     using F = ct::Fft<T, typename ct::Plan<L>::type, P, NTB, false, 2>;
     constexpr int NO = F::template nout<-1>();
     static_assert(NO == F::template nin<1>(), "inverse must start where the forward ends");
+    constexpr bool TAB = std::is_same<T, double>::value;
     const int prob = (int)blockIdx.z;
     if (prob > 0) {
         const long long o = (long long)prob * g_in.pstride;
@@ -314,6 +363,7 @@ __global__ __launch_bounds__(NTB) void k_z2c(Geo g_in, Z2Args a) {
     __shared__ cx<T> lds[F::LDS_ELEMS];
     const Consts &c = *g.cs;
     const int Kx = g.Kx, S = g.S;
+    const long long NC = g.NC;
     int bx, y;
     xcd_block(bx, y);
     const int kx0 = bx * P;
@@ -324,8 +374,12 @@ __global__ __launch_bounds__(NTB) void k_z2c(Geo g_in, Z2Args a) {
     const ZWave<T> kw(c, kx0, y);
     int pp[NO], ee[NO];
     bool okk[NO];
+    long long ti[NO];
 #pragma unroll
-    for (int i = 0; i < NO; ++i) okk[i] = F::template out_pos<-1>(i, pp[i], ee[i]) && pp[i] < Pact;
+    for (int i = 0; i < NO; ++i) {
+        okk[i] = F::template out_pos<-1>(i, pp[i], ee[i]) && pp[i] < Pact;
+        ti[i] = okk[i] ? ee[i] * rs + pp[i] : 0;
+    }
     cx<T> v[F::V];
     int ph = 0;
     auto load_fwd = [&](const cx<T> *src) {
@@ -353,7 +407,7 @@ __global__ __launch_bounds__(NTB) void k_z2c(Geo g_in, Z2Args a) {
 #pragma unroll
         for (int i = 0; i < NO; ++i) acc[i][0] = acc[i][1] = 0.0;
         for (int is = 0; is < a.nsrc; ++is) {
-            load_fwd(reinterpret_cast<const cx<T> *>(a.specA) + (long long)is * g.NC + off);
+            load_fwd(reinterpret_cast<const cx<T> *>(a.specA) + (long long)is * NC + off);
             double wj = 0.0;   // a.wsrc[is] read with constant indices (no scratch copy of the arguments)
 #pragma unroll
             for (int k = 0; k < DFT_MAX_SPECIES; ++k)
@@ -382,7 +436,7 @@ __global__ __launch_bounds__(NTB) void k_z2c(Geo g_in, Z2Args a) {
 #pragma unroll
         for (int i = 0; i < NO; ++i) u[m][i] = mk<T>(T(0), T(0));
     for (int al = 0; al < DFT_NALPHA; ++al) {
-        load_fwd(reinterpret_cast<const cx<T> *>(a.specB) + (long long)al * g.NC + off);
+        load_fwd(reinterpret_cast<const cx<T> *>(a.specB) + (long long)al * NC + off);
         const int m = al < 4 ? al : (al < 7 ? 4 : 5);
         const int d = al < 4 ? 0 : (al - 4) % 3;
 #pragma unroll
@@ -398,16 +452,25 @@ __global__ __launch_bounds__(NTB) void k_z2c(Geo g_in, Z2Args a) {
         }
     }
     const T invN = T(c.invN);
-    T kmag[NO];
+    constexpr int NOF = TAB ? 1 : NO;
+    T kmag[NOF];
+    if constexpr (!TAB) {
 #pragma unroll
-    for (int i = 0; i < NO; ++i) kmag[i] = kw.kmag(pp[i], ee[i]);
+        for (int i = 0; i < NO; ++i) kmag[i] = kw.kmag(pp[i], ee[i]);
+    }
     for (int is = 0; is < S; ++is) {
         const T Ri = T(c.R[is]), a0 = T(c.i4piR2[is]), a1 = T(c.i4piR[is]);
-        const cx<T> *esrc = reinterpret_cast<const cx<T> *>(a.specA) + (long long)is * g.NC + off;
+        const cx<T> *esrc = reinterpret_cast<const cx<T> *>(a.specA) + (long long)is * NC + off;
 #pragma unroll
         for (int i = 0; i < NO; ++i) {
             T w2, w3;
-            weight_w2_w3<T>(kmag[i], Ri, w2, w3);
+            if constexpr (TAB) {
+                const double *tab = g.tab64 + off;
+                w2 = ct::gld(tab + (long long)is * NC + ti[i]);
+                w3 = ct::gld(tab + (long long)(S + is) * NC + ti[i]);
+            } else {
+                weight_w2_w3<T>(kmag[i], Ri, w2, w3);
+            }
             const T s2x = u[0][i].x * a0 + u[1][i].x * a1 + u[2][i].x;
             const T s2y = u[0][i].y * a0 + u[1][i].y * a1 + u[2][i].y;
             const T s3x = u[3][i].x + u[4][i].x * a1 + u[5][i].x;
@@ -415,13 +478,13 @@ __global__ __launch_bounds__(NTB) void k_z2c(Geo g_in, Z2Args a) {
             T ex = -(s2x * w2 + s3x * w3);
             T ey = -(s2y * w2 + s3y * w3);
             if (c.es && okk[i]) {
-                const cx<T> ev = ct::gld(esrc + ee[i] * rs + pp[i]);
+                const cx<T> ev = ct::gld(esrc + ti[i]);
                 ex += ev.x;
                 ey += ev.y;
             }
             v[i] = mk<T>(ex * invN, ey * invN);
         }
-        inv_store(reinterpret_cast<cx<T> *>(a.specA) + (long long)is * g.NC + off);
+        inv_store(reinterpret_cast<cx<T> *>(a.specA) + (long long)is * NC + off);
     }
 }
 

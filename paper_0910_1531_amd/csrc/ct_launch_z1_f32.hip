@@ -5,27 +5,37 @@
 namespace dft {
 
 template <typename T> constexpr int z_width(int v);
-template <> constexpr int z_width<float>(int v) { return v == 0 ? 8 : 4; }
-template <> constexpr int z_width<double>(int v) { return v == 0 ? 4 : 2; }
+template <> constexpr int z_width<float>(int v) { return v == 0 ? 8 : v == 1 ? 4 : 16; }
+template <> constexpr int z_width<double>(int v) { return v == 0 ? 4 : v == 1 ? 2 : 8; }
 
 template <typename T, int L, int V>
 static void launch_z1c_var(const Geo &g, const Z1Args &a, int es, hipStream_t s) {
     constexpr int P = z_width<T>(V), NTB = fit_threads(L, P, 4, 512);
     dim3 grid((unsigned)ct_cdiv(g.Kx, P), (unsigned)g.ny, (unsigned)g.nprob);
     if (!es) hipLaunchKernelGGL((k_z1c<T, L, P, NTB, 0>), grid, dim3(NTB), 0, s, g, a);
-    else hipLaunchKernelGGL((k_z1c<T, L, P, NTB, 4>), grid, dim3(NTB), 0, s, g, a);
+    else {
+        bool done = false;
+        if constexpr (std::is_same<T, float>::value) {
+            if (g.S <= 2) {
+                hipLaunchKernelGGL((k_z1c<T, L, P, NTB, 2>), grid, dim3(NTB), 0, s, g, a);
+                done = true;
+            }
+        }
+        if (!done) hipLaunchKernelGGL((k_z1c<T, L, P, NTB, 4>), grid, dim3(NTB), 0, s, g, a);
+    }
     ct_check("z1 (compiled length)");
 }
 
 template <typename T, int L>
 static void launch_z1c_len(const Geo &g, const Z1Args &a, int es, hipStream_t s, int v) {
     if (v == 1) launch_z1c_var<T, L, 1>(g, a, es, s);
+    else if (v == 2) launch_z1c_var<T, L, 2>(g, a, es, s);
     else launch_z1c_var<T, L, 0>(g, a, es, s);
 }
 
 template <>
 bool launch_z1_ct<float>(const Geo &g, const Z1Args &a, int es, hipStream_t s) {
-    if (es && g.S > 4) return false;   // electrostatic sums of more species: run-time-length kernel
+    if (!g.tab64) return false;   // no spectral tables (or S > 4 with electrostatics): run-time kernel
     const int v = g.tune[TUNE_Z1][std::is_same<float, float>::value ? 1 : 0];
     switch (g.nz) {
 #define DFT_CASE(n) case n: launch_z1c_len<float, n>(g, a, es, s, v); return true;

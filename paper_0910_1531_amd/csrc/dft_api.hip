@@ -41,6 +41,8 @@ struct HipError : std::runtime_error {
 struct Layout {
     size_t consts, state, tw64[3], tw32[3], fpart, mpart, fflag, mflag, specA, specB;
     size_t base, rho0, g0, ga, gb, gs, rho_t, rho_ref, lp, nref, phi_fix, count_part;
+    size_t tab64;
+    int ntab;
     size_t total;
     int red_cap;
     int count_blocks;
@@ -92,6 +94,8 @@ Layout make_layout(const dft_params *p) {
     } else {
         L.rho_ref = L.lp = L.nref = 0;
     }
+    L.ntab = spec_table_rows(p->n[2], S, p->electrostatics ? 1 : 0);
+    L.tab64 = L.ntab ? take(sizeof(double) * (size_t)NC * L.ntab) : 0;
     L.total = off;
     return L;
 }
@@ -483,6 +487,11 @@ dft_status dft_setup(const dft_params *params, const double *beta_vext, const do
         }
         HIPCHK(hipMemcpyAsync(c->cs, &c->hc, sizeof(Consts), hipMemcpyHostToDevice, c->stream));
         HIPCHK(hipStreamSynchronize(c->stream));
+        if (lay.ntab) {
+            g.ntab = lay.ntab;
+            g.tab64 = (const double *)(w + lay.tab64);
+            launch_spec_tables(g, c->stream);
+        }
         if (!(params->flags & DFT_FLAG_NO_AUTOTUNE)) {
             TuneBufs tb{c->specA, 2 * sizeof(double) * (size_t)g.NC * g.S, c->specB,
                         2 * sizeof(double) * (size_t)g.NC * DFT_NALPHA};

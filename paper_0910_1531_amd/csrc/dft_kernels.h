@@ -38,6 +38,11 @@ struct Geo {
     // problems whose workspaces sit pstride bytes apart (blockIdx.z carries the problem).
     int nprob = 1;
     long long pstride = 0;
+    // FP64 spectral tables of the compiled-length z kernels, [row][z][y][kx] (null: none):
+    // rows 0..S-1 w2_s(k), S..2S-1 w3_s(k), then with electrostatics the
+    // screening-minus-Coulomb kernel K_ij(k) of each pair i <= j.
+    const double *tab64 = nullptr;
+    int ntab = 0;
     // Launch shape of the compiled-length kernels per tunable pass and precision
     // ([pass][0] FP64, [pass][1] FP32); 0 is the default shape.
     int tune[4][2] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
@@ -139,6 +144,10 @@ template <typename T> bool launch_x3_ct(const Geo &g, const X3Args &a, hipStream
 int x_ct_pairs(int nx);   // row pairs per block of the compiled-length x kernels, 0 if none
 int y_ct_variants(int L, bool fp32);   // launch shapes of the y kernels of length L (0: none)
 int z_ct_variants(int L);              // launch shapes of the z kernels of length L (0: none)
+// Rows of the spectral tables for S species (0 when the compiled z kernels cannot run).
+int spec_table_rows(int nz, int S, int es);
+// Fill g.tab64 from the constants and twiddle tables.
+void launch_spec_tables(const Geo &g, hipStream_t s);
 template <typename T> void launch_z1(const Geo &g, const Z1Args &a, hipStream_t s);
 template <typename T> void launch_z2(const Geo &g, const Z2Args &a, hipStream_t s);
 template <typename T> void launch_x2(const Geo &g, const X2Args &a, hipStream_t s);

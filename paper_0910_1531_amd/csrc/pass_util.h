@@ -62,9 +62,11 @@ __device__ __forceinline__ X3Args shift(X3Args a, long long o) {
     a.e_phi = shp(a.e_phi, o); a.lp_out = shp(a.lp_out, o); a.red = shift(a.red, o); a.gate = shp(a.gate, o);
     return a;
 }
-// Geometry of problem `prob`: its constants move with its workspace; twiddles are shared.
+// Geometry of problem `prob`: its constants and spectral tables move with its workspace;
+// twiddles are shared.
 __device__ __forceinline__ Geo shift(Geo g, long long o) {
     g.cs = shp(g.cs, o);
+    g.tab64 = shp(g.tab64, o);
     return g;
 }
 

@@ -37,7 +37,7 @@ def test_every_shape_gives_the_same_residual(precision):
             sol.set_reference(torch.tensor(p.initial_density(), dtype=torch.float64, device="cuda"))
         g0, r0 = sol.residual(rho)
         g0 = g0.clone()
-        nshape = {"y": 3, "z_plain": 3, "z_weights": 2, "z_back": 2}
+        nshape = {"y": 3, "z_plain": 3, "z_weights": 3, "z_back": 3}
         for ps, nv in nshape.items():
             for v in range(1, nv):
                 for t in (0, 1):
@@ -50,7 +50,7 @@ def test_every_shape_gives_the_same_residual(precision):
                          f"{'identical' if same else 'DIFFERENT'}")
                     assert same, (name, ps, v, t)
         with pytest.raises(RuntimeError):
-            sol.set_schedule({"z_weights": (2, 0)})
+            sol.set_schedule({"z_weights": (3, 0)})
         sol.close()
 
 
