@@ -97,6 +97,73 @@ def gpu_leg(prob, precision, steps, warmup, solve_tol, profile_reps):
     return out
 
 
+def batch_leg():
+    """The 64-point batched electrolyte workload (64^3 / 96^3 / 128^3, FP32-mixed) to 1e-8."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_0910_1531_amd import _abi
+    from paper_0910_1531_amd.solver import Batch
+
+    pts = W.batch_points(count=64, seed=4)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b = Batch(pts, precision=_abi.DFT_FP32_MIXED)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    rhos = [torch.tensor(p.initial_density(), dtype=torch.float64, device="cuda") for p in pts]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its, norms, sts = b.solve(rhos, 1e-8, 2000)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    gev = sum(b.stats(i)["g_evals"] for i in range(len(pts)))
+    upd = sum(it * int(np.prod(p.n)) for it, p in zip(its, pts))
+    b.close()
+    sizes = [p.n[0] for p in pts]
+    return {"points": len(pts), "grids": {str(n): sizes.count(n) for n in sorted(set(sizes))},
+            "setup_s": round(t_setup, 3), "solve_s": round(dt, 3), "points_per_s": round(len(pts) / dt, 2),
+            "iterations": {"min": int(min(its)), "median": int(np.median(its)), "max": int(max(its)),
+                           "total": int(sum(its))},
+            "g_evals": int(gev), "grid_point_updates_per_s": round(upd / dt, 1),
+            "max_residual": float(max(norms)), "all_converged": all(s == 0 for s in sts)}
+
+
+def adjoint_leg():
+    """The 192^3 pore differentiation workload: forward solve to 1e-10, then the implicit adjoint
+    of the Ca2+ pore occupancy (gradients w.r.t. every beta V_k(x), sigma_k and rho_b,k)."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_0910_1531_amd import _abi
+    from paper_0910_1531_amd import solver as sv
+
+    p = W.config_pore(n=192, tol=1e-10)
+    out = {}
+    for name, prec in (("fp64", _abi.DFT_FP64), ("mixed", _abi.DFT_FP32_MIXED)):
+        sol = sv.from_problem(p, precision=prec)
+        x = torch.tensor(p.initial_density(), dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        it, r, st = sol.solve(x, 1e-10, 5000, raise_on_fail=False)
+        torch.cuda.synchronize()
+        out[f"forward_{name}"] = {"seconds": round(time.perf_counter() - t0, 3), "iters": it, "r": r,
+                                  "status": st}
+        if name == "fp64":
+            mask = torch.from_numpy(W.pore_observable_mask(p)).to("cuda")
+            g = torch.zeros_like(x)
+            g[0][mask] = float(np.prod(p.h))
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            adj = sol.adjoint(x, g, tol=1e-10)
+            torch.cuda.synchronize()
+            out["adjoint"] = {"seconds": round(time.perf_counter() - t0, 3), "cg_iters": adj["iters"],
+                              "resid": adj["resid"], "dO_dsigma": [float(v) for v in adj["sigma"]],
+                              "dO_drho_bulk": [float(v) for v in adj["rho_bulk"]]}
+        sol.close()
+    return out
+
+
 def cpu_baseline(evals_per_iter):
     """The oracle's rate: one residual evaluation of the same pore system at 128^3, scaled to 256^3."""
     import workloads as W
@@ -127,6 +194,8 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--profile-reps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the batched 64-point and 192^3 adjoint measurements")
     ap.add_argument("--fp64-only", action="store_true")
     ap.add_argument("--profile-only", action="store_true",
                     help="only the per-pass HIP-event profile (for rocprofv3 runs: every launch does full work)")
@@ -182,6 +251,9 @@ def main():
     f64 = legs["fp64"]
     evals_per_iter = f64["steps"]["g_evals"] / max(args.steps, 1)
     cpu = None if args.no_cpu_baseline else cpu_baseline(evals_per_iter)
+    extras = None
+    if not args.no_extras:
+        extras = {"batch_64_points_fp32_mixed": batch_leg(), "pore192_adjoint": adjoint_leg()}
 
     line = {
         "metric": METRIC,
@@ -210,6 +282,7 @@ def main():
         "eval_ms": round(eval_ms, 4),
         "eval_GBs": round(eval_gbs, 1),
         "cpu_baseline": cpu,
+        "extras": extras,
         "fft_schedule": {"shapes": {k: {"fp64": v[0], "fp32": v[1]} for k, v in head["schedule"].items()},
                          "legend": "autotuned tile shape per pass; y: 0/1/2 = 16/8/32 (FP32) or 8/4/16 (FP64) "
                                    "columns per tile; z: 0/1/2 = 8/4/16 (FP32) or 4/2/8 (FP64) columns per tile"},
