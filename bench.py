@@ -97,6 +97,42 @@ def gpu_leg(prob, precision, steps, warmup, solve_tol, profile_reps):
     return out
 
 
+def _kernel_sources_sha256():
+    import glob
+    import hashlib
+    root = os.path.dirname(os.path.abspath(__file__))
+    h = hashlib.sha256()
+    files = sorted(glob.glob(os.path.join(root, "paper_0910_1531_amd", "csrc", "*")))
+    files.append(os.path.join(root, "include", "dft.h"))
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(pass_name, fp32, n):
+    """HBM bytes per launch of the pass's kernel from the committed rocprofv3 counters
+    (profiles/traffic_pore256.txt), or None when they were taken on other kernel sources."""
+    kern = {"x_fwd": "k_x1c", "x_fmt": "k_x2c", "x_el": "k_x3c"}.get(pass_name)
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "traffic_pore256.txt")
+    if kern is None or n != 256 or not os.path.exists(path):
+        return None
+    want = f"dft::{kern}<{'float' if fp32 else 'double'}, {n}>"
+    sha, found = None, None
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("source_sha256 "):
+                sha = line.split()[1]
+            elif not line.startswith("#"):
+                parts = line.rstrip("\n").split("\t")
+                if len(parts) == 3 and parts[0] == want:
+                    found = float(parts[1]) + float(parts[2])
+    if found is None or sha != _kernel_sources_sha256():
+        return None
+    return found
+
+
 def batch_leg():
     """The 64-point batched electrolyte workload (64^3 / 96^3 / 128^3, FP32-mixed) to 1e-8."""
     import numpy as np
@@ -277,7 +313,9 @@ def main():
                              for kk, vv in v["solve"].items()} for k, v in legs.items()},
         "rho_rel_diff_mixed_vs_fp64": rho_err,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(dom, fp32, args.n), "traffic_unit": "bytes per launch",
+                     "algorithmic_bytes": pb[dom]},
         "passes": passes,
         "eval_ms": round(eval_ms, 4),
         "eval_GBs": round(eval_gbs, 1),
