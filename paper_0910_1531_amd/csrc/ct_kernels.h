@@ -593,7 +593,7 @@ __global__ __launch_bounds__(XTile<L>::NTB) void k_x2c(Geo g_in, X2Args a) {
             if (n3only) {
                 double n3 = h == 0 ? (double)vals[0][i].x : (double)vals[0][i].y;
                 if (a.nref) n3 += (double)a.nref[3 * N + idx];
-                if (!isfinite(n3)) flag |= 1;
+                if (!isfinite(n3)) flag |= 5;   // 1: evaluation non-finite, 4: n3 non-finite
                 mloc = fmax(mloc, n3);
                 continue;
             }
@@ -613,7 +613,7 @@ __global__ __launch_bounds__(XTile<L>::NTB) void k_x2c(Geo g_in, X2Args a) {
             for (int f = 0; f < DFT_NALPHA; ++f) vals[f][i].y = T(0);
         }
     }
-    if (flag & 1) mloc = INFINITY;
+    if (flag & 4) mloc = INFINITY;   // the n3 bound needs finite n3 only
     block_reduce_nt<true, NTB>(mloc, flag, a.red.mpart + blockIdx.x, a.red.mflag + blockIdx.x);
     if (n3only) return;
 #pragma unroll

@@ -56,7 +56,8 @@ struct RedBufs {
     double *fpart;   // per-block partial sums of the weighted residual (X3)
     double *mpart;   // per-block partial maxima of n3 (X2)
     int *fflag;      // per-block flags of X3: 1 = non-finite
-    int *mflag;      // per-block flags of X2: 1 = non-finite, 2 = xi^2 clamp used
+    int *mflag;      // per-block flags of X2: 1 = non-finite evaluation, 2 = xi^2 clamp used,
+                     // 4 = non-finite n3 (only then is the n3 maximum +inf)
     int cap;         // capacity of each array
 };
 

@@ -517,7 +517,7 @@ __global__ __launch_bounds__(NT) void k_x2(Geo g_in, X2Args a, int P) {
             if (n3only) {
                 double n3 = nv[0][it][h];
                 if (a.nref) n3 += (double)a.nref[3 * g.N + idx];
-                if (!isfinite(n3)) flag |= 1;
+                if (!isfinite(n3)) flag |= 5;   // 1: evaluation non-finite, 4: n3 non-finite
                 mloc = fmax(mloc, n3);
                 continue;
             }
@@ -541,7 +541,8 @@ __global__ __launch_bounds__(NT) void k_x2(Geo g_in, X2Args a, int P) {
                 fmt_dphi<double>(n, d, clamped);
             }
             if (clamped) flag |= 2;
-            if (!isfinite(n[3]) || !isfinite(d[0]) || !isfinite(d[3])) flag |= 1;
+            if (!isfinite(n[3])) flag |= 5;
+            if (!isfinite(d[0]) || !isfinite(d[3])) flag |= 1;
             mloc = fmax(mloc, n[3]);
 #pragma unroll
             for (int f = 0; f < DFT_NALPHA; ++f) {
@@ -552,7 +553,7 @@ __global__ __launch_bounds__(NT) void k_x2(Geo g_in, X2Args a, int P) {
             }
         }
     }
-    if (flag & 1) mloc = INFINITY;
+    if (flag & 4) mloc = INFINITY;   // the n3 bound needs finite n3 only
     block_reduce<true>(mloc, flag, a.red.mpart + blockIdx.x, a.red.mflag + blockIdx.x);
     if (n3only) return;
     __syncthreads();
@@ -626,7 +627,7 @@ __global__ __launch_bounds__(NTB) void k_x2b(Geo g_in, X2Args a, int PB) {
             if (n3only) {
                 double n3 = h == 0 ? (double)tile[jj].x : (double)tile[jj].y;
                 if (a.nref) n3 += (double)a.nref[3 * g.N + idx];
-                if (!isfinite(n3)) flag |= 1;
+                if (!isfinite(n3)) flag |= 5;   // 1: evaluation non-finite, 4: n3 non-finite
                 mloc = fmax(mloc, n3);
                 continue;
             }
@@ -671,7 +672,8 @@ __global__ __launch_bounds__(NTB) void k_x2b(Geo g_in, X2Args a, int PB) {
                 fmt_dphi<double>(n, d, clamped);
             }
             if (clamped) flag |= 2;
-            if (!isfinite(n[3]) || !isfinite(d[0]) || !isfinite(d[3])) flag |= 1;
+            if (!isfinite(n[3])) flag |= 5;
+            if (!isfinite(d[0]) || !isfinite(d[3])) flag |= 1;
             mloc = fmax(mloc, n[3]);
 #pragma unroll
             for (int f = 0; f < DFT_NALPHA; ++f) {
@@ -688,7 +690,7 @@ __global__ __launch_bounds__(NTB) void k_x2b(Geo g_in, X2Args a, int PB) {
             for (int f = 0; f < DFT_NALPHA; ++f) tile[f * span + jj].y = T(0);
         }
     }
-    if (flag & 1) mloc = INFINITY;
+    if (flag & 4) mloc = INFINITY;   // the n3 bound needs finite n3 only
     block_reduce_nt<true, NTB>(mloc, flag, a.red.mpart + blockIdx.x, a.red.mflag + blockIdx.x);
     if (n3only) return;
     __syncthreads();
@@ -978,7 +980,7 @@ __global__ __launch_bounds__(NT) void k_finalize(RedBufs r, int nf, int nm, doub
     if (threadIdx.x == 0) {
         const bool bad = (sf[0] & 1) || !isfinite(ss[0]);
         if (fslot) *fslot = bad ? INFINITY : ss[0];
-        if (mslot) *mslot = (sf[0] & 1) ? INFINITY : sm[0];
+        if (mslot) *mslot = (sf[0] & 4) ? INFINITY : sm[0];
         if (st) {
             if (count_kind == 1) st->gevals += 1;
             if (count_kind == 2) st->n3evals += 1;

@@ -122,8 +122,9 @@ __device__ __forceinline__ void block_reduce_nt(double v, int fl, double *dst, i
 // Pointwise work of X2 at one real node idx (of N): the ten weighted densities n in
 // (FP32-mixed: differences from the reference nref), dPhi/dn of eq. (Phi) out in d
 // (FP32-mixed: the difference from dPhi/dn at the reference; X2_HESS: the product
-// Phi''(nstar) n).  Updates the running maximum of n3 and the flags (1: non-finite,
-// 2: xi^2 clamped) and writes the optional FP64 / FP32 copies.
+// Phi''(nstar) n).  Updates the running maximum of n3 and the flags (1: the evaluation is
+// non-finite, 2: xi^2 clamped, 4: n3 itself non-finite) and writes the optional FP64 /
+// FP32 copies.
 __device__ __forceinline__ void x2_node(const X2Args &a, long long N, long long idx, const double (&nin)[DFT_NALPHA],
                                         double (&d)[DFT_NALPHA], double &mloc, int &flag) {
     double n[DFT_NALPHA];
@@ -161,7 +162,8 @@ __device__ __forceinline__ void x2_node(const X2Args &a, long long N, long long 
         fmt_dphi<double>(n, d, clamped);
     }
     if (clamped) flag |= 2;
-    if (!isfinite(n[3]) || !isfinite(d[0]) || !isfinite(d[3])) flag |= 1;
+    if (!isfinite(n[3])) flag |= 5;                        // 1: evaluation non-finite, 4: n3 non-finite
+    if (!isfinite(d[0]) || !isfinite(d[3])) flag |= 1;     // e.g. n3 >= 1: f = +inf, n3 max still valid
     mloc = fmax(mloc, n[3]);
 #pragma unroll
     for (int f = 0; f < DFT_NALPHA; ++f) {

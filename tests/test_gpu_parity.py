@@ -132,6 +132,25 @@ def test_picard_trajectory_matches_oracle(case):
         assert _rel(x.cpu().numpy(), ps.rho) < 1e-11, k
 
 
+def test_trajectory_when_the_full_step_overpacks():
+    """Dense hard spheres at a wall (packing 0.3, h = sigma / 32): the full Picard step puts
+    n3 above 1 near the wall, so dPhi/dn there is non-finite while n3 itself is finite.  The
+    n3 bound must still come from the finite n3 maximum (the trial's f is +inf), as in the
+    oracle; a non-finite maximum would freeze the line search at alpha = 0."""
+    p = W.hs_wall_nm(0.3, n=(384, 1, 1))
+    st = residual.Setup(p)
+    ps = picard.PicardState(st, p.initial_density())
+    sol = _solver(p)
+    x = _dev(p.initial_density())
+    for k in range(8):
+        a_ref = ps.step()
+        a_gpu, r_gpu = sol.picard_step(x)
+        assert a_ref > 0.0
+        assert a_gpu == pytest.approx(a_ref, rel=1e-9, abs=1e-12), k
+        assert r_gpu == pytest.approx(ps.r, rel=1e-8), k
+        assert _rel(x.cpu().numpy(), ps.rho) < 1e-11, k
+
+
 def test_solve_c1_matches_oracle():
     p = W.config_hs_wall()
     _say("solve c1")

@@ -141,6 +141,35 @@ def hard_wall(n=(32, 32, 32), h=0.2, sigma=1.0, eta=0.2, literal=False, tol=1e-1
                    beta_vext=bv, tol=tol, extra={"eta": eta, "sigma": sigma})
 
 
+def hs_wall_nm(eta, n=(384, 16, 16), h=(0.00625, 0.05, 0.05), radius=0.1, tol=1e-10) -> Problem:
+    """Hard spheres of radius 0.1 nm against a planar hard wall at x = 0, on cells of
+    0.00625 nm along the normal and 0.05 nm across it (the hard-sphere accuracy study of
+    the results section), in nm.  The contact node x = R sits on the grid when R / h_x is
+    an integer."""
+    return hard_wall(n=n, h=h, sigma=2.0 * radius, eta=eta, tol=tol)
+
+
+def electrolyte_wall(n=(24, 24, 162), box=(2.0, 2.0, 6.0), radius=(0.1, 0.2125), valence=(1.0, -1.0),
+                     conc=(1.0, 1.0), lB=None, tol=1e-10, name=None) -> Problem:
+    """1:1 electrolyte (cation radius 0.1 nm, anion 0.2125 nm, 1 M each) in a periodic
+    2 x 2 x 6 nm cell against an uncharged hard wall at z = 0 (the ionic-fluid example of
+    the results section, on a 2^a 3^b grid close to its 21 x 21 x 161).  Ion k is excluded
+    where the minimum-image distance of its centre to the plane z = 0 is below R_k."""
+    n = tuple(int(v) for v in n)
+    h = tuple(box[d] / n[d] for d in range(3))
+    R = np.asarray(radius, dtype=float)
+    S = len(R)
+    z = np.arange(n[2]) * h[2]
+    dz = np.minimum(z, box[2] - z)
+    bv = np.zeros((S, n[2], n[1], n[0]))
+    for k in range(S):
+        bv[k][dz < R[k], :, :] = np.inf
+    return Problem(name=name or f"electrolyte_wall_{n[0]}x{n[1]}x{n[2]}", n=n, h=h, radius=R,
+                   valence=np.asarray(valence, dtype=float), rho_bulk=np.array([molar(c) for c in conc]),
+                   bjerrum=bjerrum_length_nm() if lB is None else lB, electrostatics=True, beta_vext=bv,
+                   tol=tol, extra={"box": box})
+
+
 # ----------------------------------------------------------------------------- electrolytes
 
 def _on_node_charge(n, h, node, q):
