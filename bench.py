@@ -200,6 +200,46 @@ def adjoint_leg():
     return out
 
 
+def paper_workloads_leg():
+    """The paper's own examples: the hard-sphere wall study over packing fractions (contact
+    theorem error and time per solve, 384 x 16 x 16 cells of 0.00625 x 0.05 x 0.05 nm) and the
+    1 M electrolyte at a hard wall (24 x 24 x 162 for the paper's 21 x 21 x 161)."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_0910_1531_amd import _abi
+    from paper_0910_1531_amd import solver as sv
+
+    e1 = []
+    for eta in (1e-5, 1e-4, 1e-3, 1e-2, 0.1, 0.2, 0.3):
+        p = W.hs_wall_nm(eta)
+        sol = sv.from_problem(p)
+        b = sv.bulk(sol.params)
+        x = torch.tensor(p.initial_density(), dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        it, r, st = sol.solve(x, 1e-10, 5000, raise_on_fail=False)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        m = int(round(p.radius[0] / p.h[0]))
+        contact = float(x[0, 0, 0, m].item())
+        e1.append({"eta": eta, "iters": it, "seconds": round(dt, 4), "status": st,
+                   "contact_over_betaP_minus_1": contact / b["beta_p"] - 1.0})
+        sol.close()
+    p = W.electrolyte_wall()
+    e2 = {"grid": list(p.n), "box_nm": list(p.extra["box"]), "paper_minutes_other_hardware": 1.5}
+    for name, prec in (("fp64", _abi.DFT_FP64), ("mixed", _abi.DFT_FP32_MIXED)):
+        sol = sv.from_problem(p, precision=prec)
+        x = torch.tensor(p.initial_density(), dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        it, r, st = sol.solve(x, 1e-10, 5000, raise_on_fail=False)
+        torch.cuda.synchronize()
+        e2[name] = {"iters": it, "seconds": round(time.perf_counter() - t0, 4), "r": r, "status": st}
+        sol.close()
+    return {"e1_hard_sphere_wall": e1, "e2_electrolyte_wall": e2}
+
+
 def cpu_baseline(evals_per_iter):
     """The oracle's rate: one residual evaluation of the same pore system at 128^3, scaled to 256^3."""
     import workloads as W
@@ -289,7 +329,8 @@ def main():
     cpu = None if args.no_cpu_baseline else cpu_baseline(evals_per_iter)
     extras = None
     if not args.no_extras:
-        extras = {"batch_64_points_fp32_mixed": batch_leg(), "pore192_adjoint": adjoint_leg()}
+        extras = {"batch_64_points_fp32_mixed": batch_leg(), "pore192_adjoint": adjoint_leg(),
+                  "paper_workloads": paper_workloads_leg()}
 
     line = {
         "metric": METRIC,
