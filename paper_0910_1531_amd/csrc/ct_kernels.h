@@ -520,7 +520,7 @@ __device__ __forceinline__ cx<T> half_at(const cx<T> *row, int e) {
 
 // X2: ten weighted-density spectra after the y inverse -> inverse x -> pointwise dPhi/dn
 // (eq. Phi) -> forward x -> half spectra, in place in specB.
-template <typename T, int L>
+template <typename T, int L, bool D32 = false>
 __global__ __launch_bounds__(XTile<L>::NTB) void k_x2c(Geo g_in, X2Args a) {
     using XT = XTile<L>;
     constexpr int PB = XT::PB, NTB = XT::NTB, KX = XT::KX;
@@ -545,6 +545,9 @@ __global__ __launch_bounds__(XTile<L>::NTB) void k_x2c(Geo g_in, X2Args a) {
     const cx<T> *tw = twp<T>(g, 0);
     const bool n3only = a.mode == X2_N3_ONLY;
     const int nf = n3only ? 1 : DFT_NALPHA;
+    // D32 (FP32 differences from the reference, no FP64 copies asked for): the nodewise
+    // difference in FP32 (x2_node_diff); the launcher picks it.
+    static_assert(!D32 || std::is_same<T, float>::value, "FP32 difference path");
     cx<T> vals[DFT_NALPHA][NO];
     cx<T> v[F::V];
     int ph = 0;
@@ -597,14 +600,26 @@ __global__ __launch_bounds__(XTile<L>::NTB) void k_x2c(Geo g_in, X2Args a) {
                 mloc = fmax(mloc, n3);
                 continue;
             }
-            double n[DFT_NALPHA], d[DFT_NALPHA];
+            if constexpr (D32) {
+                float dn[DFT_NALPHA], dd[DFT_NALPHA];
 #pragma unroll
-            for (int f = 0; f < DFT_NALPHA; ++f) n[f] = h == 0 ? (double)vals[f][i].x : (double)vals[f][i].y;
-            x2_node(a, N, idx, n, d, mloc, flag);
+                for (int f = 0; f < DFT_NALPHA; ++f) dn[f] = h == 0 ? vals[f][i].x : vals[f][i].y;
+                x2_node_diff(a, N, idx, dn, dd, mloc, flag);
 #pragma unroll
-            for (int f = 0; f < DFT_NALPHA; ++f) {
-                if (h == 0) vals[f][i].x = T(d[f]);
-                else vals[f][i].y = T(d[f]);
+                for (int f = 0; f < DFT_NALPHA; ++f) {
+                    if (h == 0) vals[f][i].x = dd[f];
+                    else vals[f][i].y = dd[f];
+                }
+            } else {
+                double n[DFT_NALPHA], d[DFT_NALPHA];
+#pragma unroll
+                for (int f = 0; f < DFT_NALPHA; ++f) n[f] = h == 0 ? (double)vals[f][i].x : (double)vals[f][i].y;
+                x2_node(a, N, idx, n, d, mloc, flag);
+#pragma unroll
+                for (int f = 0; f < DFT_NALPHA; ++f) {
+                    if (h == 0) vals[f][i].x = T(d[f]);
+                    else vals[f][i].y = T(d[f]);
+                }
             }
         }
         if (!n3only && r0 + 1 >= rows) {

@@ -8,7 +8,16 @@ static void launch_x2c_len(const Geo &g, const X2Args &a, hipStream_t s) {
     const long long npairs = ((long long)g.ny * g.nz + 1) / 2;
     const long long nb = ct_cdiv(npairs, XTile<L>::PB);
     if (nb > a.red.cap) throw std::runtime_error("x2: reduction buffer too small");
-    hipLaunchKernelGGL((k_x2c<T, L>), dim3((unsigned)nb, 1, (unsigned)g.nprob), dim3(XTile<L>::NTB), 0, s, g, a);
+    const dim3 grid((unsigned)nb, 1, (unsigned)g.nprob);
+    bool done = false;
+    if constexpr (std::is_same<T, float>::value) {
+        // FP32 differences from the reference with no FP64 copies requested: FP32 nodewise work
+        if (a.mode == X2_FULL && a.nref && !a.n_out && !a.dphi_out && !a.nref_out) {
+            hipLaunchKernelGGL((k_x2c<T, L, true>), grid, dim3(XTile<L>::NTB), 0, s, g, a);
+            done = true;
+        }
+    }
+    if (!done) hipLaunchKernelGGL((k_x2c<T, L>), grid, dim3(XTile<L>::NTB), 0, s, g, a);
     ct_check("x2 (compiled length)");
 }
 

@@ -173,4 +173,92 @@ __device__ __forceinline__ void x2_node(const X2Args &a, long long N, long long 
     }
 }
 
+// FP32-mixed nodewise work of X2: the difference dPhi(nr + dn) - dPhi(nr) of eq. (Phi)
+// computed in FP32 term by term.  Every product is expanded by telescoping,
+// a b - ar br = (a - ar) b + ar (b - br), and every term carries one difference factor, so the
+// rounding error is proportional to |dn|, as in the FP32 transforms; log(1 - n3) enters only as
+// log1p(-dn3 / (1 - nr3)).  n3 itself (the line-search bound) is formed in FP64.  Flags and
+// the n3 maximum as x2_node.
+__device__ __forceinline__ void x2_node_diff(const X2Args &a, long long N, long long idx,
+                                             const float (&dn)[DFT_NALPHA], float (&dd)[DFT_NALPHA],
+                                             double &mloc, int &flag) {
+    float nr[DFT_NALPHA], n[DFT_NALPHA];
+#pragma unroll
+    for (int f = 0; f < DFT_NALPHA; ++f) {
+        nr[f] = a.nref[f * N + idx];
+        n[f] = nr[f] + dn[f];
+    }
+    const double n3 = (double)nr[3] + (double)dn[3];
+    const float inv8pi = (float)(1.0 / (8.0 * 3.14159265358979323846));
+    const float inv12pi = (float)(1.0 / (12.0 * 3.14159265358979323846));
+    const float inv4pi = (float)(1.0 / (4.0 * 3.14159265358979323846));
+    // 1 / (1 - n3) and its powers, with their differences
+    const float Dr = 1.0f - nr[3], D = Dr - dn[3];
+    const float iDr = 1.0f / Dr, iD = 1.0f / D;
+    const float diD = dn[3] * iD * iDr;
+    const float iD2 = iD * iD, iDr2 = iDr * iDr, diD2 = diD * (iD + iDr);
+    const float iD3 = iD2 * iD, diD3 = diD * (iD2 + iD * iDr + iDr2);
+    // vector products and the xi^2 = nV2.nV2 / n2^2 ratio, clamped at 1
+    float dot12 = 0.f, dot12r = 0.f, ddot12 = 0.f, dot22 = 0.f, dot22r = 0.f, ddot22 = 0.f;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        dot12 += n[4 + d] * n[7 + d];
+        dot12r += nr[4 + d] * nr[7 + d];
+        ddot12 += dn[4 + d] * n[7 + d] + nr[4 + d] * dn[7 + d];
+        dot22 += n[7 + d] * n[7 + d];
+        dot22r += nr[7 + d] * nr[7 + d];
+        ddot22 += dn[7 + d] * (n[7 + d] + nr[7 + d]);
+    }
+    const float tiny = 1e-30f;
+    const float n2sq = n[2] * n[2], n2sqr = nr[2] * nr[2], dn2sq = dn[2] * (n[2] + nr[2]);
+    const float den = fmaxf(n2sq, tiny), denr = fmaxf(n2sqr, tiny);
+    const float dden = (n2sq > tiny && n2sqr > tiny) ? dn2sq : den - denr;
+    const float x2 = dot22 / den, x2r = dot22r / denr;
+    float dxc;
+    if (x2 < 1.0f && x2r < 1.0f) dxc = (ddot22 * denr - dot22r * dden) / (den * denr);
+    else if (!(x2 < 1.0f) && !(x2r < 1.0f)) dxc = 0.0f;
+    else dxc = fminf(x2, 1.0f) - fminf(x2r, 1.0f);
+    const float xc = fminf(x2, 1.0f), xcr = fminf(x2r, 1.0f);
+    const float q = 1.0f - xc, qr = 1.0f - xcr, dq = -dxc;
+    const float q2 = q * q, q2r = qr * qr, dq2 = dq * (q + qr);
+    const float q3 = q2 * q, q3r = q2r * qr, dq3 = dq * (q2 + q * qr + q2r);
+    if (!(x2 < 1.0f)) flag |= 2;
+    // d0 = -log(1 - n3) + log(1 - nr3)
+    dd[0] = -log1pf(-dn[3] * iDr);
+    // d1 = n2 / D
+    dd[1] = dn[2] * iD + nr[2] * diD;
+    // d2 = n1 / D + n2^2 q^2 (1 + xi^2) / (8 pi D^2)
+    {
+        const float t1 = dn[1] * iD + nr[1] * diD;
+        const float C = 1.0f + xc, Cr = 1.0f + xcr;
+        const float t2 = dn2sq * q2 * C * iD2 + n2sqr * dq2 * C * iD2 + n2sqr * q2r * dxc * iD2 +
+                         n2sqr * q2r * Cr * diD2;
+        dd[2] = t1 + t2 * inv8pi;
+    }
+    // d3 = n0 / D + (n1 n2 - nV1.nV2) / D^2 + n2^3 q^3 / (12 pi D^3)
+    {
+        const float t1 = dn[0] * iD + nr[0] * diD;
+        const float Mr = nr[1] * nr[2] - dot12r;
+        const float dM = dn[1] * n[2] + nr[1] * dn[2] - ddot12;
+        const float t2 = dM * iD2 + Mr * diD2;
+        const float n2c = n2sq * n[2], n2cr = n2sqr * nr[2];
+        const float dn2c = dn[2] * (n2sq + n[2] * nr[2] + n2sqr);
+        const float t3 = dn2c * q3 * iD3 + n2cr * dq3 * iD3 + n2cr * q3r * diD3;
+        (void)n2c;
+        dd[3] = t1 + t2 + t3 * inv12pi;
+    }
+    // d4..6 = -nV2 / D;  d7..9 = -nV1 / D - n2 q^2 nV2 / (4 pi D^2)
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        dd[4 + d] = -(dn[7 + d] * iD + nr[7 + d] * diD);
+        const float t1 = dn[4 + d] * iD + nr[4 + d] * diD;
+        const float t2 = dn[2] * q2 * n[7 + d] * iD2 + nr[2] * dq2 * n[7 + d] * iD2 +
+                         nr[2] * q2r * dn[7 + d] * iD2 + nr[2] * q2r * nr[7 + d] * diD2;
+        dd[7 + d] = -t1 - t2 * inv4pi;
+    }
+    if (!isfinite(n3)) flag |= 5;                           // 1: evaluation non-finite, 4: n3 non-finite
+    if (!isfinite(dd[0]) || !isfinite(dd[3]) || !(D > 0.0f)) flag |= 1;
+    mloc = fmax(mloc, n3);
+}
+
 }  // namespace dft
