@@ -177,8 +177,9 @@ __device__ __forceinline__ void x2_node(const X2Args &a, long long N, long long 
 // computed in FP32 term by term.  Every product is expanded by telescoping,
 // a b - ar br = (a - ar) b + ar (b - br), and every term carries one difference factor, so the
 // rounding error is proportional to |dn|, as in the FP32 transforms; log(1 - n3) enters only as
-// log1p(-dn3 / (1 - nr3)).  n3 itself (the line-search bound) is formed in FP64.  Flags and
-// the n3 maximum as x2_node.
+// log1p(-dn3 / (1 - nr3)).  Reciprocals use the hardware's correctly rounded v_rcp (the
+// coefficients need FP32 relative accuracy only).  n3 itself (the line-search bound) is formed
+// in FP64.  Flags and the n3 maximum as x2_node.
 __device__ __forceinline__ void x2_node_diff(const X2Args &a, long long N, long long idx,
                                              const float (&dn)[DFT_NALPHA], float (&dd)[DFT_NALPHA],
                                              double &mloc, int &flag) {
@@ -194,7 +195,7 @@ __device__ __forceinline__ void x2_node_diff(const X2Args &a, long long N, long 
     const float inv4pi = (float)(1.0 / (4.0 * 3.14159265358979323846));
     // 1 / (1 - n3) and its powers, with their differences
     const float Dr = 1.0f - nr[3], D = Dr - dn[3];
-    const float iDr = 1.0f / Dr, iD = 1.0f / D;
+    const float iDr = __frcp_rn(Dr), iD = __frcp_rn(D);
     const float diD = dn[3] * iD * iDr;
     const float iD2 = iD * iD, iDr2 = iDr * iDr, diD2 = diD * (iD + iDr);
     const float iD3 = iD2 * iD, diD3 = diD * (iD2 + iD * iDr + iDr2);
@@ -213,9 +214,9 @@ __device__ __forceinline__ void x2_node_diff(const X2Args &a, long long N, long 
     const float n2sq = n[2] * n[2], n2sqr = nr[2] * nr[2], dn2sq = dn[2] * (n[2] + nr[2]);
     const float den = fmaxf(n2sq, tiny), denr = fmaxf(n2sqr, tiny);
     const float dden = (n2sq > tiny && n2sqr > tiny) ? dn2sq : den - denr;
-    const float x2 = dot22 / den, x2r = dot22r / denr;
+    const float x2 = dot22 * __frcp_rn(den), x2r = dot22r * __frcp_rn(denr);
     float dxc;
-    if (x2 < 1.0f && x2r < 1.0f) dxc = (ddot22 * denr - dot22r * dden) / (den * denr);
+    if (x2 < 1.0f && x2r < 1.0f) dxc = (ddot22 * denr - dot22r * dden) * __frcp_rn(den * denr);
     else if (!(x2 < 1.0f) && !(x2r < 1.0f)) dxc = 0.0f;
     else dxc = fminf(x2, 1.0f) - fminf(x2r, 1.0f);
     const float xc = fminf(x2, 1.0f), xcr = fminf(x2r, 1.0f);
