@@ -1,15 +1,17 @@
 // Launchers of the compiled-length y passes (and plain z transforms), with the launch
 // shapes the autotuner chooses among: P adjacent columns per tile (P complex values are
-// contiguous in HBM) and one or two LDS exchange buffers.
+// contiguous in HBM), threads per tile and one or two LDS exchange buffers.
 #include "ct_kernels.h"
 
 namespace dft {
 
-// Shape v of the y kernel for precision T: tile width.
+// Shape v of the y kernel for precision T: tile width, and values per thread (8, or 16 for
+// shapes 3 and 4: half the threads, two butterflies per thread and stage).
 template <typename T> constexpr int y_width(int v);
-template <> constexpr int y_width<float>(int v) { return v == 0 ? 16 : v == 1 ? 8 : 32; }
-template <> constexpr int y_width<double>(int v) { return v == 0 ? 8 : v == 1 ? 4 : 16; }
-constexpr int kYVariants = 3;
+template <> constexpr int y_width<float>(int v) { return (v == 0 || v == 3) ? 16 : (v == 1 || v == 4) ? 8 : 32; }
+template <> constexpr int y_width<double>(int v) { return (v == 0 || v == 3) ? 8 : (v == 1 || v == 4) ? 4 : 16; }
+constexpr int y_per_thread(int v) { return v >= 3 ? 16 : 8; }
+constexpr int kYVariants = 5;
 constexpr int kLdsCap = 65536;
 
 // LDS buffers of shape (T, L, P): 2 when two tiles fit, else 1, 0 when not even one does.
@@ -26,7 +28,7 @@ static bool launch_yc_var(const Geo &g, const YArgs &a, hipStream_t s) {
     if constexpr (NB == 0) {
         return false;
     } else {
-        constexpr int NTB = fit_threads(L, P, 8, 256);
+        constexpr int NTB = fit_threads(L, P, y_per_thread(V), 256);
         const bool zax = a.axis == 2;
         dim3 grid((unsigned)ct_cdiv(g.Kx, P), (unsigned)(zax ? g.ny : g.nz), (unsigned)(a.nfield * g.nprob));
         hipLaunchKernelGGL((k_yc<T, L, P, NTB, NB>), grid, dim3(NTB), 0, s, g, a);
@@ -40,6 +42,8 @@ static bool launch_yc_len(const Geo &g, const YArgs &a, hipStream_t s, int v) {
     switch (v) {
         case 1: if (launch_yc_var<T, L, 1>(g, a, s)) return true; break;
         case 2: if (launch_yc_var<T, L, 2>(g, a, s)) return true; break;
+        case 3: if (launch_yc_var<T, L, 3>(g, a, s)) return true; break;
+        case 4: if (launch_yc_var<T, L, 4>(g, a, s)) return true; break;
         default: break;
     }
     return launch_yc_var<T, L, 0>(g, a, s);

@@ -216,7 +216,9 @@ __device__ __forceinline__ void x2_node_diff(const X2Args &a, long long N, long 
     const float dden = (n2sq > tiny && n2sqr > tiny) ? dn2sq : den - denr;
     const float x2 = dot22 * __frcp_rn(den), x2r = dot22r * __frcp_rn(denr);
     float dxc;
-    if (x2 < 1.0f && x2r < 1.0f) dxc = (ddot22 * denr - dot22r * dden) * __frcp_rn(den * denr);
+    // x2 - x2r = (d(dot22) - x2r d(den)) / den: no product of two floored denominators, which
+    // underflows where n2 vanishes
+    if (x2 < 1.0f && x2r < 1.0f) dxc = (ddot22 - x2r * dden) * __frcp_rn(den);
     else if (!(x2 < 1.0f) && !(x2r < 1.0f)) dxc = 0.0f;
     else dxc = fminf(x2, 1.0f) - fminf(x2r, 1.0f);
     const float xc = fminf(x2, 1.0f), xcr = fminf(x2r, 1.0f);

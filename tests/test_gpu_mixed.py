@@ -80,6 +80,29 @@ def test_mixed_residual_at_reference_is_the_fp64_residual():
     assert e < 1e-8
 
 
+@pytest.mark.parametrize("n", [64, 96])
+def test_mixed_difference_is_finite_where_the_densities_vanish(n):
+    """The pore excludes most of the box, so n2 and nV2 vanish there and only FP32 noise of
+    the transforms remains; the nodewise FP32 difference of dPhi must stay finite (a product of
+    two floored n2^2 underflows) and close to the FP64 evaluation."""
+    p = W.charged_pore(n=n, h=0.025 * 256 / n)
+    d = _solver(p, _abi.DFT_FP64)
+    m = _solver(p, _abi.DFT_FP32_MIXED)
+    rho = _dev(p.initial_density())
+    d.solve(rho, 1e-6, 200, raise_on_fail=False)
+    m.set_reference(rho)
+    g = torch.Generator(device="cuda").manual_seed(7)
+    for k in range(4):
+        pert = rho * (1 + 1e-3 * (2 * torch.rand(rho.shape, generator=g, device="cuda", dtype=torch.float64) - 1))
+        Gm, rm = m.residual(pert)
+        Gd, rd = d.residual(pert)
+        e = _rel(Gm.cpu().numpy(), Gd.cpu().numpy())
+        _say(f"  pore{n} perturbation {k}: r mixed {rm:.6e} fp64 {rd:.6e}, G rel diff {e:.1e}")
+        assert np.isfinite(rm) and torch.isfinite(Gm).all()
+        assert rm == pytest.approx(rd, rel=1e-4)
+        assert e < 1e-6
+
+
 def test_run_equals_repeated_steps():
     p = W.charged_sphere(n=32, h=0.1)
     _say("dft_run vs dft_picard_step")

@@ -37,7 +37,7 @@ def test_every_shape_gives_the_same_residual(precision):
             sol.set_reference(torch.tensor(p.initial_density(), dtype=torch.float64, device="cuda"))
         g0, r0 = sol.residual(rho)
         g0 = g0.clone()
-        nshape = {"y": 3, "z_plain": 3, "z_weights": 3, "z_back": 3}
+        nshape = {"y": 5, "z_plain": 5, "z_weights": 3, "z_back": 3}
         for ps, nv in nshape.items():
             for v in range(1, nv):
                 for t in (0, 1):
