@@ -62,7 +62,7 @@ def test_tuned_solve_equals_untuned():
         sched = sol.schedule()
         _say(f"  flags {flags}: schedule {sched}")
         for v in sched.values():
-            assert 0 <= v[0] < 3 and 0 <= v[1] < 3
+            assert 0 <= v[0] < 5 and 0 <= v[1] < 5
         rho = torch.tensor(p.initial_density(), dtype=torch.float64, device="cuda")
         it, r, st = sol.solve(rho, 1e-8, 500)
         assert st == 0
