@@ -119,6 +119,8 @@ def measured_traffic(pass_name, fp32, n):
     if kern is None or n != 256 or not os.path.exists(path):
         return None
     want = f"dft::{kern}<{'float' if fp32 else 'double'}, {n}>"
+    if kern == "k_x2c":   # the FP32-mixed evaluation runs the FP32 nodewise-difference instantiation
+        want = f"dft::k_x2c<{'float' if fp32 else 'double'}, {n}, {'true' if fp32 else 'false'}>"
     sha, found = None, None
     with open(path) as fh:
         for line in fh:
