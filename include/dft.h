@@ -250,6 +250,25 @@ dft_status dft_adjoint(dft_ctx *ctx, const double *rho_star, const double *dO_dr
                        int32_t *iters_out, double *resid_out);
 
 /*
+ * Newton-Krylov solve of the fixed point rho = G(rho) (eq. rhoEquation), an alternative to
+ * the Picard iteration of the nonlinear-solver section with the exact Jacobian instead of a
+ * finite-difference one: each step solves (I - diag(G) H) d = G - rho, symmetrized as
+ * (diag(G)^-1 - H) d = (G - rho) / G on fluid nodes, by conjugate gradients preconditioned
+ * with diag(G) and started from the Picard direction G - rho, with H applied through the
+ * FP64 residual passes and the exact FMT Hessian (as dft_adjoint); the forcing term shrinks
+ * with the residual.  The step is limited to keep every density positive and backtracked
+ * until the residual norm decreases and max n3 stays below eta_cap.
+ *   rho           device [S][N], in: start, out: the last accepted iterate.
+ *   adj_ws        device workspace of dft_adjoint_workspace_size bytes, 256-byte aligned.
+ *   tol           residual target (the same norm as dft_solve); max_iter Newton steps.
+ *   iters_out, cg_iters_out, norm_out: host, may be NULL.  FP64 evaluations in any precision.
+ * Same limits as dft_adjoint (S <= 4, n_x <= 384).  Errors: DFT_E_NOT_CONVERGED (max_iter or
+ * no decrease along the step), DFT_E_NONFINITE, DFT_E_PACKING.
+ */
+dft_status dft_newton(dft_ctx *ctx, double *rho, void *adj_ws, size_t adj_ws_bytes, double tol, int32_t max_iter,
+                      int32_t *iters_out, int32_t *cg_iters_out, double *norm_out);
+
+/*
  * Batches of independent state points (different concentrations, valences, radii, grids).
  * Points of one shape (n, nspecies, precision) form a group; every pass of a residual
  * evaluation is ONE launch over all points of a group, the line-search state machines run

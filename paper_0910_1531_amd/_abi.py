@@ -78,6 +78,8 @@ SIGNATURES = [
                          ctypes.POINTER(ctypes.c_int32)]),
     ("dft_batch_destroy", [_vp]),
     ("dft_get_stats", [_vp, ctypes.POINTER(Stats)]),
+    ("dft_newton", [_vp, _vp, _vp, ctypes.c_size_t, ctypes.c_double, ctypes.c_int32,
+                    ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32), _dp]),
     ("dft_get_schedule", [_vp, ctypes.POINTER(ctypes.c_int32)]),
     ("dft_set_schedule", [_vp, ctypes.POINTER(ctypes.c_int32)]),
     ("dft_destroy", [_vp]),

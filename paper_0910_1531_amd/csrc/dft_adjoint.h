@@ -34,6 +34,11 @@ void adj_dir(long long n, double beta, const double *G, const double *r, double 
 int adj_fieldsum(long long N, int S, const double *f, double *part, hipStream_t s);
 void adj_neg(long long n, const double *w, double *out, hipStream_t s);
 void adj_reduce(const double *part, int nparts, int nv, double *out, hipStream_t s);
+// Newton-Krylov helpers: g = (G - rho) / G on fluid nodes; per-block minima of -rho / d over
+// d < 0 (returns the number of blocks); out = x + a d.
+void newton_rhs(long long n, const double *G, const double *rho, double *g, hipStream_t s);
+int newton_bound(long long n, const double *rho, const double *d, double *part, hipStream_t s);
+void axpy(long long n, const double *x, double a, const double *d, double *out, hipStream_t s);
 int adj_spec(const Geo &g, const AdjSpecArgs &a, hipStream_t s);
 
 }  // namespace dft

@@ -109,6 +109,31 @@ __global__ __launch_bounds__(NTA) void k_adj_neg(long long n, const double *w, d
     GRID_STRIDE(i, n) out[i] = -w[i];
 }
 
+// Newton right-hand side (G - rho) / G on fluid nodes (G > 0), 0 elsewhere.
+__global__ __launch_bounds__(NTA) void k_newton_rhs(long long n, const double *G, const double *rho, double *g) {
+    GRID_STRIDE(i, n) g[i] = G[i] > 0.0 ? (G[i] - rho[i]) / G[i] : 0.0;
+}
+
+// Per-block minimum of -rho / d over nodes with d < 0 (the step that would reach rho = 0).
+__global__ __launch_bounds__(NTA) void k_newton_bound(long long n, const double *rho, const double *d, double *part) {
+    __shared__ double sh[NTA];
+    double m = INFINITY;
+    GRID_STRIDE(i, n) {
+        if (d[i] < 0.0) m = fmin(m, -rho[i] / d[i]);
+    }
+    sh[threadIdx.x] = m;
+    __syncthreads();
+    for (int s = NTA / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sh[threadIdx.x] = fmin(sh[threadIdx.x], sh[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ __launch_bounds__(NTA) void k_axpy(long long n, const double *x, double a, const double *d, double *out) {
+    GRID_STRIDE(i, n) out[i] = x[i] + a * d[i];
+}
+
 // Sum nparts partial records of width nv into out[0..nv) in a fixed order.
 __global__ __launch_bounds__(NTA) void k_adj_reduce(const double *part, int nparts, int nv, double *out) {
     __shared__ double sh[NTA];
@@ -290,6 +315,23 @@ int adj_fieldsum(long long N, int S, const double *f, double *part, hipStream_t 
 void adj_neg(long long n, const double *w, double *out, hipStream_t s) {
     hipLaunchKernelGGL(k_adj_neg, dim3(nblk(n)), dim3(NTA), 0, s, n, w, out);
     check_launch_a("adj_neg");
+}
+
+void newton_rhs(long long n, const double *G, const double *rho, double *g, hipStream_t s) {
+    hipLaunchKernelGGL(k_newton_rhs, dim3(nblk(n)), dim3(NTA), 0, s, n, G, rho, g);
+    check_launch_a("newton_rhs");
+}
+
+int newton_bound(long long n, const double *rho, const double *d, double *part, hipStream_t s) {
+    const int nb = nblk(n);
+    hipLaunchKernelGGL(k_newton_bound, dim3(nb), dim3(NTA), 0, s, n, rho, d, part);
+    check_launch_a("newton_bound");
+    return nb;
+}
+
+void axpy(long long n, const double *x, double a, const double *d, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_axpy, dim3(nblk(n)), dim3(NTA), 0, s, n, x, a, d, out);
+    check_launch_a("axpy");
 }
 
 void adj_reduce(const double *part, int nparts, int nv, double *out, hipStream_t s) {

@@ -800,6 +800,8 @@ dft_status dft_profile(dft_ctx *ctx, const double *rho, int32_t reps, double *ms
 }
 
 // ------------------------------------------------------------------ implicit adjoint
+}  // extern "C"
+
 namespace {
 
 struct AdjLayout {
@@ -899,6 +901,8 @@ std::vector<double> read_scalars(dft_ctx *c, const double *dev, int n) {
 }
 
 }  // namespace
+
+extern "C" {
 
 dft_status dft_adjoint_workspace_size(const dft_params *params, size_t *bytes) {
     std::string msg;
@@ -1055,6 +1059,122 @@ dft_status dft_adjoint(dft_ctx *ctx, const double *rho_star, const double *dO_dr
             if (dO_drho_bulk) dO_drho_bulk[k] = dr;
             if (dO_dsigma) dO_dsigma[k] = 0.5 * dR;
         }
+        return DFT_OK;
+    });
+}
+
+// ------------------------------------------------------------------ Newton-Krylov
+dft_status dft_newton(dft_ctx *ctx, double *rho, void *adj_ws, size_t adj_ws_bytes, double tol, int32_t max_iter,
+                      int32_t *iters_out, int32_t *cg_iters_out, double *norm_out) {
+    if (!ctx || !rho) return fail(DFT_E_INVALID_ARG, "ctx or rho is NULL");
+    if (!(tol > 0.0) || max_iter < 0) return fail(DFT_E_INVALID_ARG, "tol must be > 0 and max_iter >= 0");
+    const AdjLayout L = adj_layout(&ctx->p);
+    if (!adj_ws || adj_ws_bytes < L.total || ((uintptr_t)adj_ws) % 256 != 0)
+        return fail(DFT_E_WORKSPACE, "Newton workspace missing, misaligned or smaller than dft_adjoint_workspace_size");
+    if (ctx->geo.S > 4) return fail(DFT_E_UNSUPPORTED_SIZE, "Newton-Krylov supports at most 4 species");
+    if ((size_t)DFT_NALPHA * ctx->geo.nx * 16 > 65536)
+        return fail(DFT_E_UNSUPPORTED_SIZE, "Newton-Krylov needs n_x <= 384 (FP64 Hessian pass)");
+    return guarded([&]() -> dft_status {
+        dft_ctx *c = ctx;
+        const Geo &g = c->geo;
+        const long long SN = (long long)g.S * g.N;
+        hipStream_t s = c->stream;
+        char *w8 = (char *)adj_ws;
+        double *nstar = (double *)(w8 + L.nstar), *G = (double *)(w8 + L.G), *rhs = (double *)(w8 + L.dphi);
+        double *d = (double *)(w8 + L.w), *r = (double *)(w8 + L.r), *p = (double *)(w8 + L.p);
+        double *q = (double *)(w8 + L.q), *Hp = (double *)(w8 + L.Hp);
+        double *part = (double *)(w8 + L.part), *scal = (double *)(w8 + L.scal);
+        double *trial = c->rho_t;
+        const double nfl = c->hc.nfluid, cap = c->hc.eta_cap;
+        c->step_rho = nullptr;   // the Picard state no longer describes the caller's density
+        // FP64 evaluation: G and n at src, f and max n3 into the state's scratch slots
+        auto evaluate = [&](const double *src, double &f, double &m) {
+            Eval e;
+            e.src = src;
+            e.g_out = G;
+            e.n_out = nstar;
+            e.fslot = &c->st->fb;
+            e.mslot = &c->st->mb;
+            e.fp64 = true;
+            e.count_kind = 0;
+            enqueue_eval(c, e, s);
+            const std::vector<double> fm = read_scalars(c, &c->st->fb, 2);
+            f = fm[0];
+            m = fm[1];
+        };
+        double f, m;
+        evaluate(rho, f, m);
+        double res = std::sqrt(f / nfl), res_prev = res;
+        int it = 0, cg_total = 0;
+        while (it < max_iter && res > tol) {
+            if (!std::isfinite(f)) return fail(DFT_E_NONFINITE, "non-finite residual at the current iterate");
+            if (!(m < cap)) return fail(DFT_E_PACKING, "max n3 reached the packing cap at the current iterate");
+            // (diag(G)^-1 - H) d = (G - rho) / G by CG preconditioned with diag(G), from the
+            // Picard direction d0 = G - rho; forcing term shrinks with the residual
+            newton_rhs(SN, G, rho, rhs, s);
+            int nb = adj_r0(SN, G, rhs, r, p, part, s);
+            adj_reduce(part, nb, 2, scal, s);
+            const double gnorm = std::sqrt(read_scalars(c, scal, 2)[1]);
+            adj_init(SN, G, rhs, d, s);
+            const double eta = std::max(1e-10, std::min(0.1, it == 0 ? 0.1 : 0.9 * (res / res_prev) * (res / res_prev)));
+            if (gnorm > 0.0) {
+                enqueue_hess(c, d, Hp, nstar, nullptr, s);
+                nb = adj_r0(SN, G, Hp, r, p, part, s);
+                adj_reduce(part, nb, 2, scal, s);
+                std::vector<double> sc = read_scalars(c, scal, 2);
+                double rz = sc[0], rel = std::sqrt(sc[1]) / gnorm;
+                for (int k = 0; k < 500 && rel > eta; ++k) {
+                    enqueue_hess(c, p, Hp, nstar, nullptr, s);
+                    nb = adj_q(SN, G, p, Hp, q, part, s);
+                    adj_reduce(part, nb, 1, scal, s);
+                    const double pq = read_scalars(c, scal, 1)[0];
+                    if (!(pq > 0.0)) break;   // not positive definite here: keep the current direction
+                    const double alpha = rz / pq;
+                    nb = adj_step(SN, alpha, G, p, q, d, r, part, s);
+                    adj_reduce(part, nb, 2, scal, s);
+                    sc = read_scalars(c, scal, 2);
+                    adj_dir(SN, sc[0] / rz, G, r, p, s);
+                    rz = sc[0];
+                    rel = std::sqrt(sc[1]) / gnorm;
+                    ++cg_total;
+                    if (!std::isfinite(rel)) return fail(DFT_E_NONFINITE, "non-finite Newton-Krylov residual");
+                }
+            }
+            // largest step keeping every density positive, then backtracking on f
+            nb = newton_bound(SN, rho, d, part, s);
+            std::vector<double> mins(nb);
+            HIPCHK(hipMemcpyAsync(mins.data(), part, sizeof(double) * nb, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            double lam_pos = INFINITY;
+            for (double v : mins) lam_pos = std::min(lam_pos, v);
+            double lam = std::min(1.0, 0.9 * lam_pos);
+            bool accepted = false;
+            for (int ls = 0; ls < 40 && lam > 0.0; ++ls) {
+                axpy(SN, rho, lam, d, trial, s);
+                double ft, mt;
+                evaluate(trial, ft, mt);
+                if (mt < cap && std::isfinite(ft) && ft <= (1.0 - 1e-4 * lam) * f) {
+                    launch_copy(rho, trial, SN, s);
+                    f = ft;
+                    m = mt;
+                    accepted = true;
+                    break;
+                }
+                lam *= 0.5;
+            }
+            if (!accepted) {
+                evaluate(rho, f, m);   // G and n of the caller's density again
+                return fail(DFT_E_NOT_CONVERGED, "Newton line search found no decrease of the residual");
+            }
+            res_prev = res;
+            res = std::sqrt(f / nfl);
+            ++it;
+        }
+        HIPCHK(hipStreamSynchronize(s));
+        if (iters_out) *iters_out = it;
+        if (cg_iters_out) *cg_iters_out = cg_total;
+        if (norm_out) *norm_out = res;
+        if (res > tol) return fail(DFT_E_NOT_CONVERGED, "Newton-Krylov reached max_iter");
         return DFT_OK;
     });
 }

@@ -200,10 +200,9 @@ __device__ __forceinline__ void x2_node_diff(const X2Args &a, long long N, long 
     const float iD2 = iD * iD, iDr2 = iDr * iDr, diD2 = diD * (iD + iDr);
     const float iD3 = iD2 * iD, diD3 = diD * (iD2 + iD * iDr + iDr2);
     // vector products and the xi^2 = nV2.nV2 / n2^2 ratio, clamped at 1
-    float dot12 = 0.f, dot12r = 0.f, ddot12 = 0.f, dot22 = 0.f, dot22r = 0.f, ddot22 = 0.f;
+    float dot12r = 0.f, ddot12 = 0.f, dot22 = 0.f, dot22r = 0.f, ddot22 = 0.f;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        dot12 += n[4 + d] * n[7 + d];
         dot12r += nr[4 + d] * nr[7 + d];
         ddot12 += dn[4 + d] * n[7 + d] + nr[4 + d] * dn[7 + d];
         dot22 += n[7 + d] * n[7 + d];
@@ -244,10 +243,9 @@ __device__ __forceinline__ void x2_node_diff(const X2Args &a, long long N, long 
         const float Mr = nr[1] * nr[2] - dot12r;
         const float dM = dn[1] * n[2] + nr[1] * dn[2] - ddot12;
         const float t2 = dM * iD2 + Mr * diD2;
-        const float n2c = n2sq * n[2], n2cr = n2sqr * nr[2];
+        const float n2cr = n2sqr * nr[2];
         const float dn2c = dn[2] * (n2sq + n[2] * nr[2] + n2sqr);
         const float t3 = dn2c * q3 * iD3 + n2cr * dq3 * iD3 + n2cr * q3r * diD3;
-        (void)n2c;
         dd[3] = t1 + t2 + t3 * inv12pi;
     }
     // d4..6 = -nV2 / D;  d7..9 = -nV1 / D - n2 q^2 nV2 / (4 pi D^2)

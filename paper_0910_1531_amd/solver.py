@@ -169,6 +169,20 @@ class Solver:
                    "dft_adjoint")
         return {"vext": dv, "rho_bulk": list(drb), "sigma": list(dsg), "iters": it.value, "resid": res.value}
 
+    def newton(self, rho, tol, max_iter=100, raise_on_fail=True):
+        """dft_newton: Newton-Krylov solve in place; returns (iterations, CG iterations, r, status)."""
+        self._check_rho(rho)
+        nbytes = ctypes.c_size_t()
+        _abi.check(self.lib.dft_adjoint_workspace_size(ctypes.byref(self.params), ctypes.byref(nbytes)),
+                   "dft_adjoint_workspace_size")
+        ws = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
+        it, cg, r = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+        st = self.lib.dft_newton(self.ctx, _ptr(rho), _ptr(ws), ws.numel(), float(tol), int(max_iter),
+                                 ctypes.byref(it), ctypes.byref(cg), ctypes.byref(r))
+        if raise_on_fail:
+            _abi.check(st, "dft_newton")
+        return it.value, cg.value, r.value, st
+
     def stats(self):
         s = _abi.Stats()
         _abi.check(self.lib.dft_get_stats(self.ctx, ctypes.byref(s)), "dft_get_stats")
