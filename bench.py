@@ -242,6 +242,25 @@ def paper_workloads_leg():
     return {"e1_hard_sphere_wall": e1, "e2_electrolyte_wall": e2}
 
 
+def newton_leg(n):
+    """Time to solution of the pore by Newton-Krylov (FP64, exact Jacobian) from the bath start."""
+    import torch
+    import workloads as W
+    from paper_0910_1531_amd import solver as sv
+
+    p = W.config_pore(n=n)
+    sol = sv.from_problem(p)
+    x = torch.tensor(p.initial_density(), dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    it, cg, r, st = sol.newton(x, 1e-8, 50, raise_on_fail=False)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    sol.close()
+    return {"workload": f"charged pore {n}^3", "tol": 1e-8, "newton_steps": it, "cg_iterations": cg,
+            "seconds": round(dt, 4), "r": r, "status": st}
+
+
 def cpu_baseline(evals_per_iter):
     """The oracle's rate: one residual evaluation of the same pore system at 128^3, scaled to 256^3."""
     import workloads as W
@@ -332,7 +351,7 @@ def main():
     extras = None
     if not args.no_extras:
         extras = {"batch_64_points_fp32_mixed": batch_leg(), "pore192_adjoint": adjoint_leg(),
-                  "paper_workloads": paper_workloads_leg()}
+                  "paper_workloads": paper_workloads_leg(), "newton_krylov_fp64": newton_leg(args.n)}
 
     line = {
         "metric": METRIC,
