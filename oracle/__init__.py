@@ -7,10 +7,12 @@ follows the paper step by step in NumPy/SciPy, using library FFTs, spherical
 Bessel functions, a root bracketer and a quadrature routine as its primitives.
 
 Modules
-  bulk      Appendix A: Percus-Yevick bulk hard-sphere mu and P, MSA Gamma.
+  bulk      Appendix A: Percus-Yevick bulk hard-sphere mu and P, MSA Gamma; the
+            BMCSL bulk of the White Bear functional.
   spectra   Appendix B weight spectra, the bulk-fluid kernel transform, k ordering.
   fmt       eq. (Phi): the anti-symmetrized Rosenfeld free-energy density and its
-            first derivatives; complex-step Hessian-vector products.
+            first derivatives; Rosenfeld's original and the White Bear forms in its
+            place; complex-step Hessian-vector products.
   residual  One residual evaluation G(rho): eqs. (nDef), (conv), (muHS),
             (potentialSolution), (muESexpansion), (rhoEquation).
   picard    Picard iteration with the quadratic line search and the n3 bound.

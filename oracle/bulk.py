@@ -9,6 +9,11 @@
   scipy's Brent solver, which reaches the same root.
 * MSA bulk electrostatic chemical potential (reporting only: it cancels in the
   bulk-fluid Euler-Lagrange exponent).
+* Boublik-Mansoori-Carnahan-Starling-Leland (BMCSL) excess free energy, pressure
+  and chemical potentials: the bulk thermodynamics of the White Bear functional
+  (oracle.fmt), which replaces the Percus-Yevick bath when that functional is used.
+  mu_i is the derivative of the free-energy density with respect to rho_i, written
+  out by hand.
 
 Units: lengths in any unit, densities in unit^-3, energies in kT.  e^2/(kT eps)
 is written 4 pi l_B with l_B the Bjerrum length in the same unit.
@@ -16,7 +21,9 @@ is written 4 pi l_B with l_B the Bjerrum length in the same unit.
 Pins (tests/test_oracle_bulk.py): one-component PY closed forms (Carnahan-free
 Percus-Yevick expressions in eta), restricted-primitive-model closed form for
 Gamma, the Debye limit Gamma -> kappa/2, and the FMT bulk consistency checks in
-the residual tests.
+the residual tests; BMCSL: one-component Carnahan-Starling closed forms,
+P = sum rho mu - f, Gibbs-Duhem, and the White Bear functional's bulk derivative
+(tests/test_oracle_fmt.py).
 """
 import math
 
@@ -46,6 +53,45 @@ def hs_mu(rho_b, sigma):
     bP = hs_pressure(rho_b, sigma)
     return (-math.log(D) + (3.0 * xi[2] * sigma + 3.0 * xi[1] * sigma ** 2) / D
             + 9.0 * xi[2] ** 2 * sigma ** 2 / (2.0 * D ** 2) + bP * math.pi * sigma ** 3 / 6.0)
+
+
+def bmcsl_free_energy(rho_b, sigma):
+    """Excess free-energy density beta f_ex of the BMCSL equation of state."""
+    xi = moments(rho_b, sigma)
+    D = 1.0 - xi[3]
+    return 6.0 / math.pi * ((xi[2] ** 3 / xi[3] ** 2 - xi[0]) * math.log(D) + 3.0 * xi[1] * xi[2] / D
+                            + xi[2] ** 3 / (xi[3] * D ** 2))
+
+
+def bmcsl_pressure(rho_b, sigma):
+    """beta P of the BMCSL equation of state (ideal part included)."""
+    xi = moments(rho_b, sigma)
+    D = 1.0 - xi[3]
+    return 6.0 / math.pi * (xi[0] / D + 3.0 * xi[1] * xi[2] / D ** 2 + (3.0 - xi[3]) * xi[2] ** 3 / D ** 3)
+
+
+def bmcsl_mu(rho_b, sigma):
+    """beta mu_ex per species: d(beta f_ex)/d(rho_i) = sum_n d(beta f_ex)/d(xi_n) (pi/6) sigma_i^n."""
+    sigma = np.asarray(sigma, float)
+    xi = moments(rho_b, sigma)
+    D = 1.0 - xi[3]
+    lD = math.log(D)
+    a0 = -lD
+    a1 = 3.0 * xi[2] / D
+    a2 = 3.0 * xi[1] / D + 3.0 * xi[2] ** 2 * (lD / xi[3] ** 2 + 1.0 / (xi[3] * D ** 2))
+    a3 = (xi[0] / D + 3.0 * xi[1] * xi[2] / D ** 2
+          + xi[2] ** 3 * (-2.0 * lD / xi[3] ** 3 - 1.0 / (xi[3] ** 2 * D) - 1.0 / (xi[3] ** 2 * D ** 2)
+                          + 2.0 / (xi[3] * D ** 3)))
+    return a0 + a1 * sigma + a2 * sigma ** 2 + a3 * sigma ** 3
+
+
+def bath(functional, rho_b, sigma):
+    """(beta mu_ex per species, beta P) of the uniform fluid of a hard-sphere functional."""
+    if functional in ("rslt", "rosenfeld"):
+        return hs_mu(rho_b, sigma), hs_pressure(rho_b, sigma)
+    if functional == "whitebear":
+        return bmcsl_mu(rho_b, sigma), bmcsl_pressure(rho_b, sigma)
+    raise ValueError(f"unknown functional {functional!r}")
 
 
 def msa_terms(gamma, rho_b, sigma, z):

@@ -15,6 +15,7 @@ sections, discretization section):
   R8  G_i = rho_b_i exp(beta mu_HS_bath_i - beta V_i + E_i) on fluid nodes, 0 elsewhere
                                                       eq. (rhoEquation) with the bath
                                                       chemical potential of Appendix A
+                                                      (BMCSL for the White Bear functional)
 
 Readings (the paper is silent or ambiguous):
   * DFT is unnormalized with exp(-i k.x); IDFT carries 1/N, so the discrete
@@ -76,8 +77,8 @@ class Setup:
         self.es = bool(prob.electrostatics) and self.lB > 0.0
         self.eta_cap = float(prob.eta_cap)
         sigma = 2.0 * self.R
-        self.mu_hs = bulk.hs_mu(self.rho_b, sigma)
-        self.betaP = bulk.hs_pressure(self.rho_b, sigma)
+        self.functional = getattr(prob, "hs_functional", "rslt")
+        self.mu_hs, self.betaP = bulk.bath(self.functional, self.rho_b, sigma)
         self.mesh = spectra.KMesh(self.n, self.h)
         self.w = [spectra.weight_spectra(R, self.mesh) for R in self.R]
         if prob.beta_vext is None:
@@ -169,7 +170,7 @@ class Setup:
         rho = np.asarray(rho, float)
         rho_hat = dft(rho)
         n = self.weighted_densities(rho, rho_hat, check)
-        d = fmt.dphi(n)
+        d = fmt.dphi(n, self.functional)
         c_hs = self.back_convolution(d, check)
         E = c_hs.copy()
         phi = np.zeros(self.shape)
@@ -206,4 +207,4 @@ class Setup:
     def free_energy_hs(self, rho):
         """F_HS = h^3 sum_x Phi(n(x)) (kT units), used to pin c_HS as its gradient."""
         n = self.weighted_densities(rho)
-        return float(np.prod(self.h) * np.sum(fmt.phi(n)))
+        return float(np.prod(self.h) * np.sum(fmt.phi(n, self.functional)))

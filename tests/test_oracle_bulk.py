@@ -50,6 +50,40 @@ def test_mixture_gibbs_duhem():
         assert dP == pytest.approx(1.0 + np.dot(rho, dmu), rel=1e-8)
 
 
+@pytest.mark.parametrize("eta", [1e-6, 0.05, 0.2, 0.3, 0.45])
+def test_one_component_bmcsl_is_carnahan_starling(eta):
+    # Carnahan-Starling: beta P / rho = (1 + eta + eta^2 - eta^3) / (1 - eta)^3,
+    # beta mu_ex = eta (8 - 9 eta + 3 eta^2) / (1 - eta)^3, beta f_ex / rho = eta (4 - 3 eta) / (1 - eta)^2.
+    sigma = 0.8
+    rho = 6 * eta / (math.pi * sigma ** 3)
+    assert bulk.bmcsl_pressure([rho], [sigma]) == pytest.approx(
+        rho * (1 + eta + eta ** 2 - eta ** 3) / (1 - eta) ** 3, rel=1e-13)
+    assert bulk.bmcsl_mu([rho], [sigma])[0] == pytest.approx(
+        eta * (8 - 9 * eta + 3 * eta ** 2) / (1 - eta) ** 3, rel=1e-9 if eta < 1e-3 else 1e-13)
+    assert bulk.bmcsl_free_energy([rho], [sigma]) == pytest.approx(
+        rho * eta * (4 - 3 * eta) / (1 - eta) ** 2, rel=1e-9 if eta < 1e-3 else 1e-13)
+
+
+def test_bmcsl_mixture_thermodynamic_identities():
+    # beta P = sum_i rho_i (1 + beta mu_ex_i) - beta f_ex, Gibbs-Duhem, and mu_i = d f_ex / d rho_i.
+    rho = np.array([0.3, 0.8, 0.1])
+    sig = np.array([1.0, 0.6, 1.4])
+    mu = bulk.bmcsl_mu(rho, sig)
+    assert bulk.bmcsl_pressure(rho, sig) == pytest.approx(
+        np.sum(rho * (1 + mu)) - bulk.bmcsl_free_energy(rho, sig), rel=1e-13)
+    for k in range(3):
+        e = np.zeros(3)
+        e[k] = 1e-6 * rho[k]
+        dP = (bulk.bmcsl_pressure(rho + e, sig) - bulk.bmcsl_pressure(rho - e, sig)) / (2 * e[k])
+        dmu = (bulk.bmcsl_mu(rho + e, sig) - bulk.bmcsl_mu(rho - e, sig)) / (2 * e[k])
+        df = (bulk.bmcsl_free_energy(rho + e, sig) - bulk.bmcsl_free_energy(rho - e, sig)) / (2 * e[k])
+        assert dP == pytest.approx(1.0 + np.dot(rho, dmu), rel=1e-8)
+        assert df == pytest.approx(mu[k], rel=1e-8)
+    # identical species reduce to one component
+    same = np.array([0.9, 0.9, 0.9])
+    assert np.allclose(bulk.bmcsl_mu(rho, same), bulk.bmcsl_mu([rho.sum()], [0.9])[0], rtol=1e-13)
+
+
 @pytest.mark.parametrize("c,sigma", [(0.1, 0.3), (1.0, 0.425), (0.01, 0.2)])
 def test_msa_gamma_restricted_primitive_closed_form(c, sigma):
     # Equal diameters, symmetric valences: eta_MSA = 0 and Gamma = (sqrt(1 + 2 kappa sigma) - 1) / (2 sigma).

@@ -1,4 +1,5 @@
-"""Pins for oracle.fmt: derivatives by complex step, bulk Percus-Yevick identities, Hessian."""
+"""Pins for oracle.fmt: derivatives by complex step, bulk Percus-Yevick / Carnahan-Starling / BMCSL
+identities, the White Bear factor's series against its closed form, Hessian."""
 import math
 
 import numpy as np
@@ -20,15 +21,17 @@ def _random_n(rng, npts, xi_big=False):
     return n
 
 
+@pytest.mark.parametrize("functional", fmt.FUNCTIONALS)
 @pytest.mark.parametrize("xi_big", [False, True])
-def test_dphi_matches_complex_step(xi_big):
+def test_dphi_matches_complex_step(xi_big, functional):
     rng = np.random.default_rng(1)
     n = _random_n(rng, 200, xi_big)
-    d = fmt.dphi(n)
+    n[3, :20] = np.linspace(-0.12, 0.12, 20)     # both sides of the White Bear series switch
+    d = fmt.dphi(n, functional)
     for a in range(10):
         e = np.zeros_like(n)
         e[a] = 1e-30
-        cs = np.imag(fmt.phi(n + 1j * e)) / 1e-30
+        cs = np.imag(fmt.phi(n + 1j * e, functional)) / 1e-30
         assert np.allclose(d[a], cs, rtol=1e-13, atol=1e-13 * np.abs(cs).max() + 1e-300), a
 
 
@@ -56,6 +59,84 @@ def test_bulk_fmt_reproduces_percus_yevick(rho, R):
     assert P == pytest.approx(bulk.hs_pressure(rho, 2 * R), rel=1e-13)
 
 
+@pytest.mark.parametrize("rho,R", [([0.38197186342], [0.5]), ([0.02, 0.05, 0.01], [0.1, 0.1, 0.181]),
+                                   ([0.3, 0.1], [0.5, 0.3]), ([1e-7], [0.5])])
+@pytest.mark.parametrize("functional", ["rosenfeld", "whitebear"])
+def test_bulk_of_the_alternative_functionals(rho, R, functional):
+    # Uniform fluid: the vector densities vanish, so Rosenfeld's original form has the same bulk as
+    # eq. (Phi) (Percus-Yevick), and the White Bear form has the BMCSL bulk: Phi(bulk n) = beta f_ex,
+    # sum_alpha dPhi/dn_alpha w_hat_alpha^i(0) = beta mu_ex_i and n0 + n.dPhi - Phi = beta P.
+    rho, R = np.asarray(rho), np.asarray(R)
+    n = fmt.bulk_weighted(rho, R)
+    d = fmt.dphi(n[:, None], functional)[:, 0]
+    mu = np.array([d[0] + d[1] * Ri + d[2] * 4 * math.pi * Ri ** 2 + d[3] * 4 * math.pi * Ri ** 3 / 3
+                   for Ri in R])
+    P = n[0] + np.dot(n, d) - fmt.phi(n[:, None], functional)[0]
+    if functional == "rosenfeld":
+        mu_ref, P_ref = bulk.hs_mu(rho, 2 * R), bulk.hs_pressure(rho, 2 * R)
+    else:
+        mu_ref, P_ref = bulk.bmcsl_mu(rho, 2 * R), bulk.bmcsl_pressure(rho, 2 * R)
+        assert fmt.phi(n[:, None], functional)[0] == pytest.approx(bulk.bmcsl_free_energy(rho, 2 * R),
+                                                                   rel=1e-12)
+    assert np.allclose(mu, mu_ref, rtol=1e-12, atol=1e-15)
+    assert P == pytest.approx(P_ref, rel=1e-12)
+
+
+@pytest.mark.parametrize("eta", [1e-6, 0.05, 0.2, 0.35, 0.45])
+def test_white_bear_one_component_is_carnahan_starling(eta):
+    # One component: beta f_ex / rho = eta (4 - 3 eta) / (1 - eta)^2,
+    # beta mu_ex = eta (8 - 9 eta + 3 eta^2) / (1 - eta)^3, beta P / rho = (1 + eta + eta^2 - eta^3) / (1 - eta)^3.
+    R = 0.37
+    rho = eta / (4 * math.pi * R ** 3 / 3)
+    n = fmt.bulk_weighted([rho], [R])
+    d = fmt.dphi(n[:, None], "whitebear")[:, 0]
+    f = fmt.phi(n[:, None], "whitebear")[0]
+    mu = d[0] + d[1] * R + d[2] * 4 * math.pi * R ** 2 + d[3] * 4 * math.pi * R ** 3 / 3
+    assert f / rho == pytest.approx(eta * (4 - 3 * eta) / (1 - eta) ** 2, rel=1e-11)
+    assert mu == pytest.approx(eta * (8 - 9 * eta + 3 * eta ** 2) / (1 - eta) ** 3, rel=1e-11)
+    assert (n[0] + np.dot(n, d) - f) / rho == pytest.approx((1 + eta + eta ** 2 - eta ** 3) / (1 - eta) ** 3,
+                                                              rel=1e-12)
+
+
+def test_white_bear_factor_series_and_closed_form_agree():
+    # Where both are accurate (0.1 <= |n3| <= 0.15: the 30-term series' remainder is below 1e-20 there
+    # and the closed form's cancellation costs f' a few hundred ulps at |n3| = 0.1), the coefficients (k+1)(k+3)/(k+2)
+    # and the closed form must give the same f and f'.  f(0) = 3/2 and f'(0) = 8/3 are the low-density
+    # limits (f -> 3/2 makes the third term Rosenfeld's at n3 -> 0).
+    x = np.concatenate([np.linspace(0.1, 0.15, 41), -np.linspace(0.1, 0.15, 41)])
+    fs, fps = fmt.wb_factor(x, series_below=1.0)
+    fc, fpc = fmt.wb_factor(x, series_below=0.0)
+    assert np.allclose(fs, fc, rtol=1e-14, atol=0)
+    assert np.allclose(fps, fpc, rtol=1e-13, atol=0)
+    f0, fp0 = fmt.wb_factor(np.array([0.0]))
+    assert f0[0] == 1.5 and fp0[0] == pytest.approx(8.0 / 3.0, rel=1e-15)
+    fr, _ = fmt._third_factor(np.array([0.0]), "rosenfeld")
+    assert fr[0] == 1.5
+
+
+@pytest.mark.parametrize("functional", ["rosenfeld", "whitebear"])
+def test_alternative_clamp_is_continuous_and_saturates(functional):
+    # Beyond |nV2| = n2 the clamped third term no longer depends on nV2; at the bound it is continuous.
+    rng = np.random.default_rng(4)
+    n = _random_n(rng, 40)
+    u = n[7:10] / np.linalg.norm(n[7:10], axis=0)
+
+    def at(scale):
+        m = n.copy()
+        m[7:10] = u * scale * n[2]
+        return fmt.phi(m, functional), fmt.dphi(m, functional)
+
+    p_in, _ = at(1.0 - 1e-9)
+    p_on, d_on = at(1.0 + 1e-9)
+    p_far, d_far = at(3.0)
+    assert np.abs(p_in - p_on).max() < 1e-7 * np.abs(p_on).max()   # a jump would not shrink with the gap
+    nv1 = n[4:7]
+    D = 1 - n[3]
+    # the vector-2 derivative keeps only its first-order part -nV1/(1 - n3); d/dn2 no longer moves with nV2
+    assert np.allclose(d_far[7:10], -nv1 / D, rtol=1e-14, atol=1e-14)
+    assert np.allclose(d_on[2], d_far[2], rtol=1e-12, atol=0)
+
+
 def test_fundamental_measures_c1():
     n = fmt.bulk_weighted([0.381971863421], [0.5])
     assert n[0] == pytest.approx(0.381971863421, abs=1e-12)
@@ -64,15 +145,16 @@ def test_fundamental_measures_c1():
     assert n[3] == pytest.approx(0.2, abs=1e-12)
 
 
-def test_hessian_vec_against_central_difference():
+@pytest.mark.parametrize("functional", fmt.FUNCTIONALS)
+def test_hessian_vec_against_central_difference(functional):
     rng = np.random.default_rng(3)
     n = _random_n(rng, 100)
     dn = rng.normal(size=n.shape) * 1e-2 * np.abs(n).max(axis=1, keepdims=True)
-    hv = fmt.hessian_vec(n, dn)
+    hv = fmt.hessian_vec(n, dn, functional=functional)
     eps = 1e-6
-    fd = (fmt.dphi(n + eps * dn) - fmt.dphi(n - eps * dn)) / (2 * eps)
+    fd = (fmt.dphi(n + eps * dn, functional) - fmt.dphi(n - eps * dn, functional)) / (2 * eps)
     assert np.allclose(hv, fd, rtol=1e-6, atol=1e-8 * np.abs(fd).max())
     # symmetry of the Hessian: u . H v = v . H u
     du = rng.normal(size=n.shape) * 1e-2
-    assert np.allclose(np.sum(du * fmt.hessian_vec(n, dn), axis=0),
-                       np.sum(dn * fmt.hessian_vec(n, du), axis=0), rtol=1e-10, atol=1e-14)
+    assert np.allclose(np.sum(du * fmt.hessian_vec(n, dn, functional=functional), axis=0),
+                       np.sum(dn * fmt.hessian_vec(n, du, functional=functional), axis=0), rtol=1e-10, atol=1e-14)

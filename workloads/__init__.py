@@ -58,6 +58,7 @@ class Problem:
     fixed_charge: np.ndarray | None = None  # [nz, ny, nx], e / unit^3
     tol: float = 1e-8
     eta_cap: float = 0.9
+    hs_functional: str = "rslt"   # "rslt" (eq. Phi), "rosenfeld" (original vector form), "whitebear"
     extra: dict = dataclasses.field(default_factory=dict)
 
     @property
