@@ -120,7 +120,7 @@ def measured_traffic(pass_name, fp32, n):
         return None
     want = f"dft::{kern}<{'float' if fp32 else 'double'}, {n}>"
     if kern == "k_x2c":   # the FP32-mixed evaluation runs the FP32 nodewise-difference instantiation
-        want = f"dft::k_x2c<{'float' if fp32 else 'double'}, {n}, {'true' if fp32 else 'false'}>"
+        want = f"dft::k_x2c<{'float' if fp32 else 'double'}, {n}, {1 if fp32 else 0}>"
     sha, found = None, None
     with open(path) as fh:
         for line in fh:
@@ -261,6 +261,33 @@ def newton_leg(n):
             "seconds": round(dt, 4), "r": r, "status": st}
 
 
+def functionals_leg(n):
+    """The pore solved to 1e-8 with each hard-sphere functional (eq. (Phi) as printed, Rosenfeld's
+    original vector form, White Bear), FP64 and FP32-mixed: the cost of the functional swap."""
+    import torch
+    import workloads as W
+    from paper_0910_1531_amd import _abi
+    from paper_0910_1531_amd import solver as sv
+
+    out = {}
+    for name in ("rslt", "rosenfeld", "whitebear"):
+        out[name] = {}
+        for pname, prec in (("fp64", _abi.DFT_FP64), ("mixed", _abi.DFT_FP32_MIXED)):
+            p = W.config_pore(n=n)
+            p.hs_functional = name
+            sol = sv.from_problem(p, precision=prec)
+            x = torch.tensor(p.initial_density(), dtype=torch.float64, device="cuda")
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            it, r, st = sol.solve(x, 1e-8, 500, raise_on_fail=False)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            out[name][pname] = {"iters": it, "seconds": round(dt, 4), "its": round(it / dt, 2), "r": r,
+                                "status": st}
+            sol.close()
+    return out
+
+
 def cpu_baseline(evals_per_iter):
     """The oracle's rate: one residual evaluation of the same pore system at 128^3, scaled to 256^3."""
     import workloads as W
@@ -292,7 +319,7 @@ def main():
     ap.add_argument("--profile-reps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the batched 64-point and 192^3 adjoint measurements")
+                    help="skip the batch, adjoint, paper-workload, Newton and functional measurements")
     ap.add_argument("--fp64-only", action="store_true")
     ap.add_argument("--profile-only", action="store_true",
                     help="only the per-pass HIP-event profile (for rocprofv3 runs: every launch does full work)")
@@ -351,7 +378,8 @@ def main():
     extras = None
     if not args.no_extras:
         extras = {"batch_64_points_fp32_mixed": batch_leg(), "pore192_adjoint": adjoint_leg(),
-                  "paper_workloads": paper_workloads_leg(), "newton_krylov_fp64": newton_leg(args.n)}
+                  "paper_workloads": paper_workloads_leg(), "newton_krylov_fp64": newton_leg(args.n),
+                  "hs_functionals": functionals_leg(args.n)}
 
     line = {
         "metric": METRIC,

@@ -67,6 +67,25 @@ typedef enum dft_precision {
                            FP64 pointwise FMT, exponent, norms and master density */
 } dft_precision;
 
+/*
+ * Hard-sphere free-energy density Phi (hard-sphere section: the scheme does not depend on
+ * which fundamental-measure functional is used).  Every choice keeps the first two terms of
+ * eq. (Phi); the third term and the bath (Appendix A) are:
+ *   DFT_HS_RSLT        n2^3 (1 - xi^2)^3 / (24 pi (1 - n3)^2), as eq. (Phi) prints it;
+ *                      Percus-Yevick bath (eqs. muHSBath, HSPressure).
+ *   DFT_HS_ROSENFELD   (n2^3 - 3 n2 nV2.nV2) / (24 pi (1 - n3)^2), Rosenfeld's original
+ *                      vector form; the same Percus-Yevick bath (vectors vanish in bulk).
+ *   DFT_HS_WHITE_BEAR  (n2^3 - 3 n2 nV2.nV2) f(n3) / (36 pi),
+ *                      f = (n3 + (1 - n3)^2 ln(1 - n3)) / (n3^2 (1 - n3)^2) (White Bear);
+ *                      Boublik-Mansoori-Carnahan-Starling-Leland (BMCSL) bath.
+ * The bound |nV2| <= n2 of Appendix C applies to all three (xi^2 <- min(xi^2, 1)).
+ */
+typedef enum dft_hs_functional {
+    DFT_HS_RSLT = 0,
+    DFT_HS_ROSENFELD = 1,
+    DFT_HS_WHITE_BEAR = 2
+} dft_hs_functional;
+
 /* Flags for dft_params.flags */
 #define DFT_FLAG_ALLOW_NON_NEUTRAL 1   /* accept a non-neutral bulk (finite-difference probes) */
 #define DFT_FLAG_CUTOFF_LAMBDA     2   /* cut the screening kernel at lambda_i + lambda_j, not R_i + R_j */
@@ -88,12 +107,13 @@ typedef struct dft_params {
     int32_t precision;                    /* dft_precision */
     double eta_cap;                       /* bound on max n3 in the line search; 0 selects 0.9 */
     int32_t flags;                        /* DFT_FLAG_* */
+    int32_t hs_functional;                /* dft_hs_functional; 0 = eq. (Phi) as printed */
 } dft_params;
 
 /* Bath quantities of Appendix A, computed on the host in FP64. */
 typedef struct dft_bulk_info {
-    double mu_hs[DFT_MAX_SPECIES];   /* beta mu_k^HS,bath (eq. muHSBath) */
-    double beta_p;                   /* beta P^HS_bath (eq. HSPressure) */
+    double mu_hs[DFT_MAX_SPECIES];   /* beta mu_k^HS,bath (eq. muHSBath; BMCSL for White Bear) */
+    double beta_p;                   /* beta P^HS_bath (eq. HSPressure; BMCSL for White Bear) */
     double xi[4];                    /* xi_0 .. xi_3 */
     double gamma;                    /* MSA Gamma (eq. Gamma), 0 without electrostatics */
     double eta_msa;                  /* MSA eta at Gamma */

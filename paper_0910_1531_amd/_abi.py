@@ -20,6 +20,8 @@ DFT_FP32_MIXED = 1
 FLAG_ALLOW_NON_NEUTRAL = 1
 FLAG_CUTOFF_LAMBDA = 2
 FLAG_NO_AUTOTUNE = 4
+HS_RSLT, HS_ROSENFELD, HS_WHITE_BEAR = 0, 1, 2
+HS_FUNCTIONALS = {"rslt": HS_RSLT, "rosenfeld": HS_ROSENFELD, "whitebear": HS_WHITE_BEAR}
 SCHEDULE_LEN = 8
 TUNE_PASSES = ["y", "z_plain", "z_weights", "z_back"]
 
@@ -30,7 +32,7 @@ class Params(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32 * 3), ("h", ctypes.c_double * 3), ("nspecies", ctypes.c_int32),
                 ("radius", D8), ("valence", D8), ("rho_bulk", D8), ("bjerrum_length", ctypes.c_double),
                 ("electrostatics", ctypes.c_int32), ("precision", ctypes.c_int32), ("eta_cap", ctypes.c_double),
-                ("flags", ctypes.c_int32)]
+                ("flags", ctypes.c_int32), ("hs_functional", ctypes.c_int32)]
 
 
 class BulkInfo(ctypes.Structure):

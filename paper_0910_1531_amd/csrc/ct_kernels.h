@@ -518,9 +518,13 @@ __device__ __forceinline__ cx<T> half_at(const cx<T> *row, int e) {
     return v;
 }
 
+// Nodewise variants of X2: FP64 eq. (Phi); FP32 differences from the reference (eq. (Phi),
+// x2_node_diff); FP64 with an alternative functional chosen by X2Args::hs.
+enum X2Node { X2N_FP64 = 0, X2N_D32 = 1, X2N_ALT = 2 };
+
 // X2: ten weighted-density spectra after the y inverse -> inverse x -> pointwise dPhi/dn
 // (eq. Phi) -> forward x -> half spectra, in place in specB.
-template <typename T, int L, bool D32 = false>
+template <typename T, int L, int NODE = X2N_FP64>
 __global__ __launch_bounds__(XTile<L>::NTB) void k_x2c(Geo g_in, X2Args a) {
     using XT = XTile<L>;
     constexpr int PB = XT::PB, NTB = XT::NTB, KX = XT::KX;
@@ -545,8 +549,9 @@ __global__ __launch_bounds__(XTile<L>::NTB) void k_x2c(Geo g_in, X2Args a) {
     const cx<T> *tw = twp<T>(g, 0);
     const bool n3only = a.mode == X2_N3_ONLY;
     const int nf = n3only ? 1 : DFT_NALPHA;
-    // D32 (FP32 differences from the reference, no FP64 copies asked for): the nodewise
+    // X2N_D32 (FP32 differences from the reference, no FP64 copies asked for): the nodewise
     // difference in FP32 (x2_node_diff); the launcher picks it.
+    constexpr bool D32 = NODE == X2N_D32;
     static_assert(!D32 || std::is_same<T, float>::value, "FP32 difference path");
     cx<T> vals[DFT_NALPHA][NO];
     cx<T> v[F::V];
@@ -614,7 +619,7 @@ __global__ __launch_bounds__(XTile<L>::NTB) void k_x2c(Geo g_in, X2Args a) {
                 double n[DFT_NALPHA], d[DFT_NALPHA];
 #pragma unroll
                 for (int f = 0; f < DFT_NALPHA; ++f) n[f] = h == 0 ? (double)vals[f][i].x : (double)vals[f][i].y;
-                x2_node(a, N, idx, n, d, mloc, flag);
+                x2_node<NODE == X2N_ALT>(a, N, idx, n, d, mloc, flag);
 #pragma unroll
                 for (int f = 0; f < DFT_NALPHA; ++f) {
                     if (h == 0) vals[f][i].x = T(d[f]);

@@ -9,15 +9,20 @@ static void launch_x2c_len(const Geo &g, const X2Args &a, hipStream_t s) {
     const long long nb = ct_cdiv(npairs, XTile<L>::PB);
     if (nb > a.red.cap) throw std::runtime_error("x2: reduction buffer too small");
     const dim3 grid((unsigned)nb, 1, (unsigned)g.nprob);
+    if (a.hs != DFT_HS_RSLT && a.mode != X2_N3_ONLY) {
+        // other functionals: FP64 nodewise work, kernels of their own (launch_x2_alt_ct)
+        if (!launch_x2_alt_ct<T>(g, a, s)) throw std::runtime_error("x2: no kernel for this functional");
+        return;
+    }
     bool done = false;
     if constexpr (std::is_same<T, float>::value) {
         // FP32 differences from the reference with no FP64 copies requested: FP32 nodewise work
         if (a.mode == X2_FULL && a.nref && !a.n_out && !a.dphi_out && !a.nref_out) {
-            hipLaunchKernelGGL((k_x2c<T, L, true>), grid, dim3(XTile<L>::NTB), 0, s, g, a);
+            hipLaunchKernelGGL((k_x2c<T, L, X2N_D32>), grid, dim3(XTile<L>::NTB), 0, s, g, a);
             done = true;
         }
     }
-    if (!done) hipLaunchKernelGGL((k_x2c<T, L>), grid, dim3(XTile<L>::NTB), 0, s, g, a);
+    if (!done) hipLaunchKernelGGL((k_x2c<T, L, X2N_FP64>), grid, dim3(XTile<L>::NTB), 0, s, g, a);
     ct_check("x2 (compiled length)");
 }
 

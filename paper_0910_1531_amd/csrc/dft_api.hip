@@ -180,6 +180,7 @@ void enqueue_eval_t(dft_ctx *c, const Eval &ev, hipStream_t s) {
     mark(ev, 4, s);
     X2Args x2{};
     x2.specB = c->specB;
+    x2.hs = c->p.hs_functional;
     x2.mode = X2_FULL;
     x2.nref = diff ? c->nref : nullptr;
     x2.nref_out = ev.refresh ? c->nref : nullptr;
@@ -250,6 +251,7 @@ void enqueue_n3_t(dft_ctx *c, const double *alpha, double *mslot, const int *gat
     launch_y<T>(g, yb, s);
     X2Args x2{};
     x2.specB = c->specB;
+    x2.hs = c->p.hs_functional;
     x2.mode = X2_N3_ONLY;
     x2.nref = diff ? c->nref : nullptr;
     x2.red = c->red;
@@ -856,6 +858,7 @@ void enqueue_hess(dft_ctx *c, const double *u, double *hu, const double *nstar, 
     launch_y<double>(g, yb, s);
     X2Args x2{};
     x2.specB = c->specB;
+    x2.hs = c->p.hs_functional;
     x2.mode = X2_HESS;
     x2.nstar = nstar;
     x2.t_out = t_out;
@@ -1183,7 +1186,7 @@ dft_status dft_newton(dft_ctx *ctx, double *rho, void *adj_ws, size_t adj_ws_byt
 struct dft_batch {
     std::vector<dft_ctx *> members;   // caller order; each owns a slice of the batch workspace
     struct Group {
-        std::vector<int> idx;         // members of one shape (n, S, precision)
+        std::vector<int> idx;         // members of one shape (n, S, precision, functional)
         dft_ctx *lead = nullptr;      // geometry covering the whole group (nprob, pstride)
         long long stride = 0;
     };
@@ -1195,7 +1198,7 @@ namespace {
 
 bool same_shape(const dft_params &a, const dft_params &b) {
     return a.n[0] == b.n[0] && a.n[1] == b.n[1] && a.n[2] == b.n[2] && a.nspecies == b.nspecies &&
-           a.precision == b.precision;
+           a.precision == b.precision && a.hs_functional == b.hs_functional;
 }
 
 // Groups (first-seen order) and the byte offset of every member in the batch workspace.

@@ -370,6 +370,8 @@ struct FmtOps<double> {
     static __device__ __forceinline__ double val(double a) { return a; }
     static __device__ __forceinline__ double cst(double a) { return a; }
     static __device__ __forceinline__ double lg(double a) { return log(a); }
+    // a scalar function g of x given g(x) and g'(x): the value (duals also carry g'(x) dx)
+    static __device__ __forceinline__ double fn(double, double g, double) { return g; }
 };
 
 // Forward-mode dual number: value and derivative along one direction.  fmt_dphi on duals
@@ -391,6 +393,7 @@ struct FmtOps<Dual> {
     static __device__ __forceinline__ double val(Dual a) { return a.v; }
     static __device__ __forceinline__ Dual cst(double a) { return {a, 0.0}; }
     static __device__ __forceinline__ Dual lg(Dual a) { return {log(a.v), a.d / a.v}; }
+    static __device__ __forceinline__ Dual fn(Dual x, double g, double gp) { return {g, gp * x.d}; }
 };
 
 template <typename D>
@@ -421,6 +424,96 @@ __device__ __forceinline__ void fmt_dphi(const D n[DFT_NALPHA], D out[DFT_NALPHA
         out[4 + d] = O::cst(0.0) - n[7 + d] * iD;
         out[7 + d] = O::cst(0.0) - n[4 + d] * iD - n[2] * q2 * n[7 + d] * iD2 * inv4pi;
     }
+}
+
+
+// ------------------------------------------------------------------ alternative Phi
+// Functionals that keep the first two terms of eq. (Phi) and replace the third by
+// (n2^3 - 3 n2 nV2.nV2) f(n3) / (36 pi): Rosenfeld's original vector form, f = 3 / (2 (1 - n3)^2),
+// and White Bear, f = (n3 + (1 - n3)^2 ln(1 - n3)) / (n3^2 (1 - n3)^2), whose bulk is the BMCSL
+// equation of state.  The bound |nV2| <= n2 is applied as nV2.nV2 <- min(nV2.nV2, n2^2).
+
+// White Bear f and its first two derivatives.  The closed forms cancel as n3 -> 0 (f -> 3/2);
+// below |n3| = 0.1 the Taylor series f = sum_k (k+1)(k+3)/(k+2) n3^k is summed instead (24 terms:
+// the remainder of f'' is below 1e-17 there).  Above, with L = ln(1 - x) and y = 1 - x:
+//   f'  = -2 L / x^3 - (x^2 - 5 x + 2) / (x^2 y^3)
+//   f'' =  6 L / x^4 + (-5 x^3 + 26 x^2 - 21 x + 6) / (x^3 y^4)
+__device__ __forceinline__ void wb_factor(double x, double &f0, double &f1, double &f2) {
+    if (fabs(x) < 0.1) {
+        double a = 0.0, b = 0.0, c = 0.0;
+#pragma unroll
+        for (int k = 23; k >= 0; --k) {
+            const double ck = (double)((k + 1) * (k + 3)) / (double)(k + 2);
+            c = c * x + 2.0 * b;   // running second derivative of the partial sum
+            b = b * x + a;
+            a = a * x + ck;
+        }
+        f0 = a;
+        f1 = b;
+        f2 = c;
+        return;
+    }
+    const double y = 1.0 - x, L = log1p(-x);
+    const double ix = 1.0 / x, iy = 1.0 / y;
+    const double ix2 = ix * ix, iy2 = iy * iy;
+    f0 = (x + y * y * L) * ix2 * iy2;
+    f1 = -2.0 * L * ix2 * ix - (x * x - 5.0 * x + 2.0) * ix2 * iy2 * iy;
+    f2 = 6.0 * L * ix2 * ix2 + (((-5.0 * x + 26.0) * x - 21.0) * x + 6.0) * ix2 * ix * iy2 * iy2;
+}
+
+// dPhi/dn of the alternative forms; hs = DFT_HS_ROSENFELD or DFT_HS_WHITE_BEAR.
+template <typename D>
+__device__ __forceinline__ void fmt_dphi_alt(int hs, const D n[DFT_NALPHA], D out[DFT_NALPHA], bool &clamped) {
+    using O = FmtOps<D>;
+    const double inv36pi = 1.0 / (36.0 * 3.14159265358979323846);
+    const D one = O::cst(1.0);
+    const D Dm = one - n[3];
+    const D iD = one / Dm;
+    const D dot12 = n[4] * n[7] + n[5] * n[8] + n[6] * n[9];
+    const D dot22 = n[7] * n[7] + n[8] * n[8] + n[9] * n[9];
+    const D n2sq = n[2] * n[2];
+    const double den = O::val(n2sq) > 1e-300 ? O::val(n2sq) : 1e-300;
+    clamped = !(O::val(dot22) / den < 1.0);
+    const D g = clamped ? n2sq : dot22;   // nV2.nV2 after the bound
+    D f, fp;
+    if (hs == DFT_HS_WHITE_BEAR) {
+        double f0, f1, f2;
+        wb_factor(O::val(n[3]), f0, f1, f2);
+        f = O::fn(n[3], f0, f1);
+        fp = O::fn(n[3], f1, f2);
+    } else {
+        const D iD2 = iD * iD;
+        f = iD2 * 1.5;
+        fp = iD2 * iD * 3.0;
+    }
+    // d/dn2 of (n2^3 - 3 n2 g): 3 n2^2 - 3 g, or -6 n2^2 where g = n2^2 (bound active)
+    const D dn2 = clamped ? n2sq * (-6.0) : (n2sq - g) * 3.0;
+    const D third = n[2] * (n2sq - g * 3.0);
+    out[0] = O::cst(0.0) - O::lg(Dm);
+    out[1] = n[2] * iD;
+    out[2] = n[1] * iD + dn2 * f * inv36pi;
+    out[3] = n[0] * iD + (n[1] * n[2] - dot12) * iD * iD + third * fp * inv36pi;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        out[4 + d] = O::cst(0.0) - n[7 + d] * iD;
+        out[7 + d] = O::cst(0.0) - n[4 + d] * iD;
+        if (!clamped) out[7 + d] = out[7 + d] - n[2] * n[7 + d] * f * (6.0 * inv36pi);
+    }
+}
+
+// dPhi/dn of the functional hs (dft_hs_functional), chosen at run time.
+template <typename D>
+__device__ __forceinline__ void fmt_dphi_sel(int hs, const D n[DFT_NALPHA], D out[DFT_NALPHA], bool &clamped) {
+    if (hs == DFT_HS_RSLT) fmt_dphi<D>(n, out, clamped);
+    else fmt_dphi_alt<D>(hs, n, out, clamped);
+}
+
+// Compile-time choice for kernels instantiated per family: ALT = false compiles eq. (Phi) only,
+// ALT = true the alternative forms only (hs picks between them).
+template <bool ALT, typename D>
+__device__ __forceinline__ void fmt_dphi_as(int hs, const D n[DFT_NALPHA], D out[DFT_NALPHA], bool &clamped) {
+    if constexpr (ALT) fmt_dphi_alt<D>(hs, n, out, clamped);
+    else fmt_dphi<D>(n, out, clamped);
 }
 
 }  // namespace dft

@@ -62,6 +62,11 @@ dft_status validate(const dft_params *p, std::string *msg) {
         *msg = "unknown bits in flags";
         return DFT_E_INVALID_ARG;
     }
+    if (p->hs_functional != DFT_HS_RSLT && p->hs_functional != DFT_HS_ROSENFELD &&
+        p->hs_functional != DFT_HS_WHITE_BEAR) {
+        *msg = "hs_functional must be DFT_HS_RSLT, DFT_HS_ROSENFELD or DFT_HS_WHITE_BEAR";
+        return DFT_E_INVALID_ARG;
+    }
     if (!(p->eta_cap >= 0.0 && p->eta_cap < 1.0)) {
         *msg = "eta_cap must lie in [0, 1) (0 selects 0.9)";
         return DFT_E_INVALID_ARG;
@@ -129,6 +134,53 @@ Msa msa_eval(double g, int S, const double *rho, const double *sig, const double
 
 }  // namespace
 
+namespace {
+
+// Hard-sphere bath of the selected functional: beta mu_i^HS for i < S and beta P^HS, from the
+// moments xi_n = pi/6 sum_k rho_k sigma_k^n.  C is double or std::complex<double> (complex
+// steps of the bath derivatives).
+//   Percus-Yevick (eqs. muHSBath, HSPressure; the bulk of eq. (Phi) and of Rosenfeld's form).
+//   BMCSL (White Bear bulk): beta f = 6/pi [(xi2^3/xi3^2 - xi0) ln D + 3 xi1 xi2/D + xi2^3/(xi3 D^2)],
+//   beta P = 6/pi [xi0/D + 3 xi1 xi2/D^2 + (3 - xi3) xi2^3/D^3], mu_i = d(beta f)/d(rho_i)
+//   = sum_n a_n sigma_i^n with the a_n below (D = 1 - xi3).
+template <typename C>
+void hs_bath(int hs, int S, const C *rho, const C *sig, C *mu, C *bP) {
+    C xi[4];
+    for (int n = 0; n < 4; ++n) {
+        C sum = 0.0;
+        for (int k = 0; k < S; ++k) {
+            C pw = 1.0;
+            for (int m = 0; m < n; ++m) pw *= sig[k];
+            sum += rho[k] * pw;
+        }
+        xi[n] = M_PI / 6.0 * sum;
+    }
+    const C D = 1.0 - xi[3];
+    const C lD = std::log(D);
+    if (hs == DFT_HS_WHITE_BEAR) {
+        *bP = 6.0 / M_PI * (xi[0] / D + 3.0 * xi[1] * xi[2] / (D * D) + (3.0 - xi[3]) * xi[2] * xi[2] * xi[2] / (D * D * D));
+        const C x2 = xi[2] * xi[2], x3 = xi[3];
+        const C a1 = 3.0 * xi[2] / D;
+        const C a2 = 3.0 * xi[1] / D + 3.0 * x2 * (lD / (x3 * x3) + 1.0 / (x3 * D * D));
+        const C a3 = xi[0] / D + 3.0 * xi[1] * xi[2] / (D * D) +
+                     x2 * xi[2] * (-2.0 * lD / (x3 * x3 * x3) - 1.0 / (x3 * x3 * D) - 1.0 / (x3 * x3 * D * D) +
+                                   2.0 / (x3 * D * D * D));
+        for (int i = 0; i < S; ++i) {
+            const C s = sig[i];
+            mu[i] = -lD + s * (a1 + s * (a2 + s * a3));
+        }
+        return;
+    }
+    *bP = 6.0 / M_PI * (xi[0] / D + 3.0 * xi[1] * xi[2] / (D * D) + 3.0 * xi[2] * xi[2] * xi[2] / (D * D * D));
+    for (int i = 0; i < S; ++i) {
+        const C s = sig[i];
+        mu[i] = -lD + (3.0 * xi[2] * s + 3.0 * xi[1] * s * s) / D + 9.0 * xi[2] * xi[2] * s * s / (2.0 * D * D) +
+                *bP * M_PI * s * s * s / 6.0;
+    }
+}
+
+}  // namespace
+
 dft_status bulk_info(const dft_params *p, dft_bulk_info *out, std::string *msg) {
     dft_status st = validate(p, msg);
     if (st != DFT_OK) return st;
@@ -143,13 +195,7 @@ dft_status bulk_info(const dft_params *p, dft_bulk_info *out, std::string *msg) 
         out->xi[n] = M_PI / 6.0 * s;
     }
     const double D = 1.0 - out->xi[3];
-    const double *xi = out->xi;
-    out->beta_p = 6.0 / M_PI * (xi[0] / D + 3.0 * xi[1] * xi[2] / (D * D) + 3.0 * xi[2] * xi[2] * xi[2] / (D * D * D));
-    for (int k = 0; k < S; ++k) {
-        const double s = sig[k];
-        out->mu_hs[k] = -std::log(D) + (3.0 * xi[2] * s + 3.0 * xi[1] * s * s) / D +
-                        9.0 * xi[2] * xi[2] * s * s / (2.0 * D * D) + out->beta_p * M_PI * s * s * s / 6.0;
-    }
+    hs_bath<double>(p->hs_functional, S, p->rho_bulk, sig, out->mu_hs, &out->beta_p);
     if (!p->electrostatics) return DFT_OK;
     const double lB = p->bjerrum_length;
     double kap2 = 0;
@@ -185,21 +231,6 @@ dft_status bulk_info(const dft_params *p, dft_bulk_info *out, std::string *msg) 
 namespace {
 
 using cd = std::complex<double>;
-
-// beta mu_i^HS,bath (eq. muHSBath) for complex-step arguments.
-cd mu_hs_c(int i, int S, const cd *rho, const cd *sig) {
-    cd xi[4];
-    for (int n = 0; n < 4; ++n) {
-        cd sum = 0.0;
-        for (int k = 0; k < S; ++k) sum += rho[k] * std::pow(sig[k], n);
-        xi[n] = M_PI / 6.0 * sum;
-    }
-    const cd D = 1.0 - xi[3];
-    const cd bP = 6.0 / M_PI * (xi[0] / D + 3.0 * xi[1] * xi[2] / (D * D) + 3.0 * xi[2] * xi[2] * xi[2] / (D * D * D));
-    const cd s = sig[i];
-    return -std::log(D) + (3.0 * xi[2] * s + 3.0 * xi[1] * s * s) / D + 9.0 * xi[2] * xi[2] * s * s / (2.0 * D * D) +
-           bP * M_PI * s * s * s / 6.0;
-}
 
 // F(Gamma) of eq. (Gamma) for complex-step arguments.
 cd msa_F_c(cd g, int S, const cd *rho, const cd *sig, const double *z, double lB) {
@@ -245,8 +276,10 @@ void bulk_derivatives(const dft_params *p, const dft_bulk_info &b, BulkDeriv *ou
             reset();
             if (which == 0) rho[k] += cd(0.0, hstep);
             else sig[k] += cd(0.0, hstep);
+            cd mu[DFT_MAX_SPECIES], bP;
+            hs_bath<cd>(p->hs_functional, S, rho, sig, mu, &bP);
             for (int i = 0; i < S; ++i) {
-                const double d = std::imag(mu_hs_c(i, S, rho, sig)) / hstep;
+                const double d = std::imag(mu[i]) / hstep;
                 if (which == 0) out->dmu_drho[i][k] = d;
                 else out->dmu_dsigma[i][k] = d;
             }

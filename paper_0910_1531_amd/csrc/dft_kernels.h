@@ -112,6 +112,7 @@ struct X2Args {
     double *dphi_out;         // [10][N], may be null
     const double *nstar;      // X2_HESS: weighted densities of the expansion point [10][N] (FP64)
     double *t_out;            // X2_HESS: Phi''(nstar) n written as [10][N] FP64, may be null
+    int hs;                   // dft_hs_functional (the FP32 difference form covers DFT_HS_RSLT only)
     RedBufs red;
     const int *gate;
 };
@@ -140,6 +141,7 @@ template <typename T> bool launch_y_ct(const Geo &g, const YArgs &a, hipStream_t
 template <typename T> bool launch_z1_ct(const Geo &g, const Z1Args &a, int es, hipStream_t s);
 template <typename T> bool launch_z2_ct(const Geo &g, const Z2Args &a, hipStream_t s);
 template <typename T> bool launch_x2_ct(const Geo &g, const X2Args &a, hipStream_t s);
+template <typename T> bool launch_x2_alt_ct(const Geo &g, const X2Args &a, hipStream_t s);
 template <typename T> bool launch_x1_ct(const Geo &g, const XFwdArgs &a, hipStream_t s);
 template <typename T> bool launch_x3_ct(const Geo &g, const X3Args &a, hipStream_t s);
 int x_ct_pairs(int nx);   // row pairs per block of the compiled-length x kernels, 0 if none

@@ -533,12 +533,12 @@ __global__ __launch_bounds__(NT) void k_x2(Geo g_in, X2Args a, int P) {
                     n[f] += nr[f];
                 }
                 bool c2;
-                fmt_dphi<double>(n, d, clamped);
-                fmt_dphi<double>(nr, dr, c2);
+                fmt_dphi_sel<double>(a.hs, n, d, clamped);
+                fmt_dphi_sel<double>(a.hs, nr, dr, c2);
 #pragma unroll
                 for (int f = 0; f < DFT_NALPHA; ++f) d[f] -= dr[f];
             } else {
-                fmt_dphi<double>(n, d, clamped);
+                fmt_dphi_sel<double>(a.hs, n, d, clamped);
             }
             if (clamped) flag |= 2;
             if (!isfinite(n[3])) flag |= 5;
@@ -643,7 +643,7 @@ __global__ __launch_bounds__(NTB) void k_x2b(Geo g_in, X2Args a, int PB) {
                 Dual nd[DFT_NALPHA], dd[DFT_NALPHA];
 #pragma unroll
                 for (int f = 0; f < DFT_NALPHA; ++f) nd[f] = Dual{a.nstar[f * g.N + idx], n[f]};
-                fmt_dphi<Dual>(nd, dd, clamped);
+                fmt_dphi_sel<Dual>(a.hs, nd, dd, clamped);
                 bool bad = false;
 #pragma unroll
                 for (int f = 0; f < DFT_NALPHA; ++f) {
@@ -664,12 +664,12 @@ __global__ __launch_bounds__(NTB) void k_x2b(Geo g_in, X2Args a, int PB) {
                     n[f] += nr[f];
                 }
                 bool c2;
-                fmt_dphi<double>(n, d, clamped);
-                fmt_dphi<double>(nr, dr, c2);
+                fmt_dphi_sel<double>(a.hs, n, d, clamped);
+                fmt_dphi_sel<double>(a.hs, nr, dr, c2);
 #pragma unroll
                 for (int f = 0; f < DFT_NALPHA; ++f) d[f] -= dr[f];
             } else {
-                fmt_dphi<double>(n, d, clamped);
+                fmt_dphi_sel<double>(a.hs, n, d, clamped);
             }
             if (clamped) flag |= 2;
             if (!isfinite(n[3])) flag |= 5;

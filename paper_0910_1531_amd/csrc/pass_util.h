@@ -119,12 +119,14 @@ __device__ __forceinline__ void block_reduce_nt(double v, int fl, double *dst, i
 }
 
 // ------------------------------------------------------------------ X2 node work
-// Pointwise work of X2 at one real node idx (of N): the ten weighted densities n in
+// Pointwise work of X2 at one real node idx (of N), for eq. (Phi) (ALT = false) or the
+// alternative functional a.hs (ALT = true): the ten weighted densities n in
 // (FP32-mixed: differences from the reference nref), dPhi/dn of eq. (Phi) out in d
 // (FP32-mixed: the difference from dPhi/dn at the reference; X2_HESS: the product
 // Phi''(nstar) n).  Updates the running maximum of n3 and the flags (1: the evaluation is
 // non-finite, 2: xi^2 clamped, 4: n3 itself non-finite) and writes the optional FP64 /
 // FP32 copies.
+template <bool ALT>
 __device__ __forceinline__ void x2_node(const X2Args &a, long long N, long long idx, const double (&nin)[DFT_NALPHA],
                                         double (&d)[DFT_NALPHA], double &mloc, int &flag) {
     double n[DFT_NALPHA];
@@ -135,7 +137,7 @@ __device__ __forceinline__ void x2_node(const X2Args &a, long long N, long long 
         Dual nd[DFT_NALPHA], dd[DFT_NALPHA];
 #pragma unroll
         for (int f = 0; f < DFT_NALPHA; ++f) nd[f] = Dual{a.nstar[f * N + idx], n[f]};
-        fmt_dphi<Dual>(nd, dd, clamped);
+        fmt_dphi_as<ALT, Dual>(a.hs, nd, dd, clamped);
         bool bad = false;
 #pragma unroll
         for (int f = 0; f < DFT_NALPHA; ++f) {
@@ -154,12 +156,12 @@ __device__ __forceinline__ void x2_node(const X2Args &a, long long N, long long 
             n[f] += nr[f];
         }
         bool c2;
-        fmt_dphi<double>(n, d, clamped);
-        fmt_dphi<double>(nr, dr, c2);
+        fmt_dphi_as<ALT, double>(a.hs, n, d, clamped);
+        fmt_dphi_as<ALT, double>(a.hs, nr, dr, c2);
 #pragma unroll
         for (int f = 0; f < DFT_NALPHA; ++f) d[f] -= dr[f];
     } else {
-        fmt_dphi<double>(n, d, clamped);
+        fmt_dphi_as<ALT, double>(a.hs, n, d, clamped);
     }
     if (clamped) flag |= 2;
     if (!isfinite(n[3])) flag |= 5;                        // 1: evaluation non-finite, 4: n3 non-finite

@@ -12,8 +12,8 @@ from . import _abi
 
 
 def make_params(n, h, radius, valence, rho_bulk, bjerrum=0.0, electrostatics=False, precision=_abi.DFT_FP64,
-                eta_cap=0.0, flags=0):
-    """Fill a dft_params struct."""
+                eta_cap=0.0, flags=0, hs_functional=_abi.HS_RSLT):
+    """Fill a dft_params struct (hs_functional: a dft_hs_functional value or its name)."""
     p = _abi.Params()
     S = len(radius)
     for d in range(3):
@@ -29,6 +29,9 @@ def make_params(n, h, radius, valence, rho_bulk, bjerrum=0.0, electrostatics=Fal
     p.precision = int(precision)
     p.eta_cap = float(eta_cap)
     p.flags = int(flags)
+    if isinstance(hs_functional, str):
+        hs_functional = _abi.HS_FUNCTIONALS[hs_functional]
+    p.hs_functional = int(hs_functional)
     return p
 
 
@@ -218,7 +221,8 @@ class Solver:
 def from_problem(prob, precision=_abi.DFT_FP64, device="cuda", flags=0):
     """Build a Solver from a workloads.Problem-like object (attributes n, h, radius, ...)."""
     p = make_params(prob.n, prob.h, prob.radius, prob.valence, prob.rho_bulk, prob.bjerrum, prob.electrostatics,
-                    precision, 0.0 if prob.eta_cap == 0.9 else prob.eta_cap, flags)
+                    precision, 0.0 if prob.eta_cap == 0.9 else prob.eta_cap, flags,
+                    getattr(prob, "hs_functional", "rslt"))
     return Solver(p, prob.beta_vext, prob.fixed_charge, device=device)
 
 
@@ -239,7 +243,8 @@ class Batch:
         qfix = (ctypes.c_void_p * n)()
         for i, prob in enumerate(problems):
             p = make_params(prob.n, prob.h, prob.radius, prob.valence, prob.rho_bulk, prob.bjerrum,
-                            prob.electrostatics, precision, 0.0 if prob.eta_cap == 0.9 else prob.eta_cap, flags)
+                            prob.electrostatics, precision, 0.0 if prob.eta_cap == 0.9 else prob.eta_cap, flags,
+                            getattr(prob, "hs_functional", "rslt"))
             self.params[i] = p
             nx, ny, nz = prob.n
             shape = (len(prob.radius), nz, ny, nx)

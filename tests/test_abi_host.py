@@ -52,6 +52,21 @@ def test_bulk_matches_oracle(make):
                            rtol=1e-13)
 
 
+@pytest.mark.parametrize("make", [W.config_hs_wall, W.config_sphere_128, lambda: W.config_pore(n=32)])
+@pytest.mark.parametrize("functional", ["rosenfeld", "whitebear"])
+def test_bulk_of_the_alternative_functionals_matches_oracle(make, functional):
+    # Rosenfeld's original form keeps the Percus-Yevick bath; White Bear takes the BMCSL one.
+    from paper_0910_1531_amd.solver import bulk
+    prob = make()
+    b = bulk(_params(prob, hs_functional=functional))
+    mu, bP = obulk.bath(functional, prob.rho_bulk, 2 * prob.radius)
+    assert np.allclose(b["mu_hs"], mu, rtol=1e-13, atol=1e-16)
+    assert b["beta_p"] == pytest.approx(bP, rel=1e-14)
+    if functional == "whitebear" and obulk.moments(prob.rho_bulk, 2 * prob.radius)[3] > 0.1:
+        # dense enough for Carnahan-Starling and Percus-Yevick to differ visibly (O(eta^3))
+        assert not np.allclose(b["mu_hs"], obulk.hs_mu(prob.rho_bulk, 2 * prob.radius), rtol=1e-3)
+
+
 def _status(fn, *args):
     return fn(*args)
 
@@ -75,6 +90,8 @@ def test_validation_errors_without_gpu():
     p = _params(prob); p.flags = 64; cases.append((p, 1))
     p = _params(prob); p.bjerrum_length = 0.0; cases.append((p, 1))
     p = _params(prob); p.eta_cap = 1.5; cases.append((p, 1))
+    p = _params(prob); p.hs_functional = 3; cases.append((p, 1))
+    p = _params(prob); p.hs_functional = -1; cases.append((p, 1))
     for p, want in cases:
         assert lib.dft_workspace_size(ctypes.byref(p), ctypes.byref(nbytes)) == want
         assert lib.dft_last_error()
