@@ -288,8 +288,52 @@ def functionals_leg(n):
     return out
 
 
-def cpu_baseline(evals_per_iter):
-    """The oracle's rate: one residual evaluation of the same pore system at 128^3, scaled to 256^3."""
+def screening_leg(n):
+    """The RFD screening operator (ball averages with a radius R_SC(x) that varies over 0.3-0.6 nm)
+    of the pore's three species at n^3, by Chebyshev interpolation in the radius (the paper's
+    O(N^2) per-point dot product is timed on the host in cpu_baseline)."""
+    import math
+    import torch
+    import workloads as W
+    from paper_0910_1531_amd import solver as sv
+
+    p = W.config_pore(n=n)
+    f = torch.tensor(p.initial_density(), dtype=torch.float64, device="cuda")
+    Rh = W.screening_radius(p, 0.3, 0.6, seed=4)
+    R = torch.tensor(Rh, dtype=torch.float64, device="cuda")
+    kmax = math.sqrt(sum((math.pi / hd) ** 2 for hd in p.h))
+    M = min(128, int(math.ceil(kmax * (Rh.max() - Rh.min()))) + 8)
+    sol = sv.from_problem(p)
+    out = sol.rfd_reference(f, R, M)
+    torch.cuda.synchronize()
+    reps = 3
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        sol.rfd_reference(f, R, M, out=out)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    sol.close()
+    return {"workload": f"charged pore {n}^3, 3 species, R_SC 0.3-0.6 nm", "nodes": M, "seconds": round(dt, 4)}
+
+
+def screening_oracle_rate(n):
+    """The oracle's O(N^2) screening operator (the paper's per-point dot product) at one grid point
+    of the same n^3 workload, and that time scaled to all N points."""
+    import workloads as W
+    from oracle import screening
+
+    p = W.config_pore(n=n)
+    Rh = W.screening_radius(p, 0.3, 0.6, seed=4)
+    t0 = time.perf_counter()
+    screening.reference_at(p.initial_density(), Rh, p.n, p.h, [(0, 0, 0)])
+    t = time.perf_counter() - t0
+    return {"one_point_s": round(t, 2), "all_points_estimate_s": round(t * n ** 3, 0),
+            "sample": f"one of the {n}^3 points (forward FFT included), scaled by N"}
+
+
+def cpu_baseline(evals_per_iter, screening_n=None):
+    """The oracle's rate: one residual evaluation of the same pore system at 128^3, scaled to 256^3
+    (with screening_n, also the O(N^2) screening operator of the screening extra)."""
     import workloads as W
     from oracle import residual
 
@@ -303,10 +347,13 @@ def cpu_baseline(evals_per_iter):
     n1, n2 = 128 ** 3, 256 ** 3
     scale = (n2 * math.log(n2)) / (n1 * math.log(n1))
     t_iter = t * scale * evals_per_iter
-    return {"value": 1.0 / t_iter, "unit": "Picard iterations/s", "cores": cores, "kind": "oracle",
-            "sample": (f"one FP64 residual evaluation of the same pore system at 128^3 took {t:.2f} s on "
-                       f"{cores} threads; scaled by N log N ({scale:.3f}) to 256^3 and by the FP64 GPU run's "
-                       f"{evals_per_iter:.2f} residual evaluations per iteration")}
+    out = {"value": 1.0 / t_iter, "unit": "Picard iterations/s", "cores": cores, "kind": "oracle",
+           "sample": (f"one FP64 residual evaluation of the same pore system at 128^3 took {t:.2f} s on "
+                      f"{cores} threads; scaled by N log N ({scale:.3f}) to 256^3 and by the FP64 GPU run's "
+                      f"{evals_per_iter:.2f} residual evaluations per iteration")}
+    if screening_n:
+        out["rfd_screening"] = screening_oracle_rate(screening_n)
+    return out
 
 
 def main():
@@ -319,7 +366,7 @@ def main():
     ap.add_argument("--profile-reps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the batch, adjoint, paper-workload, Newton and functional measurements")
+                    help="skip the batch, adjoint, paper-workload, Newton, functional and screening measurements")
     ap.add_argument("--fp64-only", action="store_true")
     ap.add_argument("--profile-only", action="store_true",
                     help="only the per-pass HIP-event profile (for rocprofv3 runs: every launch does full work)")
@@ -374,12 +421,12 @@ def main():
 
     f64 = legs["fp64"]
     evals_per_iter = f64["steps"]["g_evals"] / max(args.steps, 1)
-    cpu = None if args.no_cpu_baseline else cpu_baseline(evals_per_iter)
+    cpu = None if args.no_cpu_baseline else cpu_baseline(evals_per_iter, None if args.no_extras else args.n)
     extras = None
     if not args.no_extras:
         extras = {"batch_64_points_fp32_mixed": batch_leg(), "pore192_adjoint": adjoint_leg(),
                   "paper_workloads": paper_workloads_leg(), "newton_krylov_fp64": newton_leg(args.n),
-                  "hs_functionals": functionals_leg(args.n)}
+                  "hs_functionals": functionals_leg(args.n), "rfd_screening": screening_leg(args.n)}
 
     line = {
         "metric": METRIC,

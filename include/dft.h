@@ -289,6 +289,30 @@ dft_status dft_newton(dft_ctx *ctx, double *rho, void *adj_ws, size_t adj_ws_byt
                       int32_t *iters_out, int32_t *cg_iters_out, double *norm_out);
 
 /*
+ * Screening operator of the reference-fluid-density (RFD) electrostatics (RFD section, eqs.
+ * rhoRef, rhoRefKDotProduct, screening-kernel-hat): each of the ctx's S fields f_i is averaged
+ * over the ball of radius R_SC(x) centred on every grid point x,
+ *   f_ref_i(x) = N^-1 sum_k f_hat_i(k) B(|k| R_SC(x)) exp(i k.x),  B(t) = 3 (sin t - t cos t) / t^3,
+ * on the k set of eq. Kvalues (f_hat: forward DFT).  The paper evaluates this as an O(N^2) dot
+ * product per grid point.  Here B is interpolated in the radius: the fields are convolved by FFT
+ * with the balls of `nodes` first-kind Chebyshev radii spanning [min R_SC, max R_SC], and each
+ * point combines the results with the barycentric Lagrange weights of its own R_SC.  Cost: one
+ * forward and `nodes` inverse 3-D transforms per field.  The error falls geometrically once
+ * `nodes` exceeds about k_max (max R_SC - min R_SC) / 2 (k_max the largest |k| of the grid); a
+ * constant R_SC is exact with any `nodes` (one convolution).
+ *   f      device [S][N] FP64 (pass alpha_i rho_i for the weighted average of eq. rhoBarDef).
+ *   rsc    device [N] FP64, R_SC(x) in the length unit, positive and finite.
+ *   nodes  1 .. DFT_RFD_MAX_NODES.
+ *   f_ref  device [S][N] FP64 out; may be the same buffer as f.
+ * FP64 in either precision.  Uses the ctx's spectral and line-search scratch buffers (the
+ * iterate, its G and the captured step are kept); reads the R_SC range back to the host, so it
+ * synchronizes the ctx stream once.  Errors: DFT_E_INVALID_ARG (NULL pointers, nodes out of
+ * range, an R_SC that is not positive and finite, a batch group ctx).
+ */
+#define DFT_RFD_MAX_NODES 128
+dft_status dft_rfd_reference(dft_ctx *ctx, const double *f, const double *rsc, int32_t nodes, double *f_ref);
+
+/*
  * Batches of independent state points (different concentrations, valences, radii, grids).
  * Points of one shape (n, nspecies, precision) form a group; every pass of a residual
  * evaluation is ONE launch over all points of a group, the line-search state machines run

@@ -18,6 +18,7 @@ Modules
   picard    Picard iteration with the quadratic line search and the n3 bound.
   brute     Real-space circulant convolution for tiny grids (pins the FFT path).
   adjoint   Implicit-adjoint gradient of an observable through the fixed point.
+  screening RFD screening operator (ball average with a varying radius), O(N^2).
 
 Parity-pinning status of each function is stated in its module header.
 """

@@ -23,6 +23,7 @@ FLAG_NO_AUTOTUNE = 4
 HS_RSLT, HS_ROSENFELD, HS_WHITE_BEAR = 0, 1, 2
 HS_FUNCTIONALS = {"rslt": HS_RSLT, "rosenfeld": HS_ROSENFELD, "whitebear": HS_WHITE_BEAR}
 SCHEDULE_LEN = 8
+RFD_MAX_NODES = 128
 TUNE_PASSES = ["y", "z_plain", "z_weights", "z_back"]
 
 D8 = ctypes.c_double * MAX_SPECIES
@@ -82,6 +83,7 @@ SIGNATURES = [
     ("dft_get_stats", [_vp, ctypes.POINTER(Stats)]),
     ("dft_newton", [_vp, _vp, _vp, ctypes.c_size_t, ctypes.c_double, ctypes.c_int32,
                     ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32), _dp]),
+    ("dft_rfd_reference", [_vp, _vp, _vp, ctypes.c_int32, _vp]),
     ("dft_get_schedule", [_vp, ctypes.POINTER(ctypes.c_int32)]),
     ("dft_set_schedule", [_vp, ctypes.POINTER(ctypes.c_int32)]),
     ("dft_destroy", [_vp]),

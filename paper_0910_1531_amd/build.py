@@ -17,7 +17,7 @@ LIB = os.path.join(HERE, "libdftpicard.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
 SOURCES = ["dft_host.cpp", "dft_kernels.hip", "ct_launch_x.hip", "ct_launch_x2_alt.hip", "ct_launch_y.hip", "ct_launch_z1_f32.hip",
-           "ct_launch_z1_f64.hip", "ct_launch_z2.hip", "dft_tune.hip", "dft_adjoint.hip", "dft_api.hip"]
+           "ct_launch_z1_f64.hip", "ct_launch_z2.hip", "dft_tune.hip", "dft_adjoint.hip", "dft_screen.hip", "dft_api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -345,7 +345,8 @@ __global__ __launch_bounds__(NTB) void k_z1c(Geo g_in, Z1Args a) {
 // Z2: forward z transform of the ten dPhi/dn spectra, back-convolution with conj(w_hat)
 // (eq. muHS; the vector parts enter as +i k_d times a w3 weight), plus the electrostatic
 // spectra Z1 left in specA, times 1/N, inverse z -> specA.  Z2_POISSON instead forms the
-// potential of weighted source spectra.  Weights: tables in FP64, on the fly in FP32.
+// potential of weighted source spectra, Z2_BALL the ball averages of the RFD screening operator.
+// Weights: tables in FP64, on the fly in FP32.
 template <typename T, int L, int P, int NTB>
 __global__ __launch_bounds__(NTB) void k_z2c(Geo g_in, Z2Args a) {
     using F = ct::Fft<T, typename ct::Plan<L>::type, P, NTB, false, 2>;
@@ -401,6 +402,20 @@ __global__ __launch_bounds__(NTB) void k_z2c(Geo g_in, Z2Args a) {
         }
     };
 
+    if (a.mode == Z2_BALL) {
+        // ball average of every source field (the RFD screening operator at one radius):
+        // specA[i] x B(|k| radius) / N -> specB[i]
+        double m[NO];
+#pragma unroll
+        for (int i = 0; i < NO; ++i) m[i] = ball_mean<double>((double)kw.kmag(pp[i], ee[i]), a.radius) * c.invN;
+        for (int is = 0; is < a.nsrc; ++is) {
+            load_fwd(reinterpret_cast<const cx<T> *>(a.specA) + (long long)is * NC + off);
+#pragma unroll
+            for (int i = 0; i < NO; ++i) v[i] = mk<T>(T((double)v[i].x * m[i]), T((double)v[i].y * m[i]));
+            inv_store(reinterpret_cast<cx<T> *>(a.specB) + (long long)is * NC + off);
+        }
+        return;
+    }
     if (a.mode == Z2_POISSON) {
         // phi_hat = 4 pi l_B (sum_j w_j src_j) / D(k), zero mode 0; x invN; output in specA[0].
         double acc[NO][2];

@@ -14,6 +14,7 @@
 #include "dft_adjoint.h"
 #include "dft_host.h"
 #include "dft_kernels.h"
+#include "dft_screen.h"
 #include "dft_tune.h"
 
 using namespace dft;
@@ -1178,6 +1179,69 @@ dft_status dft_newton(dft_ctx *ctx, double *rho, void *adj_ws, size_t adj_ws_byt
         if (cg_iters_out) *cg_iters_out = cg_total;
         if (norm_out) *norm_out = res;
         if (res > tol) return fail(DFT_E_NOT_CONVERGED, "Newton-Krylov reached max_iter");
+        return DFT_OK;
+    });
+}
+
+dft_status dft_rfd_reference(dft_ctx *ctx, const double *f, const double *rsc, int32_t nodes, double *f_ref) {
+    if (!ctx || !f || !rsc || !f_ref) return fail(DFT_E_INVALID_ARG, "ctx, f, rsc or f_ref is NULL");
+    if (nodes < 1 || nodes > DFT_RFD_MAX_NODES) return fail(DFT_E_INVALID_ARG, "nodes must lie in 1 .. DFT_RFD_MAX_NODES");
+    if (ctx->geo.nprob != 1) return fail(DFT_E_INVALID_ARG, "a batch group ctx holds several points; use a member ctx");
+    return guarded([&]() -> dft_status {
+        dft_ctx *c = ctx;
+        const Geo &g = c->geo;
+        hipStream_t s = c->stream;
+        // range of R_SC (and its validity) on the host
+        const int nb = rsc_range(g.N, rsc, c->red.fpart, c->red.mpart, c->red.fflag, c->red.cap, s);
+        std::vector<double> lo(nb), hi(nb);
+        std::vector<int> bad(nb);
+        HIPCHK(hipMemcpyAsync(lo.data(), c->red.fpart, sizeof(double) * nb, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(hi.data(), c->red.mpart, sizeof(double) * nb, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(bad.data(), c->red.fflag, sizeof(int) * nb, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        double rlo = INFINITY, rhi = -INFINITY;
+        long long nbad = 0;
+        for (int i = 0; i < nb; ++i) {
+            rlo = std::min(rlo, lo[i]);
+            rhi = std::max(rhi, hi[i]);
+            nbad += bad[i];
+        }
+        if (nbad) return fail(DFT_E_INVALID_ARG, "rsc must be positive and finite at every node");
+        // Chebyshev points of the range (one point when R_SC is constant)
+        int M = nodes;
+        if (!(rhi - rlo > 1e-15 * rhi)) M = 1;
+        const double cc = 0.5 * (rlo + rhi), dd = M == 1 ? 0.0 : 0.5 * (rhi - rlo);
+        // forward x, y transforms of the S fields (FP64), kept in specA for every radius
+        XFwdArgs xa{};
+        xa.src = f;
+        xa.spec = c->specA;
+        xa.nfield = g.S;
+        xa.mode = XF_PLAIN;
+        launch_x_forward<double>(g, xa, s);
+        YArgs ya{c->specA, g.S, -1, nullptr};
+        launch_y<double>(g, ya, s);
+        double *inv_den = c->gs;
+        int *hit = reinterpret_cast<int *>(c->ga);
+        cheb_prep(g.N, rsc, M, cc, dd, inv_den, hit, s);
+        for (int m = 0; m < M; ++m) {
+            const double Rm = cc + dd * std::cos(M_PI * (2.0 * m + 1.0) / (2.0 * M));
+            Z2Args z2{};
+            z2.specA = c->specA;
+            z2.specB = c->specB;
+            z2.mode = Z2_BALL;
+            z2.nsrc = g.S;
+            z2.radius = Rm;
+            launch_z2<double>(g, z2, s);
+            YArgs yb{c->specB, g.S, 1, nullptr};
+            launch_y<double>(g, yb, s);
+            X3Args x3{};
+            x3.specA = c->specB;
+            x3.nfield = g.S;
+            x3.raw = 1;
+            x3.raw_out = c->rho_t;
+            launch_x3<double>(g, x3, s);
+            cheb_accum(g.N, g.S, m, M, cc, dd, rsc, inv_den, hit, c->rho_t, f_ref, m == 0, s);
+        }
         return DFT_OK;
     });
 }

@@ -248,6 +248,15 @@ __device__ __forceinline__ void weight_w2_w3(R k, R Rad, R &w2, R &w3) {
     weight_w2_w3_sc<R>(k, Rad, s, c, w2, w3);
 }
 
+// Transform of the unit-mean ball indicator of radius R at |k| (the screening kernel of the RFD
+// section, eq. screening-kernel-hat): 3 (sin kR - kR cos kR) / (kR)^3 = w3 / (4 pi R^3 / 3).
+template <typename R>
+__device__ __forceinline__ R ball_mean(R k, R Rad) {
+    R w2, w3;
+    weight_w2_w3<R>(k, Rad, w2, w3);
+    return w3 * R(3.0 / kFourPi) / (Rad * Rad * Rad);
+}
+
 // Bulk-fluid kernel transform for one pair: c1 F1 + c0 F0 + cm1 Fm1 with
 // F_m = integral over |r| <= Rc of r^m exp(-i k.r) = (4 pi / k) I_m(Rc, k),
 // given s = sin(k Rc), c = cos(k Rc) (used for k Rc >= 1).

@@ -63,7 +63,7 @@ struct RedBufs {
 
 enum XFwdMode { XF_PLAIN = 0, XF_TRIAL = 1 };
 enum X2Mode { X2_FULL = 0, X2_N3_ONLY = 1, X2_HESS = 2 };
-enum Z2Mode { Z2_EL = 0, Z2_POISSON = 1 };
+enum Z2Mode { Z2_EL = 0, Z2_POISSON = 1, Z2_BALL = 2 };
 
 struct XFwdArgs {
     const double *src;        // [S][N] input (plain) or rho0 (trial)
@@ -97,9 +97,10 @@ struct Z1Args {
 struct Z2Args {
     void *specB;        // [10] dPhi/dn half spectra after x, y forward
     void *specA;        // [S] in: electrostatic spectra from Z1; out: E_hat after inverse z (x invN)
-    int mode;           // Z2_EL or Z2_POISSON
-    int nsrc;           // Z2_POISSON: number of source fields in specA
+    int mode;           // Z2_EL, Z2_POISSON or Z2_BALL
+    int nsrc;           // Z2_POISSON, Z2_BALL: number of source fields in specA
     double wsrc[DFT_MAX_SPECIES];   // Z2_POISSON: weights of the sources
+    double radius;      // Z2_BALL: specB[i] = specA[i] x ball_mean(|k|, radius) / N (z transformed)
     const int *gate;
 };
 

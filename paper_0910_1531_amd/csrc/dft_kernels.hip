@@ -355,6 +355,30 @@ __global__ __launch_bounds__(NT) void k_z2(Geo g_in, Z2Args a, int W) {
     const cx<T> *tw = twp<T>(g, 2);
     const int S = g.S;
 
+    if (a.mode == Z2_BALL) {
+        // ball average of every source field at one radius: specA[i] x B(|k| radius) / N -> specB[i]
+        for (int i = 0; i < a.nsrc; ++i) {
+            const cx<T> *src = reinterpret_cast<const cx<T> *>(a.specA) + (long long)i * g.NC + off;
+            z_load(tile, src, Wact, L, rs);
+            __syncthreads();
+            fft_tile<T, -1, NT, MAXE>(tile, g.pz, Wact, Wact, 1, false, tw);
+#pragma unroll
+            for (int it = 0; it < MAXE; ++it) {
+                const int j = threadIdx.x + it * NT;
+                if (j < Wact * L) {
+                    const int e = j / Wact, p = j - e * Wact;
+                    const KInfo q = kinfo(c, kx0 + p, y, e);
+                    const double m = ball_mean<double>(q.kmag, a.radius) * c.invN;
+                    tile[j] = mk<T>(T((double)tile[j].x * m), T((double)tile[j].y * m));
+                }
+            }
+            __syncthreads();
+            fft_tile<T, 1, NT, MAXE>(tile, g.pz, Wact, Wact, 1, false, tw);
+            z_store(tile, reinterpret_cast<cx<T> *>(a.specB) + (long long)i * g.NC + off, Wact, L, rs);
+            __syncthreads();
+        }
+        return;
+    }
     if (a.mode == Z2_POISSON) {
         // phi_hat = 4 pi l_B (sum_j w_j src_j) / D(k), zero mode 0; x invN; output in specA[0].
         double acc[MAXE][2];

@@ -186,6 +186,18 @@ class Solver:
             _abi.check(st, "dft_newton")
         return it.value, cg.value, r.value, st
 
+    def rfd_reference(self, f, rsc, nodes, out=None):
+        """dft_rfd_reference: ball averages of the S fields f with the radius field rsc [nz][ny][nx]."""
+        self._check_rho(f)
+        rsc = rsc.contiguous()
+        if rsc.dtype != torch.float64 or rsc.device != self.device or tuple(rsc.shape) != tuple(f.shape[1:]):
+            raise ValueError(f"rsc must be float64 {tuple(f.shape[1:])} on {self.device}")
+        if out is None:
+            out = torch.empty_like(f)
+        _abi.check(self.lib.dft_rfd_reference(self.ctx, _ptr(f), _ptr(rsc), int(nodes), _ptr(out)),
+                   "dft_rfd_reference")
+        return out
+
     def stats(self):
         s = _abi.Stats()
         _abi.check(self.lib.dft_get_stats(self.ctx, ctypes.byref(s)), "dft_get_stats")

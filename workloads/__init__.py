@@ -312,6 +312,24 @@ def batch_points(count=64, seed=4, h=0.025, sizes=(64, 96, 128), tol=1e-8):
     return pts
 
 
+def screening_radius(prob: Problem, lo: float, hi: float, seed=0, modes=3) -> np.ndarray:
+    """A smooth positive radius field [nz][ny][nx] spanning [lo, hi]: a few random low-order
+    Fourier modes of the periodic box, shifted and scaled onto the interval (a stand-in for the
+    local screening length R_SC(x) of the RFD electrostatics, which varies near walls and ions)."""
+    rng = np.random.default_rng(seed)
+    nx, ny, nz = prob.n
+    x = np.arange(nx)[None, None, :] / nx
+    y = np.arange(ny)[None, :, None] / ny
+    z = np.arange(nz)[:, None, None] / nz
+    u = np.zeros(prob.shape)
+    for _ in range(modes):
+        jx, jy, jz = rng.integers(0, 3, 3)
+        ph = rng.uniform(0.0, 2.0 * math.pi)
+        u = u + rng.uniform(0.5, 1.0) * np.cos(2.0 * math.pi * (jx * x + jy * y + jz * z) + ph)
+    u = (u - u.min()) / max(u.max() - u.min(), 1e-300)
+    return lo + (hi - lo) * u
+
+
 def random_density(prob: Problem, seed=0, amplitude=0.3):
     """rho = rho_bulk * mask * (1 + amplitude * u), u ~ U[-1, 1): a rough positive test field."""
     rng = np.random.default_rng(seed)
