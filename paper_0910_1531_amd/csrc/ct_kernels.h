@@ -100,7 +100,7 @@ struct ZWave {
     __device__ T kz(int e) const { return T(signed_mode(e, nz)) * dkz; }
     __device__ T kmag(int p, int e) const {
         const T a = kx(p), b = kz(e);
-        return sqrt(a * a + ky * ky + b * b);
+        return sqrt_r(a * a + ky * ky + b * b);
     }
     __device__ bool zero(int p, int e) const { return yzero && jx0 + p == 0 && e == 0; }
     // component d of k, zero on the Nyquist plane of axis d
@@ -195,7 +195,7 @@ __global__ __launch_bounds__(NTB) void k_z1c(Geo g_in, Z1Args a) {
             kmag[i] = kw.kmag(pp[i], ee[i]);
             invD[i] = T(0);
             if constexpr (MS > 0) {
-                if (es && !kw.zero(pp[i], ee[i])) invD[i] = T(c.four_pi_lB) / pd.denom(kx0 + pp[i], ee[i]);
+                if (es && !kw.zero(pp[i], ee[i])) invD[i] = T(c.four_pi_lB) * rcp_r(pd.denom(kx0 + pp[i], ee[i]));
 #pragma unroll
                 for (int is = 0; is < MS; ++is) {
                     sn[is][i] = T(0);
@@ -592,6 +592,23 @@ __global__ __launch_bounds__(XTile<L>::NTB) void k_x2c(Geo g_in, X2Args a) {
             vals[f][i] = c;
         }
     }
+    // D32: the reference weighted densities of a register's two nodes, fetched one register
+    // ahead of the nodewise work (the first before the transforms) so their latency is hidden
+    constexpr int NRB = D32 ? 2 : 1;
+    float nrc[NRB][2][DFT_NALPHA];
+    auto fetch_nref = [&](int i, float (&dst)[2][DFT_NALPHA]) {
+        int p, e;
+        const bool ok = F::template out_pos<1>(i, p, e) && p < Pact;
+        const long long r0 = 2 * (pair0 + p);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const bool okh = ok && r0 + h < rows;
+            const long long idx = (r0 + h) * L + e;
+#pragma unroll
+            for (int f = 0; f < DFT_NALPHA; ++f) dst[h][f] = okh ? ct::gld(a.nref + f * N + idx) : 0.0f;
+        }
+    };
+    if constexpr (D32) fetch_nref(0, nrc[0]);
 #pragma unroll
     for (int f = 0; f < DFT_NALPHA; ++f) {
         if (f >= nf) continue;
@@ -605,6 +622,9 @@ __global__ __launch_bounds__(XTile<L>::NTB) void k_x2c(Geo g_in, X2Args a) {
     int flag = 0;
 #pragma unroll
     for (int i = 0; i < NO; ++i) {
+        if constexpr (D32) {
+            if (i + 1 < NO) fetch_nref(i + 1, nrc[(i + 1) % NRB]);
+        }
         int p, e;
         if (!(F::template out_pos<1>(i, p, e) && p < Pact)) continue;
         const long long r0 = 2 * (pair0 + p);
@@ -624,7 +644,7 @@ __global__ __launch_bounds__(XTile<L>::NTB) void k_x2c(Geo g_in, X2Args a) {
                 float dn[DFT_NALPHA], dd[DFT_NALPHA];
 #pragma unroll
                 for (int f = 0; f < DFT_NALPHA; ++f) dn[f] = h == 0 ? vals[f][i].x : vals[f][i].y;
-                x2_node_diff(a, N, idx, dn, dd, mloc, flag);
+                x2_node_diff(nrc[i % NRB][h], dn, dd, mloc, flag);
 #pragma unroll
                 for (int f = 0; f < DFT_NALPHA; ++f) {
                     if (h == 0) vals[f][i].x = dd[f];

@@ -220,6 +220,14 @@ constexpr double kFourPi = 12.566370614359172953850573533118011536788677597500;
 __device__ __forceinline__ void sincos_r(double y, double *s, double *c) { sincos(y, s, c); }
 __device__ __forceinline__ void sincos_r(float y, float *s, float *c) { sincosf(y, s, c); }
 
+// Reciprocal and square root in the arithmetic type: IEEE operations in FP64; in FP32 the
+// hardware's single-instruction approximations (about 1 ulp), enough for the spectral factors
+// that multiply FP32 difference spectra.
+__device__ __forceinline__ double rcp_r(double x) { return 1.0 / x; }
+__device__ __forceinline__ float rcp_r(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double sqrt_r(double x) { return sqrt(x); }
+__device__ __forceinline__ float sqrt_r(float x) { return __builtin_amdgcn_sqrtf(x); }
+
 // Weight transforms of a sphere of radius R at |k| (Appendix B):
 //   w2 = 4 pi R sin(kR) / k,   w3 = 4 pi (sin kR - kR cos kR) / k^3,
 // given s = sin(kR) and c = cos(kR) (used only for kR >= 1; the series covers kR < 1).
@@ -235,7 +243,7 @@ __device__ __forceinline__ void weight_w2_w3_sc(R k, R Rad, R s, R c, R &w2, R &
         w2 = R(kFourPi) * R2 * horner_y2<R>(s0, y2);
         w3 = R(kFourPi) * R2 * Rad * horner_y2<R>(s3, y2);
     } else {
-        const R iy = R(1) / y;
+        const R iy = rcp_r(y);
         w2 = R(kFourPi) * R2 * s * iy;
         w3 = R(kFourPi) * R2 * Rad * (s - y * c) * iy * iy * iy;
     }
@@ -274,8 +282,8 @@ __device__ __forceinline__ R screening_hat_sc(R k, R Rc, R s, R c, R c1, R c0, R
         F0 = R(kFourPi) * R2 * Rc * horner_y2<R>(s0, y2);
         F1 = R(kFourPi) * R2 * R2 * horner_y2<R>(s1, y2);
     } else {
-        const R omc = (c > R(0)) ? s * s / (R(1) + c) : R(1) - c;   // 1 - cos y without cancellation
-        const R iy = R(1) / y, iy2 = iy * iy;
+        const R omc = (c > R(0)) ? s * s * rcp_r(R(1) + c) : R(1) - c;   // 1 - cos y without cancellation
+        const R iy = rcp_r(y), iy2 = iy * iy;
         Fm1 = R(kFourPi) * R2 * omc * iy2;
         F0 = R(kFourPi) * R2 * Rc * (s - y * c) * iy2 * iy;
         F1 = R(kFourPi) * R2 * R2 * (-c * iy2 + R(2) * s * iy2 * iy - R(2) * omc * iy2 * iy2);
@@ -293,7 +301,7 @@ __device__ __forceinline__ R screening_hat(R k, R Rc, R c1, R c0, R cm1) {
 // 2 (1 - cos t) = 4 sin^2(t / 2) from (cos t, +-sin t) without cancellation.
 template <typename R>
 __device__ __forceinline__ R two_omc(R c, R s) {
-    return (c > R(0)) ? R(2) * s * s / (R(1) + c) : R(2) * (R(1) - c);
+    return (c > R(0)) ? R(2) * s * s * rcp_r(R(1) + c) : R(2) * (R(1) - c);
 }
 
 // Eigenvalue of minus the 7-point Laplacian for wavenumber components kd.

@@ -179,16 +179,16 @@ __device__ __forceinline__ void x2_node(const X2Args &a, long long N, long long 
 // computed in FP32 term by term.  Every product is expanded by telescoping,
 // a b - ar br = (a - ar) b + ar (b - br), and every term carries one difference factor, so the
 // rounding error is proportional to |dn|, as in the FP32 transforms; log(1 - n3) enters only as
-// log1p(-dn3 / (1 - nr3)).  Reciprocals use the hardware's correctly rounded v_rcp (the
-// coefficients need FP32 relative accuracy only).  n3 itself (the line-search bound) is formed
+// log1p(-dn3 / (1 - nr3)).  Reciprocals use the hardware's reciprocal instruction (about 1 ulp;
+// the coefficients need FP32 relative accuracy only).  n3 itself (the line-search bound) is formed
 // in FP64.  Flags and the n3 maximum as x2_node.
-__device__ __forceinline__ void x2_node_diff(const X2Args &a, long long N, long long idx,
-                                             const float (&dn)[DFT_NALPHA], float (&dd)[DFT_NALPHA],
-                                             double &mloc, int &flag) {
+// nrv holds the reference values nref[f][idx], loaded by the caller ahead of time.
+__device__ __forceinline__ void x2_node_diff(const float (&nrv)[DFT_NALPHA], const float (&dn)[DFT_NALPHA],
+                                             float (&dd)[DFT_NALPHA], double &mloc, int &flag) {
     float nr[DFT_NALPHA], n[DFT_NALPHA];
 #pragma unroll
     for (int f = 0; f < DFT_NALPHA; ++f) {
-        nr[f] = a.nref[f * N + idx];
+        nr[f] = nrv[f];
         n[f] = nr[f] + dn[f];
     }
     const double n3 = (double)nr[3] + (double)dn[3];
@@ -197,7 +197,7 @@ __device__ __forceinline__ void x2_node_diff(const X2Args &a, long long N, long 
     const float inv4pi = (float)(1.0 / (4.0 * 3.14159265358979323846));
     // 1 / (1 - n3) and its powers, with their differences
     const float Dr = 1.0f - nr[3], D = Dr - dn[3];
-    const float iDr = __frcp_rn(Dr), iD = __frcp_rn(D);
+    const float iDr = rcp_r(Dr), iD = rcp_r(D);
     const float diD = dn[3] * iD * iDr;
     const float iD2 = iD * iD, iDr2 = iDr * iDr, diD2 = diD * (iD + iDr);
     const float iD3 = iD2 * iD, diD3 = diD * (iD2 + iD * iDr + iDr2);
@@ -215,11 +215,11 @@ __device__ __forceinline__ void x2_node_diff(const X2Args &a, long long N, long 
     const float n2sq = n[2] * n[2], n2sqr = nr[2] * nr[2], dn2sq = dn[2] * (n[2] + nr[2]);
     const float den = fmaxf(n2sq, tiny), denr = fmaxf(n2sqr, tiny);
     const float dden = (n2sq > tiny && n2sqr > tiny) ? dn2sq : den - denr;
-    const float x2 = dot22 * __frcp_rn(den), x2r = dot22r * __frcp_rn(denr);
+    const float x2 = dot22 * rcp_r(den), x2r = dot22r * rcp_r(denr);
     float dxc;
     // x2 - x2r = (d(dot22) - x2r d(den)) / den: no product of two floored denominators, which
     // underflows where n2 vanishes
-    if (x2 < 1.0f && x2r < 1.0f) dxc = (ddot22 - x2r * dden) * __frcp_rn(den);
+    if (x2 < 1.0f && x2r < 1.0f) dxc = (ddot22 - x2r * dden) * rcp_r(den);
     else if (!(x2 < 1.0f) && !(x2r < 1.0f)) dxc = 0.0f;
     else dxc = fminf(x2, 1.0f) - fminf(x2r, 1.0f);
     const float xc = fminf(x2, 1.0f), xcr = fminf(x2r, 1.0f);
