@@ -59,12 +59,14 @@ def test_matches_the_per_point_dot_product(n, S):
     assert errs[8] < errs[4] and errs[16] < errs[8]
 
 
-def test_constant_radius_is_one_convolution():
+@pytest.mark.parametrize("precision", [0, 1])
+def test_constant_radius_is_one_convolution(precision):
+    # FP64 arithmetic in either precision of the context
     p = _problem((16, 12, 18), 2)
     f = W.random_density(p, seed=8, amplitude=0.5)
     R = np.full(p.shape, 0.23)
     want = screening.convolution(f, 0.23, p.n, p.h)
-    sol = from_problem(p)
+    sol = from_problem(p, precision=precision)
     for M in (1, 7):
         out = sol.rfd_reference(_dev(f), _dev(R), M).cpu().numpy()
         assert np.abs(out - want).max() < 1e-13 * np.abs(want).max()
