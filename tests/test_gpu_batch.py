@@ -56,3 +56,22 @@ def test_batched_electrolyte_workload_fp32_mixed():
     _say(f"  solved in {dt:.2f} s; iterations min/median/max {min(its)}/{int(np.median(its))}/{max(its)}")
     assert all(s == 0 for s in sts), sts
     assert max(norms) <= 1e-8
+
+
+def test_batch_groups_split_by_functional():
+    # Points of one grid that use different hard-sphere functionals form separate groups and each
+    # solves exactly as it does alone.
+    from paper_0910_1531_amd.solver import Batch, from_problem
+    pts = W.batch_points(count=4, seed=6, h=0.1, sizes=(16,))
+    for p, fn in zip(pts, ["rslt", "whitebear", "rosenfeld", "whitebear"]):
+        p.hs_functional = fn
+    b = Batch(pts)
+    rhos = [_dev(p.initial_density()) for p in pts]
+    its, norms, sts = b.solve(rhos, 1e-9, 500)
+    assert all(s == 0 for s in sts) and all(r <= 1e-9 for r in norms)
+    for i, p in enumerate(pts):
+        sol = from_problem(p)
+        x = _dev(p.initial_density())
+        it, r, st = sol.solve(x, 1e-9, 500)
+        assert st == 0 and it == its[i]
+        assert torch.equal(x, rhos[i]), i
