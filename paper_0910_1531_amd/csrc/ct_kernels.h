@@ -310,34 +310,60 @@ __global__ __launch_bounds__(NTB) void k_z1c(Geo g_in, Z1Args a) {
             }
         }
     }
-    const int nout = a.n3only ? 1 : DFT_NALPHA;
+    // Seven inverse transforms give the ten outputs: along a z pencil k_x and k_y are constant, so
+    // the x and y components of the vector densities are -i k_x and -i k_y times the transform of
+    // their scalar sum; only n0..n3, the two vector sums' k_z multiples and the nV1 sum are
+    // transformed.  Transform t, its source sum and whether it is multiplied by -i k_z:
+    //   t = 0..3: acc[t] (n0..n3; t = 3 also gives the x, y components of nV2)
+    //   t = 4: acc[4] (x, y components of nV1);  t = 5: -i k_z acc[4] (nV1_z);  t = 6: -i k_z acc[3] (nV2_z)
+    const int ntr = a.n3only ? 1 : 7;
     const T invN = T(c.invN);
-    for (int o = 0; o < nout; ++o) {
-        const int alpha = a.n3only ? 3 : o;
+    for (int t = 0; t < ntr; ++t) {
+        const int src = a.n3only ? 3 : (t < 5 ? t : (t == 5 ? 4 : 3));
+        const bool kzm = t >= 5;
 #pragma unroll
         for (int i = 0; i < NO; ++i) {
             // source sum selected with compile-time register indices
             cx<T> s = acc[3][i];
 #pragma unroll
-            for (int m = 0; m < 5; ++m) {
-                const bool pick = (alpha < 4) ? (m == alpha) : (m == (alpha < 7 ? 4 : 3));
-                if (pick) s = acc[m][i];
+            for (int m = 0; m < 5; ++m)
+                if (m == src) s = acc[m][i];
+            if (kzm) {
+                const T kd = kw.comp(pp[i], ee[i], 2);
+                s = mk<T>(kd * s.y, -kd * s.x);   // -i k_z s
             }
-            cx<T> r = s;
-            if (alpha >= 4) {
-                const int d = (alpha - 4) % 3;
-                const T kd = kw.comp(pp[i], ee[i], d);
-                r = mk<T>(kd * s.y, -kd * s.x);   // -i k_d s
-            }
-            v[i] = mk<T>(r.x * invN, r.y * invN);
+            v[i] = mk<T>(s.x * invN, s.y * invN);
         }
         F::template run<1>(v, lds, ph, tw);
-        cx<T> *dst = reinterpret_cast<cx<T> *>(a.specB) + (long long)o * NC + off;
+        // store the transform as output o, times -i k_d for d = 0 (x) or 1 (y), plain for d < 0
+        auto store = [&](int o, int d) {
+            cx<T> *dst = reinterpret_cast<cx<T> *>(a.specB) + (long long)o * NC + off;
 #pragma unroll
-        for (int i = 0; i < F::template nout<1>(); ++i) {
-            int p, e;
-            const bool ok = F::template out_pos<1>(i, p, e);
-            if (ok && p < Pact) ct::gst(dst + e * rs + p, v[i]);
+            for (int i = 0; i < F::template nout<1>(); ++i) {
+                int p, e;
+                const bool ok = F::template out_pos<1>(i, p, e);
+                if (!(ok && p < Pact)) continue;
+                cx<T> w = v[i];
+                if (d >= 0) {
+                    const T kd = kw.comp(p, e, d);
+                    w = mk<T>(kd * w.y, -kd * w.x);
+                }
+                ct::gst(dst + e * rs + p, w);
+            }
+        };
+        if (a.n3only) {
+            store(0, -1);
+        } else if (t < 4) {
+            store(t, -1);
+            if (t == 3) {
+                store(7, 0);
+                store(8, 1);
+            }
+        } else if (t == 4) {
+            store(4, 0);
+            store(5, 1);
+        } else {
+            store(t == 5 ? 6 : 9, -1);
         }
     }
 }
@@ -450,20 +476,43 @@ __global__ __launch_bounds__(NTB) void k_z2c(Geo g_in, Z2Args a) {
     for (int m = 0; m < 6; ++m)
 #pragma unroll
         for (int i = 0; i < NO; ++i) u[m][i] = mk<T>(T(0), T(0));
-    for (int al = 0; al < DFT_NALPHA; ++al) {
-        load_fwd(reinterpret_cast<const cx<T> *>(a.specB) + (long long)al * NC + off);
-        const int m = al < 4 ? al : (al < 7 ? 4 : 5);
-        const int d = al < 4 ? 0 : (al - 4) % 3;
+    // Eight forward transforms: along a z pencil k_x and k_y are constant, so the x and y parts of
+    // each vector sum, i k_x dPhi_x + i k_y dPhi_y, are combined before one transform; the z parts
+    // are transformed and multiplied by i k_z after.  Transform t: 0..3 the scalars (u0..u3);
+    // 4, 6 the combined x, y parts of V1, V2; 5, 7 their z parts.
+    for (int t = 0; t < 8; ++t) {
+        const int m = t < 4 ? t : (t < 6 ? 4 : 5);
+        if (t < 4 || t == 5 || t == 7) {
+            const int al = t < 4 ? t : (t == 5 ? 6 : 9);
+            load_fwd(reinterpret_cast<const cx<T> *>(a.specB) + (long long)al * NC + off);
+        } else {
+            const int al = t == 4 ? 4 : 7;
+            const cx<T> *sx = reinterpret_cast<const cx<T> *>(a.specB) + (long long)al * NC + off;
+            const cx<T> *sy = sx + NC;
+#pragma unroll
+            for (int i = 0; i < F::template nin<-1>(); ++i) {
+                int p, e;
+                const bool ok = F::template in_pos<-1>(i, p, e) && p < Pact;
+                cx<T> w = mk<T>(T(0), T(0));
+                if (ok) {
+                    const cx<T> fx = ct::gld(sx + e * rs + p), fy = ct::gld(sy + e * rs + p);
+                    const T kx = kw.comp(p, e, 0), ky = kw.comp(p, e, 1);
+                    w = mk<T>(-(kx * fx.y + ky * fy.y), kx * fx.x + ky * fy.x);   // i k_x fx + i k_y fy
+                }
+                v[i] = w;
+            }
+            F::template run<-1>(v, lds, ph, tw);
+        }
 #pragma unroll
         for (int i = 0; i < NO; ++i) {
-            cx<T> t = v[i];
-            if (al >= 4) {
-                const T kd = kw.comp(pp[i], ee[i], d);
-                t = mk<T>(-kd * t.y, kd * t.x);   // + i k_d t
+            cx<T> w = v[i];
+            if (t == 5 || t == 7) {
+                const T kd = kw.comp(pp[i], ee[i], 2);
+                w = mk<T>(-kd * w.y, kd * w.x);   // + i k_z w
             }
 #pragma unroll
             for (int mm = 0; mm < 6; ++mm)
-                if (mm == m) { u[mm][i].x += t.x; u[mm][i].y += t.y; }
+                if (mm == m) { u[mm][i].x += w.x; u[mm][i].y += w.y; }
         }
     }
     const T invN = T(c.invN);
