@@ -436,6 +436,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(head["ms_per_step"], 4),
+        "evals_per_step": round(head["steps"]["g_evals"] / max(args.steps, 1), 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
