@@ -108,6 +108,7 @@ def test_validation_errors_without_gpu():
     assert lib.dft_residual(None, None, None, None) == 1
     assert lib.dft_solve(None, None, 1e-8, 10, None, None) == 1
     assert lib.dft_destroy(None) == 0
+    assert lib.dft_rfd_reference(None, None, None, 8, None) == 1
 
 
 def test_all_supported_axis_lengths_validate():

@@ -82,3 +82,28 @@ def test_e2_electrolyte_wall():
         assert spread <= 1e-12
         assert dev <= 1e-8
         sol.close()
+
+
+@pytest.mark.parametrize("functional", ["rslt", "whitebear"])
+def test_e1_contact_error_is_first_order_and_extrapolates(functional):
+    # Packing 0.3, normal spacing R/16, R/32, R/64 on a 1.6 nm box (256, 512 and 1024 nodes: the last
+    # two run the run-time-length kernels): the contact-theorem error halves with h and its
+    # Richardson extrapolation vanishes, against the bath pressure of the functional (Percus-Yevick
+    # for eq. (Phi), Carnahan-Starling for White Bear).
+    eta = 0.3
+    errs = []
+    for m in (16, 32, 64):                         # contact node; h = R / m keeps it on the grid exactly
+        p = W.hs_wall_nm(eta, n=(16 * m, 16, 16), h=(0.1 / m, 0.05, 0.05))
+        p.hs_functional = functional
+        sol = from_problem(p)
+        x = _dev(p.initial_density())
+        it, r, st = sol.solve(x, 1e-10, 3000)
+        assert st == 0 and r <= 1e-10
+        from paper_0910_1531_amd.solver import bulk
+        betaP = bulk(sol.params)["beta_p"]
+        errs.append(float(x[0, 0, 0, m].item()) / betaP - 1.0)
+    _say(f"  E1 {functional} eta {eta}: contact errors {errs[0]:.4e} {errs[1]:.4e} {errs[2]:.4e}, "
+         f"ratios {errs[0] / errs[1]:.3f} {errs[1] / errs[2]:.3f}, extrapolated {2 * errs[2] - errs[1]:.2e}")
+    assert errs[0] / errs[1] == pytest.approx(2.0, rel=0.03)
+    assert errs[1] / errs[2] == pytest.approx(2.0, rel=0.03)
+    assert abs(2 * errs[2] - errs[1]) < 5e-4
