@@ -582,6 +582,34 @@ __device__ __forceinline__ cx<T> half_at(const cx<T> *row, int e) {
     return v;
 }
 
+// Half spectra of the two real rows of every row pair from the forward transform of the pair
+// (C held in split): A_k = (C_k + conj C_{L-k}) / 2, B_k = (C_k - conj C_{L-k}) / (2i).  In a
+// wave-private tile each wave splits its own pencils (lanes along k); otherwise the block does
+// (split must have been synchronized accordingly by the caller).
+template <typename T, int L, class F>
+__device__ __forceinline__ void split_rows(const cx<T> *split, cx<T> *out, long long pair0, int Pact, long long rows) {
+    constexpr int KX = L / 2 + 1;
+    auto one = [&](int p, int k) {
+        const cx<T> ck = split[F::lidx(p, k)];
+        const cx<T> cm = split[F::lidx(p, k == 0 ? 0 : L - k)];
+        const long long r0 = 2 * (pair0 + p);
+        ct::gst(out + r0 * KX + k, mk<T>(T(0.5) * (ck.x + cm.x), T(0.5) * (ck.y - cm.y)));
+        if (r0 + 1 < rows) ct::gst(out + (r0 + 1) * KX + k, mk<T>(T(0.5) * (ck.y + cm.y), T(-0.5) * (ck.x - cm.x)));
+    };
+    if constexpr (F::WP) {
+        constexpr int nb = L / 4;
+        const int lane = (int)threadIdx.x % 64;
+        const int p = ((int)threadIdx.x / 64) * (64 / nb) + lane / nb;
+        if (p < Pact)
+            for (int k = lane % nb; k < KX; k += nb) one(p, k);
+    } else {
+        for (int j = threadIdx.x; j < Pact * KX; j += (int)blockDim.x) {
+            const int p = j / KX;
+            one(p, j - p * KX);
+        }
+    }
+}
+
 // Nodewise variants of X2: FP64 eq. (Phi); FP32 differences from the reference (eq. (Phi),
 // x2_node_diff); FP64 with an alternative functional chosen by X2Args::hs.
 enum X2Node { X2N_FP64 = 0, X2N_D32 = 1, X2N_ALT = 2 };
@@ -730,16 +758,8 @@ __global__ __launch_bounds__(XTile<L>::NTB) void k_x2c(Geo g_in, X2Args a) {
             int p, e;
             if (F::template out_pos<-1>(i, p, e)) split[F::lidx(p, e)] = v[i];
         }
-        __syncthreads();
-        cx<T> *out = reinterpret_cast<cx<T> *>(a.specB) + (long long)f * NC;
-        for (int j = threadIdx.x; j < Pact * KX; j += NTB) {
-            const int p = j / KX, k = j - (j / KX) * KX;
-            const cx<T> ck = split[F::lidx(p, k)];
-            const cx<T> cm = split[F::lidx(p, k == 0 ? 0 : L - k)];
-            const long long r0 = 2 * (pair0 + p);
-            ct::gst(out + r0 * KX + k, mk<T>(T(0.5) * (ck.x + cm.x), T(0.5) * (ck.y - cm.y)));
-            if (r0 + 1 < rows) ct::gst(out + (r0 + 1) * KX + k, mk<T>(T(0.5) * (ck.y + cm.y), T(-0.5) * (ck.x - cm.x)));
-        }
+        F::sync();
+        split_rows<T, L, F>(split, reinterpret_cast<cx<T> *>(a.specB) + (long long)f * NC, pair0, Pact, rows);
     }
 }
 
@@ -803,16 +823,8 @@ __global__ __launch_bounds__(XTile<L>::NTB) void k_x1c(Geo g_in, XFwdArgs a) {
         int p, e;
         if (F::template out_pos<-1>(i, p, e)) split[F::lidx(p, e)] = v[i];
     }
-    __syncthreads();
-    cx<T> *out = reinterpret_cast<cx<T> *>(a.spec) + (long long)f * g.NC;
-    for (int j = threadIdx.x; j < Pact * KX; j += NTB) {
-        const int p = j / KX, k = j - (j / KX) * KX;
-        const cx<T> ck = split[F::lidx(p, k)];
-        const cx<T> cm = split[F::lidx(p, k == 0 ? 0 : L - k)];
-        const long long r0 = 2 * (pair0 + p);
-        ct::gst(out + r0 * KX + k, mk<T>(T(0.5) * (ck.x + cm.x), T(0.5) * (ck.y - cm.y)));
-        if (r0 + 1 < rows) ct::gst(out + (r0 + 1) * KX + k, mk<T>(T(0.5) * (ck.y + cm.y), T(-0.5) * (ck.x - cm.x)));
-    }
+    F::sync();
+    split_rows<T, L, F>(split, reinterpret_cast<cx<T> *>(a.spec) + (long long)f * g.NC, pair0, Pact, rows);
 }
 
 // X3: half spectra of E_k (species blockIdx.y) -> inverse x -> Euler-Lagrange update

@@ -114,6 +114,27 @@ struct Fft {
         return m;
     }
     static constexpr int V = vmax();   // registers (complex values) per thread
+    // Wave-private tiles: every stage radix 4 with exactly one butterfly per thread, and whole
+    // pencils per wave (L / 4 divides 64).  Each wave then reads and writes only its own pencils'
+    // LDS regions, and the LDS instructions of one wave execute in order, so a wave-level fence
+    // (compiler and memory ordering within the wavefront) replaces the block barrier.
+    static constexpr bool wave_private() {
+        if (!BF) return false;
+        for (int s = 0; s < NSTG; ++s)
+            if (SC::r(s) != 4) return false;
+        return items(4) == NT && NT % 64 == 0 && 64 % (L / 4) == 0;
+    }
+    static constexpr bool WP = wave_private();
+    __device__ static __forceinline__ void sync() {
+        if constexpr (WP) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        } else {
+            __syncthreads();
+        }
+    }
+
     template <int DIR> static constexpr int nin() { return regs(rad<DIR>(0)); }
     template <int DIR> static constexpr int nout() { return regs(rad<DIR>(NSTG - 1)); }
 
@@ -215,10 +236,10 @@ struct Fft {
                 buf = lds + (ph ? TILE : 0);
                 ph ^= 1;
             } else {
-                __syncthreads();
+                sync();
             }
             put<R, NS>(v, buf);
-            __syncthreads();
+            sync();
             get<rad<DIR>(S + 1)>(v, buf);
             run<DIR, S + 1>(v, lds, ph, tw);
         }
