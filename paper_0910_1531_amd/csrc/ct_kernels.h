@@ -639,6 +639,9 @@ __global__ __launch_bounds__(XTile<L>::NTB) void k_x2c(Geo g_in, X2Args a) {
     const long long pair0 = (long long)blockIdx.x * PB;
     const int Pact = (int)min((long long)PB, npairs - pair0);
     const cx<T> *tw = twp<T>(g, 0);
+    // wave-private tiles: the twiddles of all 20 transforms, once, in registers
+    typename F::Twiddles trw;
+    if constexpr (F::WP) F::load_twiddles(trw, tw);
     const bool n3only = a.mode == X2_N3_ONLY;
     const int nf = n3only ? 1 : DFT_NALPHA;
     // X2N_D32 (FP32 differences from the reference, no FP64 copies asked for): the nodewise
@@ -691,7 +694,8 @@ __global__ __launch_bounds__(XTile<L>::NTB) void k_x2c(Geo g_in, X2Args a) {
         if (f >= nf) continue;
 #pragma unroll
         for (int i = 0; i < NO; ++i) v[i] = vals[f][i];
-        F::template run<1>(v, lds, ph, tw);
+        if constexpr (F::WP) F::template run<1>(v, lds, ph, trw);
+        else F::template run<1>(v, lds, ph, tw);
 #pragma unroll
         for (int i = 0; i < NO; ++i) vals[f][i] = v[i];
     }
@@ -752,7 +756,8 @@ __global__ __launch_bounds__(XTile<L>::NTB) void k_x2c(Geo g_in, X2Args a) {
     for (int f = 0; f < DFT_NALPHA; ++f) {
 #pragma unroll
         for (int i = 0; i < NO; ++i) v[i] = vals[f][i];
-        F::template run<-1>(v, lds, ph, tw);
+        if constexpr (F::WP) F::template run<-1>(v, lds, ph, trw);
+        else F::template run<-1>(v, lds, ph, tw);
 #pragma unroll
         for (int i = 0; i < F::template nout<-1>(); ++i) {
             int p, e;

@@ -194,6 +194,37 @@ struct Fft {
         }
     }
 
+    // In a wave-private tile every stage has radix 4 and one butterfly per thread, so the spans
+    // are 1, 4, 16, ... in either direction and a thread's twiddles are the same for every
+    // transform of the tile (conjugated for the inverse): they can be loaded once into registers.
+    struct Twiddles {
+        cx<T> w[NSTG > 1 ? NSTG - 1 : 1][3];
+    };
+    __device__ static __forceinline__ void load_twiddles(Twiddles &t, const cx<T> *__restrict__ tw) {
+        static_assert(WP, "register twiddles need a wave-private tile");
+        int p, b;
+        decode<4>((int)threadIdx.x, p, b);
+#pragma unroll
+        for (int s = 1; s < NSTG; ++s) {
+            const int NS = 1 << (2 * s);
+            const int k = b % NS, ts = L / (NS * 4);
+#pragma unroll
+            for (int q = 1; q < 4; ++q) t.w[s - 1][q - 1] = gld(tw + q * k * ts);
+        }
+    }
+    template <int DIR, int S>
+    __device__ static __forceinline__ void butterflies_reg(cx<T> *v, const Twiddles &t) {
+        if constexpr (S > 0) {
+#pragma unroll
+            for (int q = 1; q < 4; ++q) {
+                cx<T> w = t.w[S - 1][q - 1];
+                if (DIR > 0) w.y = -w.y;
+                v[q] = mul(v[q], w);
+            }
+        }
+        bfly<T, DIR, 4>(v);
+    }
+
     // Outputs of a radix-R stage with span NS to the buffer (Stockham order).
     template <int R, int NS>
     __device__ static __forceinline__ void put(const cx<T> *v, cx<T> *buf) {
@@ -220,6 +251,22 @@ struct Fft {
             decode<R>(j, p, b);
 #pragma unroll
             for (int q = 0; q < R; ++q) v[it * R + q] = buf[lidx(p, b + q * (L / R))];
+        }
+    }
+
+    // The same transform with the twiddles from registers (wave-private tiles).
+    template <int DIR, int S = 0>
+    __device__ static __forceinline__ void run(cx<T> *v, cx<T> *lds, int &ph, const Twiddles &t) {
+        constexpr int NS = span<DIR>(S);
+        butterflies_reg<DIR, S>(v, t);
+        if constexpr (S + 1 < NSTG) {
+            cx<T> *buf = lds + (ph ? TILE : 0);
+            ph ^= 1;
+            static_assert(NB == 2, "wave-private tiles alternate two buffers");
+            put<4, NS>(v, buf);
+            sync();
+            get<4>(v, buf);
+            run<DIR, S + 1>(v, lds, ph, t);
         }
     }
 
