@@ -318,6 +318,8 @@ __global__ __launch_bounds__(NTB) void k_z1c(Geo g_in, Z1Args a) {
     //   t = 4: acc[4] (x, y components of nV1);  t = 5: -i k_z acc[4] (nV1_z);  t = 6: -i k_z acc[3] (nV2_z)
     const int ntr = a.n3only ? 1 : 7;
     const T invN = T(c.invN);
+    typename F::template TwReg<1> tri;   // inverse twiddles, shared by the output transforms
+    F::template load_tw<1>(tri, tw);
     for (int t = 0; t < ntr; ++t) {
         const int src = a.n3only ? 3 : (t < 5 ? t : (t == 5 ? 4 : 3));
         const bool kzm = t >= 5;
@@ -334,7 +336,7 @@ __global__ __launch_bounds__(NTB) void k_z1c(Geo g_in, Z1Args a) {
             }
             v[i] = mk<T>(s.x * invN, s.y * invN);
         }
-        F::template run<1>(v, lds, ph, tw);
+        F::template run<1>(v, lds, ph, tri);
         // store the transform as output o, times -i k_d for d = 0 (x) or 1 (y), plain for d < 0
         auto store = [&](int o, int d) {
             cx<T> *dst = reinterpret_cast<cx<T> *>(a.specB) + (long long)o * NC + off;
@@ -409,6 +411,15 @@ __global__ __launch_bounds__(NTB) void k_z2c(Geo g_in, Z2Args a) {
     }
     cx<T> v[F::V];
     int ph = 0;
+    // FP32: the forward twiddles in registers, shared by the input transforms (in FP64 the
+    // register budget is better spent on the transforms themselves)
+    constexpr bool TWR = std::is_same<T, float>::value;
+    typename F::template TwReg<-1> trf;
+    if constexpr (TWR) F::template load_tw<-1>(trf, tw);
+    auto fwd = [&]() {
+        if constexpr (TWR) F::template run<-1>(v, lds, ph, trf);
+        else F::template run<-1>(v, lds, ph, tw);
+    };
     auto load_fwd = [&](const cx<T> *src) {
 #pragma unroll
         for (int i = 0; i < F::template nin<-1>(); ++i) {
@@ -416,7 +427,7 @@ __global__ __launch_bounds__(NTB) void k_z2c(Geo g_in, Z2Args a) {
             const bool ok = F::template in_pos<-1>(i, p, e);
             v[i] = (ok && p < Pact) ? ct::gld(src + e * rs + p) : mk<T>(T(0), T(0));
         }
-        F::template run<-1>(v, lds, ph, tw);
+        fwd();
     };
     auto inv_store = [&](cx<T> *dst) {
         F::template run<1>(v, lds, ph, tw);
@@ -501,7 +512,7 @@ __global__ __launch_bounds__(NTB) void k_z2c(Geo g_in, Z2Args a) {
                 }
                 v[i] = w;
             }
-            F::template run<-1>(v, lds, ph, tw);
+            fwd();
         }
 #pragma unroll
         for (int i = 0; i < NO; ++i) {

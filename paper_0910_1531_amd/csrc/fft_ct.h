@@ -225,6 +225,51 @@ struct Fft {
         bfly<T, DIR, 4>(v);
     }
 
+    // Any tile: the twiddles of all stages of one direction for this thread's butterflies, loaded
+    // once (all in flight together) for the transforms of a block that share that direction.
+    template <int DIR>
+    static constexpr int tw_count(int upto) {
+        int n = 0;
+        for (int s = 1; s < upto; ++s) n += iters(rad<DIR>(s)) * (rad<DIR>(s) - 1);
+        return n;
+    }
+    template <int DIR>
+    struct TwReg {
+        cx<T> w[tw_count<DIR>(NSTG) > 0 ? tw_count<DIR>(NSTG) : 1];
+    };
+    template <int DIR, int S = 1>
+    __device__ static __forceinline__ void load_tw(TwReg<DIR> &t, const cx<T> *__restrict__ tw) {
+        if constexpr (S < NSTG) {
+            constexpr int R = rad<DIR>(S), NS = span<DIR>(S), ts = L / (NS * R), o = tw_count<DIR>(S);
+#pragma unroll
+            for (int it = 0; it < iters(R); ++it) {
+                int p, b;
+                decode<R>((int)threadIdx.x + it * NT, p, b);
+                const int k = b % NS;   // idle butterflies read an in-range entry they never use
+#pragma unroll
+                for (int q = 1; q < R; ++q) {
+                    cx<T> w = gld(tw + q * k * ts);
+                    if (DIR > 0) w.y = -w.y;
+                    t.w[o + it * (R - 1) + q - 1] = w;
+                }
+            }
+            load_tw<DIR, S + 1>(t, tw);
+        }
+    }
+    template <int DIR, int R, int S>
+    __device__ static __forceinline__ void butterflies_tw(cx<T> *v, const TwReg<DIR> &t) {
+        constexpr int o = tw_count<DIR>(S);
+#pragma unroll
+        for (int it = 0; it < iters(R); ++it) {
+            cx<T> *u = v + it * R;
+            if constexpr (S > 0) {
+#pragma unroll
+                for (int q = 1; q < R; ++q) u[q] = mul(u[q], t.w[o + it * (R - 1) + q - 1]);
+            }
+            bfly<T, DIR, R>(u);
+        }
+    }
+
     // Outputs of a radix-R stage with span NS to the buffer (Stockham order).
     template <int R, int NS>
     __device__ static __forceinline__ void put(const cx<T> *v, cx<T> *buf) {
@@ -251,6 +296,26 @@ struct Fft {
             decode<R>(j, p, b);
 #pragma unroll
             for (int q = 0; q < R; ++q) v[it * R + q] = buf[lidx(p, b + q * (L / R))];
+        }
+    }
+
+    // The same transform with the twiddles of its direction from registers (any tile).
+    template <int DIR, int S = 0>
+    __device__ static __forceinline__ void run(cx<T> *v, cx<T> *lds, int &ph, const TwReg<DIR> &t) {
+        constexpr int R = rad<DIR>(S), NS = span<DIR>(S);
+        butterflies_tw<DIR, R, S>(v, t);
+        if constexpr (S + 1 < NSTG) {
+            cx<T> *buf = lds;
+            if constexpr (NB == 2) {
+                buf = lds + (ph ? TILE : 0);
+                ph ^= 1;
+            } else {
+                sync();
+            }
+            put<R, NS>(v, buf);
+            sync();
+            get<rad<DIR>(S + 1)>(v, buf);
+            run<DIR, S + 1>(v, lds, ph, t);
         }
     }
 
