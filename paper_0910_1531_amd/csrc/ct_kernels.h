@@ -216,6 +216,8 @@ __global__ __launch_bounds__(NTB) void k_z1c(Geo g_in, Z1Args a) {
     }
     cx<T> v[F::V];
     int ph = 0;
+    typename F::template TwReg<-1> trs;   // forward twiddles, shared by the species transforms
+    F::template load_tw<-1>(trs, tw);
     for (int jsp = 0; jsp < S; ++jsp) {
         const cx<T> *src = reinterpret_cast<const cx<T> *>(a.specA) + (long long)jsp * NC + off;
 #pragma unroll
@@ -241,7 +243,7 @@ __global__ __launch_bounds__(NTB) void k_z1c(Geo g_in, Z1Args a) {
                 }
             }
         }
-        F::template run<-1>(v, lds, ph, tw);
+        F::template run<-1>(v, lds, ph, trs);
         const T Rj = T(c.R[jsp]), a0 = T(c.i4piR2[jsp]), a1 = T(c.i4piR[jsp]);
         const T bath = T((double)c.N * c.rho_b[jsp]);
 #pragma unroll
