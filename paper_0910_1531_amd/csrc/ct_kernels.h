@@ -797,6 +797,9 @@ __global__ __launch_bounds__(XTile<L>::NTB) void k_x1c(Geo g_in, XFwdArgs a) {
     }
     const Geo &g = g_in;
     if (gated_off(a.gate)) return;
+    // wave-private tiles: twiddles fetched up front, with the data
+    typename F::Twiddles trw;
+    if constexpr (F::WP) F::load_twiddles(trw, twp<T>(g_in, 0));
     __shared__ cx<T> lds[F::LDS_ELEMS + F::TILE];
     cx<T> *split = lds + F::LDS_ELEMS;
     const int f = blockIdx.y;
@@ -835,7 +838,8 @@ __global__ __launch_bounds__(XTile<L>::NTB) void k_x1c(Geo g_in, XFwdArgs a) {
         v[i] = mk<T>(T(x[0]), T(x[1]));
     }
     int ph = 0;
-    F::template run<-1>(v, lds, ph, twp<T>(g, 0));
+    if constexpr (F::WP) F::template run<-1>(v, lds, ph, trw);
+    else F::template run<-1>(v, lds, ph, twp<T>(g, 0));
 #pragma unroll
     for (int i = 0; i < F::template nout<-1>(); ++i) {
         int p, e;
@@ -861,6 +865,9 @@ __global__ __launch_bounds__(XTile<L>::NTB) void k_x3c(Geo g_in, X3Args a) {
     }
     const Geo &g = g_in;
     if (gated_off(a.gate)) return;
+    // wave-private tiles: twiddles fetched up front, with the data
+    typename F::Twiddles trw;
+    if constexpr (F::WP) F::load_twiddles(trw, twp<T>(g_in, 0));
     __shared__ cx<T> lds[F::LDS_ELEMS];
     const Consts &c = *g.cs;
     const int sp = blockIdx.y;
@@ -886,7 +893,8 @@ __global__ __launch_bounds__(XTile<L>::NTB) void k_x3c(Geo g_in, X3Args a) {
         v[i] = cv;
     }
     int ph = 0;
-    F::template run<1>(v, lds, ph, twp<T>(g, 0));
+    if constexpr (F::WP) F::template run<1>(v, lds, ph, trw);
+    else F::template run<1>(v, lds, ph, twp<T>(g, 0));
     double acc = 0.0;
     int flag = 0;
     const double rb = c.rho_b[sp], irb = c.inv_rho_b[sp], zs = c.z[sp];
