@@ -163,7 +163,8 @@ dft_status dft_workspace_size(const dft_params *params, size_t *bytes);
  *   stream        hipStream_t as void* (NULL = default stream).
  *   out           receives the new ctx (host).
  * Errors: DFT_E_INVALID_ARG, DFT_E_UNSUPPORTED_SIZE, DFT_E_NOT_NEUTRAL, DFT_E_WORKSPACE
- * before any HIP call; DFT_E_DEVICE if a HIP call fails.
+ * before any HIP call; DFT_E_INVALID_ARG also when beta_vext excludes every centre of every
+ * species (no fluid node); DFT_E_DEVICE if a HIP call fails.
  */
 dft_status dft_setup(const dft_params *params, const double *beta_vext, const double *fixed_charge,
                      void *workspace, size_t ws_bytes, void *stream, dft_ctx **out);
@@ -179,6 +180,8 @@ dft_status dft_set_stream(dft_ctx *ctx, void *stream);
  *   norm_out  host double (NULL to skip); if given, the stream is synchronized.
  * Uses the ctx's precision: in FP32-mixed mode the FP32 transforms act on rho - rho_ref
  * around the ctx's current reference state (set by dft_set_reference or dft_solve).
+ * A non-finite evaluation (n3 >= 1 somewhere, or a non-finite rho) returns DFT_OK with
+ * r = +inf; G is then not finite where the evaluation broke down.
  */
 dft_status dft_residual(dft_ctx *ctx, const double *rho, double *g_out, double *norm_out);
 

@@ -536,7 +536,7 @@ dft_status dft_setup(const dft_params *params, const double *beta_vext, const do
         launch_sum_to(cnt, lay.count_blocks, &c->st->nfluid, c->stream);
         HIPCHK(hipMemcpyAsync(&nfl, &c->st->nfluid, sizeof(double), hipMemcpyDeviceToHost, c->stream));
         HIPCHK(hipStreamSynchronize(c->stream));
-        if (!(nfl > 0.0)) throw std::runtime_error("no fluid node: every centre is excluded");
+        if (!(nfl > 0.0)) return fail(DFT_E_INVALID_ARG, "no fluid node: every centre is excluded");
         c->hc.nfluid = nfl;
         HIPCHK(hipMemcpyAsync(c->cs, &c->hc, sizeof(Consts), hipMemcpyHostToDevice, c->stream));
         DevState h = fresh_state(c, 0.0, 0);

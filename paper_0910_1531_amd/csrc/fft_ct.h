@@ -3,7 +3,8 @@
 // A tile holds P pencils of length L.  Each thread owns whole butterflies: the stage of
 // radix R has L P / R butterflies spread over the NT threads of the block, and a thread
 // keeps the R values of each of its butterflies in registers.  Between stages the values
-// go through one of two LDS buffers used in turn, so each exchange needs one barrier.
+// go through one of two LDS buffers used in turn, so each exchange needs one barrier (a
+// wave-level fence only, where every wave owns whole pencils: see wave_private).
 // The first stage takes its inputs from registers that the caller filled (straight from
 // HBM) and the last stage leaves its outputs in registers (stored straight to HBM), so a
 // transform costs (stages - 1) LDS round trips.  The inverse transform runs the radices
@@ -13,6 +14,9 @@
 //
 // With L, P, NT and the radices fixed at compile time every index is a constant or a
 // shift, and the stage loop unrolls completely (no run-time plan, no scratch memory).
+// Twiddles are read from the per-axis table at each stage, or, for blocks that run several
+// transforms in one direction, loaded once into registers (TwReg, or Twiddles for
+// wave-private tiles, which serve both directions).
 #pragma once
 
 #include "dft_device.h"
