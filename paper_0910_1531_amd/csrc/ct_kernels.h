@@ -277,7 +277,9 @@ __global__ __launch_bounds__(NTB) void k_z1c(Geo g_in, Z1Args a) {
 #pragma unroll
                     for (int is = 0; is < MS; ++is) {
                         if (is < S) {
-                            // sin, cos of k (R_i + R_j) by the addition theorem
+                            // sin, cos of k (R_i + R_j) by the addition theorem: the contact
+                            // cutoff (the launcher sends the cutoff at lambda_i + lambda_j to the
+                            // run-time-length kernel)
                             const T sp = sn[is][i] * cj + cs[is][i] * sj;
                             const T cp = cs[is][i] * cj - sn[is][i] * sj;
                             const int ij = is * DFT_MAX_SPECIES + jsp;

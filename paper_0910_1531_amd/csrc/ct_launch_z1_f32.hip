@@ -36,6 +36,9 @@ static void launch_z1c_len(const Geo &g, const Z1Args &a, int es, hipStream_t s,
 template <>
 bool launch_z1_ct<float>(const Geo &g, const Z1Args &a, int es, hipStream_t s) {
     if (!g.tab64) return false;   // no spectral tables (or S > 4 with electrostatics): run-time kernel
+    // the on-the-fly pair factors take sin and cos of k (R_i + R_j) by the addition theorem, so a
+    // screening cutoff at lambda_i + lambda_j runs the run-time-length kernel
+    if (es && g.cut_lambda) return false;
     const int v = g.tune[TUNE_Z1][std::is_same<float, float>::value ? 1 : 0];
     switch (g.nz) {
 #define DFT_CASE(n) case n: launch_z1c_len<float, n>(g, a, es, s, v); return true;

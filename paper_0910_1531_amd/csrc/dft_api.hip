@@ -470,6 +470,7 @@ dft_status dft_setup(const dft_params *params, const double *beta_vext, const do
         g.Kx = c->hc.Kx;
         g.S = params->nspecies;
         g.es = c->hc.es;
+        g.cut_lambda = c->hc.cut_lambda;
         g.N = c->hc.N;
         g.NC = c->hc.NC;
         DevPlan *dp[3] = {&g.px, &g.py, &g.pz};
@@ -1250,7 +1251,7 @@ dft_status dft_rfd_reference(dft_ctx *ctx, const double *f, const double *rsc, i
 struct dft_batch {
     std::vector<dft_ctx *> members;   // caller order; each owns a slice of the batch workspace
     struct Group {
-        std::vector<int> idx;         // members of one shape (n, S, precision, functional)
+        std::vector<int> idx;         // members sharing launch choices (see same_shape)
         dft_ctx *lead = nullptr;      // geometry covering the whole group (nprob, pstride)
         long long stride = 0;
     };
@@ -1260,9 +1261,13 @@ struct dft_batch {
 
 namespace {
 
+// Points of one group share the launch choices of its lead: grid, species count, precision,
+// functional, electrostatics on/off and the screening cutoff.
 bool same_shape(const dft_params &a, const dft_params &b) {
     return a.n[0] == b.n[0] && a.n[1] == b.n[1] && a.n[2] == b.n[2] && a.nspecies == b.nspecies &&
-           a.precision == b.precision && a.hs_functional == b.hs_functional;
+           a.precision == b.precision && a.hs_functional == b.hs_functional &&
+           a.electrostatics == b.electrostatics &&
+           (a.flags & DFT_FLAG_CUTOFF_LAMBDA) == (b.flags & DFT_FLAG_CUTOFF_LAMBDA);
 }
 
 // Groups (first-seen order) and the byte offset of every member in the batch workspace.

@@ -324,6 +324,7 @@ void fill_consts(const dft_params *p, const dft_bulk_info &b, Consts *c) {
     c->nz = p->n[2];
     c->Kx = p->n[0] / 2 + 1;
     c->es = p->electrostatics ? 1 : 0;
+    c->cut_lambda = (p->flags & DFT_FLAG_CUTOFF_LAMBDA) ? 1 : 0;
     c->N = (long long)p->n[0] * p->n[1] * p->n[2];
     c->NC = (long long)c->Kx * p->n[1] * p->n[2];
     c->invN = 1.0 / (double)c->N;

@@ -25,6 +25,7 @@ struct FftPlan {
 struct Consts {
     int S, nx, ny, nz, Kx;
     int es;                 // electrostatics on
+    int cut_lambda;         // screening kernel cut at lambda_i + lambda_j (not R_i + R_j)
     long long N;            // nx * ny * nz
     long long NC;           // nz * ny * Kx (complex values per half spectrum)
     double invN;

@@ -33,6 +33,7 @@ struct Geo {
     const void *tw32[3];   // cx<float> tables per axis
     int nx, ny, nz, Kx, S;
     int es;                // electrostatics on (mirrors Consts::es for launch choices)
+    int cut_lambda;        // screening cutoff at lambda_i + lambda_j (mirrors Consts::cut_lambda)
     long long N, NC;
     // Batches of identically shaped problems: the kernels of one launch cover nprob
     // problems whose workspaces sit pstride bytes apart (blockIdx.z carries the problem).
