@@ -76,22 +76,23 @@ def _perturbed(prob, field, k, delta):
     return p
 
 
-def dlnG_dtheta(prob, rho, field, k, rel=1e-6):
+def dlnG_dtheta(prob, rho, field, k, rel=1e-6, cutoff="contact"):
     """Central difference of ln G_i(rho) (fluid nodes) in rho_bulk[k] or sigma[k], rho fixed."""
     base = prob.rho_bulk[k] if field == "rho_bulk" else 2.0 * prob.radius[k]
     d = rel * base
-    Gp = residual.Setup(_perturbed(prob, field, k, d)).evaluate(rho)["G"]
-    Gm = residual.Setup(_perturbed(prob, field, k, -d)).evaluate(rho)["G"]
+    Gp = residual.Setup(_perturbed(prob, field, k, d), cutoff=cutoff).evaluate(rho)["G"]
+    Gm = residual.Setup(_perturbed(prob, field, k, -d), cutoff=cutoff).evaluate(rho)["G"]
     with np.errstate(divide="ignore", invalid="ignore"):
         out = (np.log(Gp) - np.log(Gm)) / (2.0 * d)
     return np.where(np.isfinite(out), out, 0.0)
 
 
-def gradient(prob, rho, dO_drho, tol=1e-12):
-    """dO/d(beta V) [S, ...], dO/d rho_bulk [S] and dO/d sigma [S] at the fixed point rho."""
-    st = residual.Setup(prob)
+def gradient(prob, rho, dO_drho, tol=1e-12, cutoff="contact"):
+    """dO/d(beta V) [S, ...], dO/d rho_bulk [S] and dO/d sigma [S] at the fixed point rho
+    (cutoff: the screening-kernel cutoff of residual.Setup)."""
+    st = residual.Setup(prob, cutoff=cutoff)
     w, G = adjoint_weights(st, rho, dO_drho, tol=tol)
     S = prob.nspecies
-    d_rho_b = np.array([np.sum(w * dlnG_dtheta(prob, rho, "rho_bulk", k)) for k in range(S)])
-    d_sigma = np.array([np.sum(w * dlnG_dtheta(prob, rho, "sigma", k)) for k in range(S)])
+    d_rho_b = np.array([np.sum(w * dlnG_dtheta(prob, rho, "rho_bulk", k, cutoff=cutoff)) for k in range(S)])
+    d_sigma = np.array([np.sum(w * dlnG_dtheta(prob, rho, "sigma", k, cutoff=cutoff)) for k in range(S)])
     return {"vext": -w, "rho_bulk": d_rho_b, "sigma": d_sigma, "w": w}

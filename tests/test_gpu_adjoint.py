@@ -171,3 +171,23 @@ def test_pore192_adjoint_matches_central_differences():
              f"max {rel.max():.2e}, max |g| {np.abs(ref).max():.2e}, re-solve r <= {rmax:.1e}")
         if step == 1e-3:
             assert np.median(rel) < 1e-5 and rel.max() < 1e-3
+
+
+def test_adjoint_with_the_lambda_cutoff_matches_oracle():
+    # the screening cutoff at lambda_i + lambda_j moves with Gamma, hence with rho_b and sigma
+    p = W.charged_sphere(n=16, h=0.1, sigma=(0.3, 0.24), conc=(0.5, 0.5), sphere_radius=0.25,
+                         sphere_charge=-1.0)
+    d = W._dist_to_point(p.n, p.h, p.extra["centre"])
+    mask = (d >= 0.39) & (d < 0.55)
+    _say("adjoint vs oracle, lambda cutoff")
+    st = residual.Setup(p, cutoff="lambda")
+    rho = picard.solve(st, p.initial_density(), 1e-13).rho
+    g = np.zeros_like(rho)
+    g[0][mask] = np.prod(p.h)
+    ref = oadj.gradient(p, rho, g, cutoff="lambda")
+    sol = _solver(p, flags=_abi.FLAG_CUTOFF_LAMBDA)
+    out = sol.adjoint(_dev(rho), _dev(g), tol=1e-12)
+    _say(f"  CG iterations {out['iters']}, residual {out['resid']:.1e}")
+    _check("dO/dbetaV", out["vext"].cpu().numpy(), ref["vext"])
+    _check("dO/drho_b", out["rho_bulk"], ref["rho_bulk"])
+    _check("dO/dsigma", out["sigma"], ref["sigma"])
