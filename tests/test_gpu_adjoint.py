@@ -191,3 +191,24 @@ def test_adjoint_with_the_lambda_cutoff_matches_oracle():
     _check("dO/dbetaV", out["vext"].cpu().numpy(), ref["vext"])
     _check("dO/drho_b", out["rho_bulk"], ref["rho_bulk"])
     _check("dO/dsigma", out["sigma"], ref["sigma"])
+
+
+def test_adjoint_and_newton_on_a_mixed_precision_context():
+    # Both run FP64 evaluations whatever the context's precision: the same results as on an FP64
+    # context, to rounding.
+    p = W.charged_pore(n=32, h=0.0625)
+    mask = W.pore_observable_mask(p, half_length=0.6)
+    st = residual.Setup(p)
+    rho = picard.solve(st, p.initial_density(), 1e-13).rho
+    g = np.zeros_like(rho)
+    g[0][mask] = np.prod(p.h)
+    a64 = _solver(p).adjoint(_dev(rho), _dev(g), tol=1e-12)
+    a32 = _solver(p, precision=_abi.DFT_FP32_MIXED).adjoint(_dev(rho), _dev(g), tol=1e-12)
+    _check("dO/dbetaV (mixed ctx)", a32["vext"].cpu().numpy(), a64["vext"].cpu().numpy())
+    _check("dO/dsigma (mixed ctx)", a32["sigma"], a64["sigma"])
+    sol = _solver(p, precision=_abi.DFT_FP32_MIXED)
+    x = _dev(p.initial_density())
+    it, cg, r, status = sol.newton(x, 1e-11, 60)
+    err = float(np.max(np.abs(x.cpu().numpy() - rho)) / np.max(np.abs(rho)))
+    _say(f"  Newton on the mixed context: {it} steps, r {r:.1e}, rho rel diff {err:.1e}")
+    assert status == 0 and r <= 1e-11 and err < 1e-9
