@@ -974,8 +974,13 @@ template void launch_x3<double>(const Geo &, const X3Args &, hipStream_t);
 template void launch_x3<float>(const Geo &, const X3Args &, hipStream_t);
 
 // --------------------------------------------------------------------- reductions, control
-__global__ __launch_bounds__(NT) void k_finalize(RedBufs r, int nf, int nm, double *fslot, double *mslot,
-                                                 DevState *st, int count_kind, const int *gate, long long pstride) {
+// Reduction of the per-block partials of one evaluation into its state slots: 1024 threads,
+// four independent accumulators per thread over fixed strides, then wave and block trees in
+// fixed order, so the result is the same for every launch of the same shape.
+constexpr int kNTF = 1024;
+
+__global__ __launch_bounds__(kNTF) void k_finalize(RedBufs r, int nf, int nm, double *fslot, double *mslot,
+                                                   DevState *st, int count_kind, const int *gate, long long pstride) {
     const long long off = (long long)blockIdx.x * pstride;
     gate = shp(gate, off);
     if (gated_off(gate)) return;
@@ -983,28 +988,55 @@ __global__ __launch_bounds__(NT) void k_finalize(RedBufs r, int nf, int nm, doub
     fslot = shp(fslot, off);
     mslot = shp(mslot, off);
     st = shp(st, off);
-    __shared__ double ss[NT], sm[NT];
-    __shared__ int sf[NT];
-    double a = 0.0, m = -INFINITY;
+    __shared__ double ss[kNTF / 64], sm[kNTF / 64];
+    __shared__ int sf[kNTF / 64];
+    const int t = threadIdx.x;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    double m0 = -INFINITY, m1 = -INFINITY;
     int fl = 0;
-    for (int b = threadIdx.x; b < nf; b += NT) { a += r.fpart[b]; fl |= r.fflag[b]; }
-    for (int b = threadIdx.x; b < nm; b += NT) { m = fmax(m, r.mpart[b]); fl |= r.mflag[b]; }
-    ss[threadIdx.x] = a;
-    sm[threadIdx.x] = m;
-    sf[threadIdx.x] = fl;
-    __syncthreads();
-    for (int w = NT / 2; w > 0; w >>= 1) {
-        if (threadIdx.x < w) {
-            ss[threadIdx.x] += ss[threadIdx.x + w];
-            sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + w]);
-            sf[threadIdx.x] |= sf[threadIdx.x + w];
-        }
-        __syncthreads();
+    int b = t;
+    for (; b + 3 * kNTF < nf; b += 4 * kNTF) {
+        a0 += r.fpart[b];
+        a1 += r.fpart[b + kNTF];
+        a2 += r.fpart[b + 2 * kNTF];
+        a3 += r.fpart[b + 3 * kNTF];
+        fl |= r.fflag[b] | r.fflag[b + kNTF] | r.fflag[b + 2 * kNTF] | r.fflag[b + 3 * kNTF];
     }
-    if (threadIdx.x == 0) {
-        const bool bad = (sf[0] & 1) || !isfinite(ss[0]);
-        if (fslot) *fslot = bad ? INFINITY : ss[0];
-        if (mslot) *mslot = (sf[0] & 4) ? INFINITY : sm[0];
+    for (; b < nf; b += kNTF) {
+        a0 += r.fpart[b];
+        fl |= r.fflag[b];
+    }
+    b = t;
+    for (; b + kNTF < nm; b += 2 * kNTF) {
+        m0 = fmax(m0, r.mpart[b]);
+        m1 = fmax(m1, r.mpart[b + kNTF]);
+        fl |= r.mflag[b] | r.mflag[b + kNTF];
+    }
+    for (; b < nm; b += kNTF) {
+        m0 = fmax(m0, r.mpart[b]);
+        fl |= r.mflag[b];
+    }
+    double a = wave_sum((a0 + a1) + (a2 + a3));
+    double m = wave_max(fmax(m0, m1));
+    fl = wave_or(fl);
+    const int w = t / 64;
+    if (t % 64 == 0) {
+        ss[w] = a;
+        sm[w] = m;
+        sf[w] = fl;
+    }
+    __syncthreads();
+    if (t == 0) {
+        double sa = ss[0], sx = sm[0];
+        int sfl = sf[0];
+        for (int i = 1; i < kNTF / 64; ++i) {
+            sa += ss[i];
+            sx = fmax(sx, sm[i]);
+            sfl |= sf[i];
+        }
+        const bool bad = (sfl & 1) || !isfinite(sa);
+        if (fslot) *fslot = bad ? INFINITY : sa;
+        if (mslot) *mslot = (sfl & 4) ? INFINITY : sx;
         if (st) {
             if (count_kind == 1) st->gevals += 1;
             if (count_kind == 2) st->n3evals += 1;
@@ -1014,7 +1046,7 @@ __global__ __launch_bounds__(NT) void k_finalize(RedBufs r, int nf, int nm, doub
 
 void launch_finalize(const RedBufs &r, int nf, int nm, double *fslot, double *mslot, DevState *st, int count_kind,
                      const int *gate, hipStream_t s, int nprob, long long pstride) {
-    hipLaunchKernelGGL(k_finalize, dim3(nprob), dim3(NT), 0, s, r, nf, nm, fslot, mslot, st, count_kind, gate,
+    hipLaunchKernelGGL(k_finalize, dim3(nprob), dim3(kNTF), 0, s, r, nf, nm, fslot, mslot, st, count_kind, gate,
                        pstride);
     check_launch("finalize");
 }
