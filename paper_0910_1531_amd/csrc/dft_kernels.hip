@@ -1159,7 +1159,22 @@ __global__ __launch_bounds__(NT) void k_update(const DevState *st, double *rho0,
     const double alpha = st->alpha_acc;
     const int src = st->src;
     const double *gsrc = shp(src == 0 ? gb : (src == 1 ? ga : gs), off);
-    for (long long i = (long long)blockIdx.x * NT + threadIdx.x; i < count; i += (long long)gridDim.x * NT) {
+    // pairs of values per thread (16-byte accesses; the arrays are 256-byte aligned), odd tail last
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    const long long npair = count / 2;
+    d2 *r2 = reinterpret_cast<d2 *>(rho0);
+    d2 *g2 = reinterpret_cast<d2 *>(g0);
+    const d2 *s2 = reinterpret_cast<const d2 *>(gsrc);
+    for (long long i = (long long)blockIdx.x * NT + threadIdx.x; i < npair; i += (long long)gridDim.x * NT) {
+        const d2 r = r2[i], g = g2[i], n = s2[i];
+        d2 o;
+        o.x = fma(alpha, g.x - r.x, r.x);
+        o.y = fma(alpha, g.y - r.y, r.y);
+        r2[i] = o;
+        g2[i] = n;
+    }
+    if ((count & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+        const long long i = count - 1;
         const double r = rho0[i];
         rho0[i] = fma(alpha, g0[i] - r, r);
         g0[i] = gsrc[i];
@@ -1168,7 +1183,7 @@ __global__ __launch_bounds__(NT) void k_update(const DevState *st, double *rho0,
 
 void launch_update(DevState *st, double *rho0, double *g0, const double *gb, const double *ga, const double *gs,
                    long long count, hipStream_t s, int nprob, long long pstride) {
-    const long long nb = std::min<long long>(ceil_div(count, NT), 8192);
+    const long long nb = std::max<long long>(1, std::min<long long>(ceil_div(count / 2, NT), 16384));
     hipLaunchKernelGGL(k_update, dim3((unsigned)nb, (unsigned)nprob), dim3(NT), 0, s, st, rho0, g0, gb, ga, gs, count,
                        pstride);
     check_launch("update");
