@@ -373,7 +373,7 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build runs on one GPU; multi-GPU sharding of the grid (slab FFT with an "
+        print("bench.py: the solver runs on one GPU; multi-GPU sharding of the grid (slab FFT with an "
               "all-to-all) is a design note only, so --gpus must be 1", file=sys.stderr)
         sys.exit(2)
 
