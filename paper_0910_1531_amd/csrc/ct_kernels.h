@@ -33,10 +33,13 @@ inline long long ct_cdiv(long long a, long long b) { return (a + b - 1) / b; }
 // ------------------------------------------------------------------ y / z plain transforms
 // One block transforms P adjacent columns (kx) of one field along y (one z plane) or z
 // (one y line); the pencils' elements sit rs apart in HBM and P columns are contiguous.
-template <typename T, int L, int P, int NTB, int NB>
+template <typename T, int L, int P, int NTB, int NB, int VEC>
 __global__ __launch_bounds__(NTB) void k_yc(Geo g_in, YArgs a) {
     using F = ct::Fft<T, typename ct::Plan<L>::type, P, NTB, false, NB>;
-    const int prob = (int)blockIdx.z / a.nfield;
+    // blocks per problem: one per field, or per block type of the compact vector layout
+    // (VEC = YArgs::vec, a template parameter so that the plain transforms keep their registers)
+    const int ntypes = VEC == 1 ? 7 : (VEC == 2 ? 8 : a.nfield);
+    const int prob = (int)blockIdx.z / ntypes;
     if (prob > 0) {
         const long long off = (long long)prob * g_in.pstride;
         g_in = shift(g_in, off);
@@ -51,27 +54,95 @@ __global__ __launch_bounds__(NTB) void k_yc(Geo g_in, YArgs a) {
     xcd_block(bx, o);
     const int kx0 = bx * P;
     const int Pact = min(P, Kx - kx0);
-    const int f = (int)blockIdx.z % a.nfield;
+    const int f = (int)blockIdx.z % ntypes;
     const long long rs = zax ? (long long)g.ny * Kx : (long long)Kx;
     const long long ob = zax ? (long long)o * Kx : (long long)o * g.ny * Kx;
-    cx<T> *base = reinterpret_cast<cx<T> *>(a.spec) + (long long)f * g.NC + ob + kx0;
+    cx<T> *spec = reinterpret_cast<cx<T> *>(a.spec) + ob + kx0;
     const cx<T> *tw = twp<T>(g, zax ? 2 : 1);
     cx<T> v[F::V];
     int ph = 0;
     auto body = [&](auto dirc) {
         constexpr int DIR = decltype(dirc)::value;
+        auto load = [&](int slot, cx<T> *w) {
+            const cx<T> *base = spec + (long long)slot * g.NC;
 #pragma unroll
-        for (int i = 0; i < F::template nin<DIR>(); ++i) {
-            int p, e;
-            const bool ok = F::template in_pos<DIR>(i, p, e);
-            v[i] = (ok && p < Pact) ? ct::gld(base + e * rs + p) : mk<T>(T(0), T(0));
-        }
-        F::template run<DIR>(v, lds, ph, tw);
+            for (int i = 0; i < F::template nin<DIR>(); ++i) {
+                int p, e;
+                const bool ok = F::template in_pos<DIR>(i, p, e);
+                w[i] = (ok && p < Pact) ? ct::gld(base + e * rs + p) : mk<T>(T(0), T(0));
+            }
+        };
+        // store slot, times -i k_x when mx (k_x of the column, zero on the Nyquist column)
+        auto store = [&](int slot, const cx<T> *w, bool mx) {
+            cx<T> *base = spec + (long long)slot * g.NC;
 #pragma unroll
-        for (int i = 0; i < F::template nout<DIR>(); ++i) {
-            int p, e;
-            const bool ok = F::template out_pos<DIR>(i, p, e);
-            if (ok && p < Pact) ct::gst(base + e * rs + p, v[i]);
+            for (int i = 0; i < F::template nout<DIR>(); ++i) {
+                int p, e;
+                const bool ok = F::template out_pos<DIR>(i, p, e);
+                if (!(ok && p < Pact)) continue;
+                cx<T> u = w[i];
+                if (mx) {
+                    const int jx = kx0 + p;
+                    const T kx = (g.nx % 2 == 0 && 2 * jx == g.nx) ? T(0) : T(jx) * T(g.cs->dk[0]);
+                    u = mk<T>(kx * u.y, -kx * u.x);
+                }
+                ct::gst(base + e * rs + p, u);
+            }
+        };
+        // k_y of element e of the pencil (zero on the Nyquist row)
+        auto ky = [&](int e) {
+            return (g.ny % 2 == 0 && 2 * e == g.ny) ? T(0) : T(signed_mode(e, g.ny)) * T(g.cs->dk[1]);
+        };
+        if constexpr (VEC == 0) {
+            load(f, v);
+            F::template run<DIR>(v, lds, ph, tw);
+            store(f, v, false);
+        } else if constexpr (VEC == 1) {
+            // inverse: slots 0-3 (n0..n3), 4 (nV1 sum), 6, 9 (z components) -> the ten fields;
+            // n3 also gives nV2_x = -i k_x n3 and nV2_y, the nV1 sum gives nV1_x and nV1_y
+            const int slot = f < 5 ? f : (f == 5 ? 6 : 9);
+            load(slot, v);
+            if (slot == 3 || slot == 4) {
+                cx<T> w[F::V];
+#pragma unroll
+                for (int i = 0; i < F::template nin<DIR>(); ++i) {
+                    int p, e;
+                    F::template in_pos<DIR>(i, p, e);
+                    const T k = ky(e);
+                    w[i] = mk<T>(k * v[i].y, -k * v[i].x);   // -i k_y
+                }
+                F::template run<DIR>(v, lds, ph, tw);
+                if (slot == 3) {
+                    store(3, v, false);
+                    store(7, v, true);
+                } else {
+                    store(4, v, true);
+                }
+                F::template run<DIR>(w, lds, ph, tw);
+                store(slot == 3 ? 8 : 5, w, false);
+            } else {
+                F::template run<DIR>(v, lds, ph, tw);
+                store(slot, v, false);
+            }
+        } else {
+            // forward: ten fields -> slots 0-3, 4 (i k_x dPhi_V1x + i k_y dPhi_V1y), 6, 7 (the same
+            // for V2), 9; the x parts arrive multiplied by i k_x
+            const int slot = f < 5 ? f : (f == 5 ? 6 : (f == 6 ? 7 : 9));
+            load(slot, v);
+            F::template run<DIR>(v, lds, ph, tw);
+            if (slot == 4 || slot == 7) {
+                cx<T> w[F::V];
+                load(slot + 1, w);
+                F::template run<DIR>(w, lds, ph, tw);
+#pragma unroll
+                for (int i = 0; i < F::template nout<DIR>(); ++i) {
+                    int p, e;
+                    F::template out_pos<DIR>(i, p, e);
+                    const T k = ky(e);
+                    v[i] = mk<T>(v[i].x - k * w[i].y, v[i].y + k * w[i].x);   // + i k_y w
+                }
+            }
+            store(slot, v, false);
         }
     };
     if (a.dir < 0) body(std::integral_constant<int, -1>());
@@ -359,6 +430,9 @@ __global__ __launch_bounds__(NTB) void k_z1c(Geo g_in, Z1Args a) {
         };
         if (a.n3only) {
             store(0, -1);
+        } else if (g.compact) {
+            // compact layout: n0..n3, the nV1 sum, nV1_z, nV2_z (the inverse y pass expands)
+            store(t < 5 ? t : (t == 5 ? 6 : 9), -1);
         } else if (t < 4) {
             store(t, -1);
             if (t == 3) {
@@ -497,8 +571,9 @@ __global__ __launch_bounds__(NTB) void k_z2c(Geo g_in, Z2Args a) {
     // 4, 6 the combined x, y parts of V1, V2; 5, 7 their z parts.
     for (int t = 0; t < 8; ++t) {
         const int m = t < 4 ? t : (t < 6 ? 4 : 5);
-        if (t < 4 || t == 5 || t == 7) {
-            const int al = t < 4 ? t : (t == 5 ? 6 : 9);
+        if (t < 4 || t == 5 || t == 7 || g.compact) {
+            // compact layout: slots 4 and 7 already hold i k_x dPhi_x + i k_y dPhi_y
+            const int al = t < 4 ? t : (t == 4 ? 4 : (t == 5 ? 6 : (t == 6 ? 7 : 9)));
             load_fwd(reinterpret_cast<const cx<T> *>(a.specB) + (long long)al * NC + off);
         } else {
             const int al = t == 4 ? 4 : 7;
@@ -601,15 +676,24 @@ __device__ __forceinline__ cx<T> half_at(const cx<T> *row, int e) {
 // (C held in split): A_k = (C_k + conj C_{L-k}) / 2, B_k = (C_k - conj C_{L-k}) / (2i).  In a
 // wave-private tile each wave splits its own pencils (lanes along k); otherwise the block does
 // (split must have been synchronized accordingly by the caller).
+// With dkx > 0 both half spectra are multiplied by i k_x (k_x = k dkx, zero on the Nyquist column).
 template <typename T, int L, class F>
-__device__ __forceinline__ void split_rows(const cx<T> *split, cx<T> *out, long long pair0, int Pact, long long rows) {
+__device__ __forceinline__ void split_rows(const cx<T> *split, cx<T> *out, long long pair0, int Pact, long long rows,
+                                           T dkx = T(0)) {
     constexpr int KX = L / 2 + 1;
     auto one = [&](int p, int k) {
         const cx<T> ck = split[F::lidx(p, k)];
         const cx<T> cm = split[F::lidx(p, k == 0 ? 0 : L - k)];
         const long long r0 = 2 * (pair0 + p);
-        ct::gst(out + r0 * KX + k, mk<T>(T(0.5) * (ck.x + cm.x), T(0.5) * (ck.y - cm.y)));
-        if (r0 + 1 < rows) ct::gst(out + (r0 + 1) * KX + k, mk<T>(T(0.5) * (ck.y + cm.y), T(-0.5) * (ck.x - cm.x)));
+        cx<T> A = mk<T>(T(0.5) * (ck.x + cm.x), T(0.5) * (ck.y - cm.y));
+        cx<T> B = mk<T>(T(0.5) * (ck.y + cm.y), T(-0.5) * (ck.x - cm.x));
+        if (dkx > T(0)) {
+            const T kx = (L % 2 == 0 && 2 * k == L) ? T(0) : T(k) * dkx;
+            A = mk<T>(-kx * A.y, kx * A.x);
+            B = mk<T>(-kx * B.y, kx * B.x);
+        }
+        ct::gst(out + r0 * KX + k, A);
+        if (r0 + 1 < rows) ct::gst(out + (r0 + 1) * KX + k, B);
     };
     if constexpr (F::WP) {
         constexpr int nb = L / 4;
@@ -779,7 +863,9 @@ __global__ __launch_bounds__(XTile<L>::NTB) void k_x2c(Geo g_in, X2Args a) {
             if (F::template out_pos<-1>(i, p, e)) split[F::lidx(p, e)] = v[i];
         }
         F::sync();
-        split_rows<T, L, F>(split, reinterpret_cast<cx<T> *>(a.specB) + (long long)f * NC, pair0, Pact, rows);
+        // compact layout: the x components of the vector derivatives leave multiplied by i k_x
+        const T dkx = (g.compact && (f == 4 || f == 7)) ? T(g.cs->dk[0]) : T(0);
+        split_rows<T, L, F>(split, reinterpret_cast<cx<T> *>(a.specB) + (long long)f * NC, pair0, Pact, rows, dkx);
     }
 }
 

@@ -30,8 +30,14 @@ static bool launch_yc_var(const Geo &g, const YArgs &a, hipStream_t s) {
     } else {
         constexpr int NTB = fit_threads(L, P, y_per_thread(V), 256);
         const bool zax = a.axis == 2;
-        dim3 grid((unsigned)ct_cdiv(g.Kx, P), (unsigned)(zax ? g.ny : g.nz), (unsigned)(a.nfield * g.nprob));
-        hipLaunchKernelGGL((k_yc<T, L, P, NTB, NB>), grid, dim3(NTB), 0, s, g, a);
+        const int ntypes = a.vec == 1 ? 7 : (a.vec == 2 ? 8 : a.nfield);
+        dim3 grid((unsigned)ct_cdiv(g.Kx, P), (unsigned)(zax ? g.ny : g.nz), (unsigned)(ntypes * g.nprob));
+        if (a.vec == 1)
+            hipLaunchKernelGGL((k_yc<T, L, P, NTB, NB, 1>), grid, dim3(NTB), 0, s, g, a);
+        else if (a.vec == 2)
+            hipLaunchKernelGGL((k_yc<T, L, P, NTB, NB, 2>), grid, dim3(NTB), 0, s, g, a);
+        else
+            hipLaunchKernelGGL((k_yc<T, L, P, NTB, NB, 0>), grid, dim3(NTB), 0, s, g, a);
         ct_check("y (compiled length)");
         return true;
     }

@@ -177,6 +177,7 @@ void enqueue_eval_t(dft_ctx *c, const Eval &ev, hipStream_t s) {
     launch_z1<T>(g, z1, s);
     mark(ev, 3, s);
     YArgs yb{c->specB, DFT_NALPHA, 1, ev.gate};
+    yb.vec = g.compact ? 1 : 0;
     launch_y<T>(g, yb, s);
     mark(ev, 4, s);
     X2Args x2{};
@@ -192,6 +193,7 @@ void enqueue_eval_t(dft_ctx *c, const Eval &ev, hipStream_t s) {
     launch_x2<T>(g, x2, s);
     mark(ev, 5, s);
     YArgs yc{c->specB, DFT_NALPHA, -1, ev.gate};
+    yc.vec = g.compact ? 2 : 0;
     launch_y<T>(g, yc, s);
     mark(ev, 6, s);
     Z2Args z2{};
@@ -496,6 +498,9 @@ dft_status dft_setup(const dft_params *params, const double *beta_vext, const do
             g.tab64 = (const double *)(w + lay.tab64);
             launch_spec_tables(g, c->stream);
         }
+        // compact vector layout when every pass of the evaluation runs a compiled-length kernel
+        g.compact = (g.tab64 && x_ct_pairs(g.nx) > 0 && y_ct_variants(g.ny, false) > 0 &&
+                     z_ct_variants(g.nz) > 0 && !(g.es && g.cut_lambda)) ? 1 : 0;
         if (!(params->flags & DFT_FLAG_NO_AUTOTUNE)) {
             TuneBufs tb{c->specA, 2 * sizeof(double) * (size_t)g.NC * g.S, c->specB,
                         2 * sizeof(double) * (size_t)g.NC * DFT_NALPHA};
@@ -857,6 +862,7 @@ void enqueue_hess(dft_ctx *c, const double *u, double *hu, const double *nstar, 
     Z1Args z1{c->specA, c->specB, 0, 1, nullptr};
     launch_z1<double>(g, z1, s);
     YArgs yb{c->specB, DFT_NALPHA, 1, nullptr};
+    yb.vec = g.compact ? 1 : 0;
     launch_y<double>(g, yb, s);
     X2Args x2{};
     x2.specB = c->specB;
@@ -867,6 +873,7 @@ void enqueue_hess(dft_ctx *c, const double *u, double *hu, const double *nstar, 
     x2.red = c->red;
     launch_x2<double>(g, x2, s);
     YArgs yc{c->specB, DFT_NALPHA, -1, nullptr};
+    yc.vec = g.compact ? 2 : 0;
     launch_y<double>(g, yc, s);
     Z2Args z2{};
     z2.specB = c->specB;

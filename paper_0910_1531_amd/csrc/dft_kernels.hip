@@ -837,6 +837,7 @@ void launch_y(const Geo &g, const YArgs &a, hipStream_t s) {
     const int L = zax ? g.nz : g.ny;
     if (L == 1) return;   // a length-1 transform is the identity
     if (launch_y_ct<T>(g, a, s)) return;
+    if (a.vec) throw std::runtime_error("y: compact vector layout without a compiled-length kernel");
     constexpr int E = Cfg<T>::YE;
     const int W = yz_width<T, E>(L, g.Kx);
     dim3 grid((unsigned)ceil_div(g.Kx, W), (unsigned)(zax ? g.ny : g.nz), (unsigned)(a.nfield * g.nprob));
@@ -848,6 +849,7 @@ void launch_y(const Geo &g, const YArgs &a, hipStream_t s) {
 template <typename T>
 void launch_z1(const Geo &g, const Z1Args &a, hipStream_t s) {
     if (launch_z1_ct<T>(g, a, g.es && !a.n3only, s)) return;
+    if (g.compact) throw std::runtime_error("z1: compact vector layout without a compiled-length kernel");
     constexpr int E = Cfg<T>::ZE;
     const int W = yz_width<T, E>(g.nz, g.Kx);
     dim3 grid((unsigned)ceil_div(g.Kx, W), (unsigned)g.ny, (unsigned)g.nprob);
@@ -862,6 +864,7 @@ void launch_z1(const Geo &g, const Z1Args &a, hipStream_t s) {
 template <typename T>
 void launch_z2(const Geo &g, const Z2Args &a, hipStream_t s) {
     if (launch_z2_ct<T>(g, a, s)) return;
+    if (g.compact) throw std::runtime_error("z2: compact vector layout without a compiled-length kernel");
     constexpr int E = Cfg<T>::ZE;
     const int W = yz_width<T, E>(g.nz, g.Kx);
     dim3 grid((unsigned)ceil_div(g.Kx, W), (unsigned)g.ny, (unsigned)g.nprob);
@@ -916,6 +919,7 @@ int x2_nblocks(const Geo &g) {
 template <typename T>
 void launch_x2(const Geo &g, const X2Args &a, hipStream_t s) {
     if (launch_x2_ct<T>(g, a, s)) return;
+    if (g.compact) throw std::runtime_error("x2: compact vector layout without a compiled-length kernel");
     const long long npairs = ((long long)g.ny * g.nz + 1) / 2;
     int ntb, pb;
     if (x2b_geometry<T>(g, &ntb, &pb)) {

@@ -41,8 +41,13 @@ void launch_pass(const Geo &g, const TuneBufs &b, int pass, hipStream_t s) {
     const bool fp32 = sizeof(T) == 4;
     switch (pass) {
         case TUNE_Y: {
-            YArgs a{b.specA, g.S, -1, nullptr};
+            // the y passes of the weighted densities and their derivatives, the largest ones
+            YArgs a{b.specB, DFT_NALPHA, 1, nullptr};
+            a.vec = g.compact ? 1 : 0;
             launch_y<T>(g, a, s);
+            YArgs c{b.specB, DFT_NALPHA, -1, nullptr};
+            c.vec = g.compact ? 2 : 0;
+            launch_y<T>(g, c, s);
             break;
         }
         case TUNE_YZ: {
