@@ -30,12 +30,13 @@ METRIC = "Picard iters/s at 256³ 2-ion FMT+ES, FP32-mixed vs FP64 at 1e-8 resid
 HBM_PEAK_GBS = 8000.0
 
 
-def pass_bytes(prob, fp32):
+def pass_bytes(prob, fp32, compact):
     """Algorithmic HBM bytes of each pass of one plain residual evaluation.
 
     Every logical array is counted once per pass in which it is read or written:
     real fields of N float64 values, half spectra of N_c = nz ny (nx/2+1) complex values
-    in the transform precision.
+    in the transform precision.  compact: the ten weighted densities leave the z pass as 7
+    spectra and their derivatives reach it as 8 (the context's compact_layout).
     """
     nx, ny, nz = prob.n
     S = prob.nspecies
@@ -45,14 +46,15 @@ def pass_bytes(prob, fp32):
     C = NC * (8 if fp32 else 16)      # one half spectrum
     ref = S * R if fp32 else 0        # FP32-mixed: reference density read in x_fwd
     nref = 10 * 4 * N if fp32 else 0  # FP32-mixed: reference weighted densities read in x_fmt
+    zin, zout = (7, 8) if compact else (10, 10)
     return {
         "x_fwd": S * R + ref + S * C,
         "y_fwd": 2 * S * C,
-        "z_weights": S * C + (S + 10) * C,
-        "y_inv": 20 * C,
+        "z_weights": S * C + (S + zin) * C,
+        "y_inv": (zin + 10) * C,
         "x_fmt": 20 * C + nref,
-        "y_fwd2": 20 * C,
-        "z_back_es": (10 + S) * C + S * C,
+        "y_fwd2": (10 + zout) * C,
+        "z_back_es": (zout + S) * C + S * C,
         "y_inv2": 2 * S * C,
         "x_el": S * C + 3 * S * R,
         "reduce": 0,
@@ -93,6 +95,7 @@ def gpu_leg(prob, precision, steps, warmup, solve_tol, profile_reps):
     out["its"] = steps / (t1 - t0)
     out["profile_ms"] = sol.profile(x, reps=profile_reps)
     out["schedule"] = sol.schedule()
+    out["compact"] = bool(sol.stats()["compact_layout"])
     sol.close()
     return out
 
@@ -391,7 +394,7 @@ def main():
             sol = sv.from_problem(prob, precision=prec)
             rho = torch.tensor(prob.initial_density(), dtype=torch.float64, device="cuda")
             prof = sol.profile(rho, reps=args.profile_reps)
-            pb = pass_bytes(prob, name == "mixed")
+            pb = pass_bytes(prob, name == "mixed", bool(sol.stats()["compact_layout"]))
             out[name] = {k: {"ms": round(v, 4), "GBs": round(pb[k] / (v * 1e-3) / 1e9, 1) if v > 0 else None}
                          for k, v in prof.items()}
             sol.close()
@@ -406,7 +409,7 @@ def main():
 
     # roofline of the dominant pass of the headline precision
     prof = head["profile_ms"]
-    pb = pass_bytes(prob, fp32)
+    pb = pass_bytes(prob, fp32, head["compact"])
     dom = max((k for k in prof if k != "reduce"), key=lambda k: prof[k])
     achieved = pb[dom] / (prof[dom] * 1e-3) / 1e9
     passes = {k: {"ms": round(prof[k], 4), "GB": round(pb[k] / 1e9, 4),

@@ -45,7 +45,8 @@ class BulkInfo(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int64), ("rejected", ctypes.c_int64), ("g_evals", ctypes.c_int64),
                 ("n3_evals", ctypes.c_int64), ("fp64_refresh", ctypes.c_int64), ("residual", ctypes.c_double),
-                ("alpha", ctypes.c_double), ("max_n3", ctypes.c_double), ("step_cap", ctypes.c_double)]
+                ("alpha", ctypes.c_double), ("max_n3", ctypes.c_double), ("step_cap", ctypes.c_double),
+                ("compact_layout", ctypes.c_int32)]
 
 
 class DftError(RuntimeError):

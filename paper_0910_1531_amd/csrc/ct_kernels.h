@@ -289,14 +289,23 @@ __global__ __launch_bounds__(NTB) void k_z1c(Geo g_in, Z1Args a) {
     int ph = 0;
     typename F::template TwReg<-1> trs;   // forward twiddles, shared by the species transforms
     F::template load_tw<-1>(trs, tw);
-    for (int jsp = 0; jsp < S; ++jsp) {
+    // each species' inputs are fetched while the previous species transforms
+    constexpr int NIN = F::template nin<-1>();
+    cx<T> vin[NIN];
+    auto load_species = [&](int jsp) {
         const cx<T> *src = reinterpret_cast<const cx<T> *>(a.specA) + (long long)jsp * NC + off;
 #pragma unroll
-        for (int i = 0; i < F::template nin<-1>(); ++i) {
+        for (int i = 0; i < NIN; ++i) {
             int p, e;
             const bool ok = F::template in_pos<-1>(i, p, e);
-            v[i] = (ok && p < Pact) ? ct::gld(src + e * rs + p) : mk<T>(T(0), T(0));
+            vin[i] = (ok && p < Pact) ? ct::gld(src + e * rs + p) : mk<T>(T(0), T(0));
         }
+    };
+    load_species(0);
+    for (int jsp = 0; jsp < S; ++jsp) {
+#pragma unroll
+        for (int i = 0; i < NIN; ++i) v[i] = vin[i];
+        if (jsp + 1 < S) load_species(jsp + 1);
         // FP64: this species' table values, fetched before the transform hides their latency
         constexpr int NOT = TAB ? NO : 1;
         T w2r[NOT], w3r[NOT], kr[ME][NOT];
@@ -569,11 +578,37 @@ __global__ __launch_bounds__(NTB) void k_z2c(Geo g_in, Z2Args a) {
     // each vector sum, i k_x dPhi_x + i k_y dPhi_y, are combined before one transform; the z parts
     // are transformed and multiplied by i k_z after.  Transform t: 0..3 the scalars (u0..u3);
     // 4, 6 the combined x, y parts of V1, V2; 5, 7 their z parts.
+    // compact layout: slots 4 and 7 already hold i k_x dPhi_x + i k_y dPhi_y and all eight inputs
+    // are plain spectra; in FP32 each is fetched while the previous one transforms (FP64 has no
+    // registers to spare for it)
+    constexpr bool PF = std::is_same<T, float>::value;
+    constexpr int NIN = F::template nin<-1>();
+    cx<T> vin[NIN];
+    auto slot_of = [](int t) { return t < 4 ? t : (t == 4 ? 4 : (t == 5 ? 6 : (t == 6 ? 7 : 9))); };
+    auto fetch = [&](int t) {
+        const int al = slot_of(t);
+        const cx<T> *src = reinterpret_cast<const cx<T> *>(a.specB) + (long long)al * NC + off;
+#pragma unroll
+        for (int i = 0; i < NIN; ++i) {
+            int p, e;
+            const bool ok = F::template in_pos<-1>(i, p, e);
+            vin[i] = (ok && p < Pact) ? ct::gld(src + e * rs + p) : mk<T>(T(0), T(0));
+        }
+    };
+    if (PF && g.compact) fetch(0);
     for (int t = 0; t < 8; ++t) {
         const int m = t < 4 ? t : (t < 6 ? 4 : 5);
-        if (t < 4 || t == 5 || t == 7 || g.compact) {
-            // compact layout: slots 4 and 7 already hold i k_x dPhi_x + i k_y dPhi_y
-            const int al = t < 4 ? t : (t == 4 ? 4 : (t == 5 ? 6 : (t == 6 ? 7 : 9)));
+        if (g.compact) {
+            if constexpr (PF) {
+#pragma unroll
+                for (int i = 0; i < NIN; ++i) v[i] = vin[i];
+                if (t + 1 < 8) fetch(t + 1);
+                fwd();
+            } else {
+                load_fwd(reinterpret_cast<const cx<T> *>(a.specB) + (long long)slot_of(t) * NC + off);
+            }
+        } else if (t < 4 || t == 5 || t == 7) {
+            const int al = t < 4 ? t : (t == 5 ? 6 : 9);
             load_fwd(reinterpret_cast<const cx<T> *>(a.specB) + (long long)al * NC + off);
         } else {
             const int al = t == 4 ? 4 : 7;
@@ -612,9 +647,22 @@ __global__ __launch_bounds__(NTB) void k_z2c(Geo g_in, Z2Args a) {
 #pragma unroll
         for (int i = 0; i < NO; ++i) kmag[i] = kw.kmag(pp[i], ee[i]);
     }
+    // FP32: the electrostatic spectra of species is + 1 fetched while species is transforms
+    // (slot is + 1 is written only in the next iteration, after every read of it)
+    cx<T> evn[NO];
+    auto fetch_es = [&](int is) {
+        const cx<T> *esrc = reinterpret_cast<const cx<T> *>(a.specA) + (long long)is * NC + off;
+#pragma unroll
+        for (int i = 0; i < NO; ++i) evn[i] = (c.es && okk[i]) ? ct::gld(esrc + ti[i]) : mk<T>(T(0), T(0));
+    };
+    if constexpr (PF) fetch_es(0);
     for (int is = 0; is < S; ++is) {
         const T Ri = T(c.R[is]), a0 = T(c.i4piR2[is]), a1 = T(c.i4piR[is]);
-        const cx<T> *esrc = reinterpret_cast<const cx<T> *>(a.specA) + (long long)is * NC + off;
+        if constexpr (!PF) fetch_es(is);
+        cx<T> ev[NO];
+#pragma unroll
+        for (int i = 0; i < NO; ++i) ev[i] = evn[i];
+        if (PF && is + 1 < S) fetch_es(is + 1);
 #pragma unroll
         for (int i = 0; i < NO; ++i) {
             T w2, w3;
@@ -631,11 +679,8 @@ __global__ __launch_bounds__(NTB) void k_z2c(Geo g_in, Z2Args a) {
             const T s3y = u[3][i].y + u[4][i].y * a1 + u[5][i].y;
             T ex = -(s2x * w2 + s3x * w3);
             T ey = -(s2y * w2 + s3y * w3);
-            if (c.es && okk[i]) {
-                const cx<T> ev = ct::gld(esrc + ti[i]);
-                ex += ev.x;
-                ey += ev.y;
-            }
+            ex += ev[i].x;
+            ey += ev[i].y;
             v[i] = mk<T>(ex * invN, ey * invN);
         }
         inv_store(reinterpret_cast<cx<T> *>(a.specA) + (long long)is * NC + off);

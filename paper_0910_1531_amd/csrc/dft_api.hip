@@ -1511,6 +1511,7 @@ dft_status dft_get_stats(dft_ctx *ctx, dft_stats *out) {
         out->alpha = h.alpha_acc;
         out->max_n3 = h.m0;
         out->step_cap = h.cap;
+        out->compact_layout = ctx->geo.compact;
         return DFT_OK;
     });
 }

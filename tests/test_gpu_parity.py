@@ -211,3 +211,18 @@ def test_lambda_cutoff_matches_oracle(n):
     assert eE < 1e-12 and eG < 1e-12
     assert r == pytest.approx(st.residual_norm(st.sqnorm(rho - ref["G"])), rel=1e-12)
     assert em < 1e-6
+
+
+@pytest.mark.parametrize("n,lam,want", [((32, 32, 32), False, 1), ((96, 64, 48), False, 1), ((12, 6, 9), False, 0),
+                                        ((256, 6, 3), False, 0), ((32, 32, 32), True, 0)])
+def test_vector_layout_choice(n, lam, want):
+    # The compact layout of the vector densities (7 spectra out of the weight pass, 8 into the
+    # back-convolution) needs compiled-length kernels on every axis and is not used with the
+    # lambda cutoff under electrostatics; the operator tests above run both layouts.
+    from paper_0910_1531_amd import _abi
+    from paper_0910_1531_amd.solver import from_problem
+    p = mixture(n, S=2, es=True)
+    for precision in (_abi.DFT_FP64, _abi.DFT_FP32_MIXED):
+        sol = from_problem(p, precision=precision, flags=_abi.FLAG_CUTOFF_LAMBDA if lam else 0)
+        assert sol.stats()["compact_layout"] == want
+        sol.close()
