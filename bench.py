@@ -36,7 +36,8 @@ def pass_bytes(prob, fp32, compact):
     Every logical array is counted once per pass in which it is read or written:
     real fields of N float64 values, half spectra of N_c = nz ny (nx/2+1) complex values
     in the transform precision.  compact: the ten weighted densities leave the z pass as 7
-    spectra and their derivatives reach it as 8 (the context's compact_layout).
+    spectra and reach the x pass as 9, and their derivatives reach the z pass as 8 (the
+    context's compact_layout).
     """
     nx, ny, nz = prob.n
     S = prob.nspecies
@@ -46,13 +47,13 @@ def pass_bytes(prob, fp32, compact):
     C = NC * (8 if fp32 else 16)      # one half spectrum
     ref = S * R if fp32 else 0        # FP32-mixed: reference density read in x_fwd
     nref = 10 * 4 * N if fp32 else 0  # FP32-mixed: reference weighted densities read in x_fmt
-    zin, zout = (7, 8) if compact else (10, 10)
+    zin, xin, zout = (7, 9, 8) if compact else (10, 10, 10)
     return {
         "x_fwd": S * R + ref + S * C,
         "y_fwd": 2 * S * C,
         "z_weights": S * C + (S + zin) * C,
-        "y_inv": (zin + 10) * C,
-        "x_fmt": 20 * C + nref,
+        "y_inv": (zin + xin) * C,
+        "x_fmt": (xin + 10) * C + nref,
         "y_fwd2": (10 + zout) * C,
         "z_back_es": (zout + S) * C + S * C,
         "y_inv2": 2 * S * C,

@@ -133,11 +133,12 @@ typedef struct dft_stats {
     double alpha;            /* last accepted step */
     double max_n3;           /* max n3 at the current iterate */
     double step_cap;         /* current line-search step cap */
-    int32_t compact_layout;  /* 1: the vector weighted densities and their derivatives pass
-                                between the z and y transforms as 7 and 8 half spectra (their
-                                x and y components are -i k_x, -i k_y times one field along a
-                                z pencil), 0: as 10; fixed at setup (every pass on a
-                                compiled-length kernel) */
+    int32_t compact_layout;  /* 1: the weighted densities pass from the z to the y transform
+                                as 7 half spectra and from the y to the x transform as 9, and
+                                their derivatives from the y to the z transform as 8 (the x
+                                and y components of a vector density are -i k_x, -i k_y times
+                                one field along a z pencil); 0: as 10 each; fixed at setup
+                                (every pass on a compiled-length kernel) */
 } dft_stats;
 
 /* Message for the last non-OK status returned on this thread ("" if none). */

@@ -98,8 +98,9 @@ __global__ __launch_bounds__(NTB) void k_yc(Geo g_in, YArgs a) {
             F::template run<DIR>(v, lds, ph, tw);
             store(f, v, false);
         } else if constexpr (VEC == 1) {
-            // inverse: slots 0-3 (n0..n3), 4 (nV1 sum), 6, 9 (z components) -> the ten fields;
-            // n3 also gives nV2_x = -i k_x n3 and nV2_y, the nV1 sum gives nV1_x and nV1_y
+            // inverse: slots 0-3 (n0..n3), 4 (nV1 sum), 6, 9 (z components) -> nine fields:
+            // n3 also gives nV2_y = -i k_y n3, the nV1 sum gives nV1_x and nV1_y (slot 7,
+            // nV2_x, is left to the x pass)
             const int slot = f < 5 ? f : (f == 5 ? 6 : 9);
             load(slot, v);
             if (slot == 3 || slot == 4) {
@@ -112,12 +113,7 @@ __global__ __launch_bounds__(NTB) void k_yc(Geo g_in, YArgs a) {
                     w[i] = mk<T>(k * v[i].y, -k * v[i].x);   // -i k_y
                 }
                 F::template run<DIR>(v, lds, ph, tw);
-                if (slot == 3) {
-                    store(3, v, false);
-                    store(7, v, true);
-                } else {
-                    store(4, v, true);
-                }
+                store(slot, v, slot == 4);   // (n_V2,x = -i k_x n3 is formed by the x pass)
                 F::template run<DIR>(w, lds, ph, tw);
                 store(slot == 3 ? 8 : 5, w, false);
             } else {
@@ -800,6 +796,18 @@ __global__ __launch_bounds__(XTile<L>::NTB) void k_x2c(Geo g_in, X2Args a) {
 #pragma unroll
     for (int f = 0; f < DFT_NALPHA; ++f) {
         if (f >= nf) continue;
+        if (f == 7 && g.compact) {
+            // compact layout: n_V2,x = -i k_x n3 (k_x zero on the Nyquist column), formed here
+            const T dkx = T(g.cs->dk[0]);
+#pragma unroll
+            for (int i = 0; i < NO; ++i) {
+                int p, e;
+                F::template in_pos<1>(i, p, e);
+                const T kx = (L % 2 == 0 && 2 * e == L) ? T(0) : T(e <= L / 2 ? e : e - L) * dkx;
+                vals[7][i] = mk<T>(kx * vals[3][i].y, -kx * vals[3][i].x);
+            }
+            continue;
+        }
         const cx<T> *in = reinterpret_cast<const cx<T> *>(a.specB) + (long long)f * NC;
 #pragma unroll
         for (int i = 0; i < NO; ++i) {

@@ -36,9 +36,10 @@ struct Geo {
     int cut_lambda;        // screening cutoff at lambda_i + lambda_j (mirrors Consts::cut_lambda)
     // Compact vector layout between the z and y passes (every pass on compiled-length kernels):
     // the x and y components of a vector density differ from one field by -i k_x and -i k_y, so
-    // Z1 writes n0..n3, the nV1 sum and the two z components (slots 0-4, 6, 9) and the inverse
-    // y pass expands them to the ten fields; X2 multiplies the x components of the derivatives by
-    // i k_x, the forward y pass folds the y components in (slots 0-4, 6, 7, 9) and Z2 reads those.
+    // Z1 writes n0..n3, the nV1 sum and the two z components (slots 0-4, 6, 9), the inverse y
+    // pass expands them to nine fields (all but nV2_x) and X2 forms nV2_x = -i k_x n3 itself; X2
+    // multiplies the x components of the derivatives by i k_x, the forward y pass folds the y
+    // components in (slots 0-4, 6, 7, 9) and Z2 reads those.
     int compact = 0;
     long long N, NC;
     // Batches of identically shaped problems: the kernels of one launch cover nprob
@@ -90,7 +91,7 @@ struct YArgs {
     int dir;
     const int *gate;
     int axis = 1;       // 1: y, 2: z (plain transform along z)
-    int vec = 0;        // compact vector layout of specB (Geo::compact): 1 inverse (7 -> 10 fields),
+    int vec = 0;        // compact vector layout of specB (Geo::compact): 1 inverse (7 -> 9 fields),
                         // 2 forward (10 -> 8 fields); 0 plain
 };
 
