@@ -33,6 +33,9 @@ inline long long ct_cdiv(long long a, long long b) { return (a + b - 1) / b; }
 // ------------------------------------------------------------------ y / z plain transforms
 // One block transforms P adjacent columns (kx) of one field along y (one z plane) or z
 // (one y line); the pencils' elements sit rs apart in HBM and P columns are contiguous.
+// VEC = 1, 2: the y passes of the compact vector layout (Geo::compact), where a block of the
+// n3 or nV1-sum slot makes two transforms (inverse: the field and -i k_y times it) and a block
+// of a vector-derivative slot adds i k_y times the transform of the y component (forward).
 template <typename T, int L, int P, int NTB, int NB, int VEC>
 __global__ __launch_bounds__(NTB) void k_yc(Geo g_in, YArgs a) {
     using F = ct::Fft<T, typename ct::Plan<L>::type, P, NTB, false, NB>;
@@ -713,6 +716,84 @@ __device__ __forceinline__ cx<T> half_at(const cx<T> *row, int e) {
     return v;
 }
 
+// Value v of lane src of the wave (cross-lane permute, 32 bits at a time; no memory access).
+template <typename T>
+__device__ __forceinline__ cx<T> lane_value(cx<T> v, int src) {
+    constexpr int W = (int)(sizeof(cx<T>) / 4);
+    int w[W];
+    __builtin_memcpy(w, &v, sizeof(v));
+#pragma unroll
+    for (int k = 0; k < W; ++k) w[k] = __builtin_amdgcn_ds_bpermute(src << 2, w[k]);
+    cx<T> r;
+    __builtin_memcpy(&r, w, sizeof(r));
+    return r;
+}
+
+// Inputs of an inverse x transform: for the row pair of register i, C_e = A_e + i B_e from the
+// half spectra of rows r0 and r0 + 1 (B = 0 past the last row; pairs past Pact read as zero).
+// In a wave-private tile lane b of a pencil holds e = b + q L/4 (q = 0..3); the elements
+// e > L/2 are conj(A_{L-e}), and L - e is an element that lane (L/4 - b) mod L/4 of the same
+// pencil loads for q = 0 or 1, so they come by cross-lane permutes instead of second loads.
+template <typename T, int L, class F>
+__device__ __forceinline__ void load_row_pairs(const cx<T> *in, long long pair0, int Pact, long long rows, cx<T> *c) {
+    constexpr int KX = L / 2 + 1;
+    if constexpr (F::WP) {
+        constexpr int Q = L / 4;
+        static_assert(F::template nin<1>() == 4, "one radix-4 butterfly per thread");
+        int p, b;
+        F::template in_pos<1>(0, p, b);
+        const bool ok = p < Pact;
+        const long long r0 = 2 * (pair0 + p);
+        const bool okb = ok && r0 + 1 < rows;
+        const cx<T> *ra = in + r0 * KX, *rb = ra + KX;
+        const cx<T> z = mk<T>(T(0), T(0));
+        cx<T> A0 = z, A1 = z, An = z, B0 = z, B1 = z, Bn = z;
+        if (ok) {
+            A0 = ct::gld(ra + b);
+            A1 = ct::gld(ra + Q + b);
+            if (b == 0) {
+                A0.y = T(0);
+                An = ct::gld(ra + 2 * Q);   // the Nyquist element
+                An.y = T(0);
+            }
+        }
+        if (okb) {
+            B0 = ct::gld(rb + b);
+            B1 = ct::gld(rb + Q + b);
+            if (b == 0) {
+                B0.y = T(0);
+                Bn = ct::gld(rb + 2 * Q);
+                Bn.y = T(0);
+            }
+        }
+        const int lane = (int)(threadIdx.x & 63);
+        const int src = lane - b + ((Q - b) & (Q - 1));
+        const cx<T> a1 = lane_value(A1, src), a0 = lane_value(A0, src);
+        const cx<T> b1 = lane_value(B1, src), b0 = lane_value(B0, src);
+        const cx<T> A2 = b == 0 ? An : conjg(a1), A3 = b == 0 ? conjg(a1) : conjg(a0);
+        const cx<T> B2 = b == 0 ? Bn : conjg(b1), B3 = b == 0 ? conjg(b1) : conjg(b0);
+        c[0] = mk<T>(A0.x - B0.y, A0.y + B0.x);
+        c[1] = mk<T>(A1.x - B1.y, A1.y + B1.x);
+        c[2] = mk<T>(A2.x - B2.y, A2.y + B2.x);
+        c[3] = mk<T>(A3.x - B3.y, A3.y + B3.x);
+    } else {
+#pragma unroll
+        for (int i = 0; i < F::template nin<1>(); ++i) {
+            int p, e;
+            const bool ok = F::template in_pos<1>(i, p, e) && p < Pact;
+            cx<T> cv = mk<T>(T(0), T(0));
+            if (ok) {
+                const long long r0 = 2 * (pair0 + p);
+                const cx<T> A = half_at<T, L>(in + r0 * KX, e);
+                cx<T> B = mk<T>(T(0), T(0));
+                if (r0 + 1 < rows) B = half_at<T, L>(in + (r0 + 1) * KX, e);
+                cv = mk<T>(A.x - B.y, A.y + B.x);
+            }
+            c[i] = cv;
+        }
+    }
+}
+
 // Half spectra of the two real rows of every row pair from the forward transform of the pair
 // (C held in split): A_k = (C_k + conj C_{L-k}) / 2, B_k = (C_k - conj C_{L-k}) / (2i).  In a
 // wave-private tile each wave splits its own pencils (lanes along k); otherwise the block does
@@ -808,21 +889,8 @@ __global__ __launch_bounds__(XTile<L>::NTB) void k_x2c(Geo g_in, X2Args a) {
             }
             continue;
         }
-        const cx<T> *in = reinterpret_cast<const cx<T> *>(a.specB) + (long long)f * NC;
-#pragma unroll
-        for (int i = 0; i < NO; ++i) {
-            int p, e;
-            const bool ok = F::template in_pos<1>(i, p, e) && p < Pact;
-            cx<T> c = mk<T>(T(0), T(0));
-            if (ok) {
-                const long long r0 = 2 * (pair0 + p);
-                const cx<T> A = half_at<T, L>(in + r0 * KX, e);
-                cx<T> B = mk<T>(T(0), T(0));
-                if (r0 + 1 < rows) B = half_at<T, L>(in + (r0 + 1) * KX, e);
-                c = mk<T>(A.x - B.y, A.y + B.x);
-            }
-            vals[f][i] = c;
-        }
+        load_row_pairs<T, L, F>(reinterpret_cast<const cx<T> *>(a.specB) + (long long)f * NC, pair0, Pact, rows,
+                                vals[f]);
     }
     // D32: the reference weighted densities of a register's two nodes, fetched one register
     // ahead of the nodewise work (the first before the transforms) so their latency is hidden
@@ -1019,20 +1087,7 @@ __global__ __launch_bounds__(XTile<L>::NTB) void k_x3c(Geo g_in, X3Args a) {
     const int Pact = (int)min((long long)PB, npairs - pair0);
     const cx<T> *in = reinterpret_cast<const cx<T> *>(a.specA) + (long long)sp * g.NC;
     cx<T> v[F::V];
-#pragma unroll
-    for (int i = 0; i < F::template nin<1>(); ++i) {
-        int p, e;
-        const bool ok = F::template in_pos<1>(i, p, e) && p < Pact;
-        cx<T> cv = mk<T>(T(0), T(0));
-        if (ok) {
-            const long long r0 = 2 * (pair0 + p);
-            const cx<T> A = half_at<T, L>(in + r0 * KX, e);
-            cx<T> B = mk<T>(T(0), T(0));
-            if (r0 + 1 < rows) B = half_at<T, L>(in + (r0 + 1) * KX, e);
-            cv = mk<T>(A.x - B.y, A.y + B.x);
-        }
-        v[i] = cv;
-    }
+    load_row_pairs<T, L, F>(in, pair0, Pact, rows, v);
     int ph = 0;
     if constexpr (F::WP) F::template run<1>(v, lds, ph, trw);
     else F::template run<1>(v, lds, ph, twp<T>(g, 0));
