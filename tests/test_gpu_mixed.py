@@ -120,3 +120,29 @@ def test_run_equals_repeated_steps():
     for _ in range(3):
         a.picard_step(xa)
     assert torch.equal(xa, xb) and r2 < r
+
+
+@pytest.mark.parametrize("n", [(64, 3, 3), (32, 1, 9), (12, 3, 9), (256, 1, 3)])
+def test_mixed_residual_with_an_odd_row_count(n):
+    # An odd number of x rows (n_y n_z) leaves the last row pair of the x passes half empty.
+    # Wave-private (64, 256), other compiled (32) and run-time (12) x lengths, and grids with
+    # n_y = 1: the FP32-mixed residual near its reference against the FP64 one (1e-6), and the
+    # FP64 one against the oracle (1e-11 of the maximum: the perturbation below is rough at the
+    # grid scale; a wrong half-empty pair would be off by far more).
+    from test_gpu_parity import mixture
+    p = mixture(n, S=2, es=True)
+    rho = W.random_density(p, seed=11, amplitude=0.3)
+    st = residual.Setup(p)
+    d = _solver(p, _abi.DFT_FP64)
+    m = _solver(p, _abi.DFT_FP32_MIXED)
+    x = _dev(rho)
+    m.set_reference(x)
+    x2 = x * (1 + 0.05 * torch.sin(torch.arange(x.numel(), device="cuda", dtype=torch.float64)).reshape(x.shape))
+    Gm, rm = m.residual(x2)
+    Gd, rd = d.residual(x2)
+    ref = st.evaluate(x2.cpu().numpy())
+    em = _rel(Gm.cpu().numpy(), Gd.cpu().numpy())
+    ed = _rel(Gd.cpu().numpy(), ref["G"])
+    _say(f"odd rows n={n}: FP32-mixed vs FP64 {em:.1e}, FP64 vs oracle {ed:.1e}")
+    assert ed < 1e-11
+    assert em < 1e-6
