@@ -803,26 +803,41 @@ template <typename T, int L, class F>
 __device__ __forceinline__ void split_rows(const cx<T> *split, cx<T> *out, long long pair0, int Pact, long long rows,
                                            T dkx = T(0)) {
     constexpr int KX = L / 2 + 1;
-    auto one = [&](int p, int k) {
+    auto coeffs = [&](int p, int k, cx<T> &A, cx<T> &B) {
         const cx<T> ck = split[F::lidx(p, k)];
         const cx<T> cm = split[F::lidx(p, k == 0 ? 0 : L - k)];
-        const long long r0 = 2 * (pair0 + p);
-        cx<T> A = mk<T>(T(0.5) * (ck.x + cm.x), T(0.5) * (ck.y - cm.y));
-        cx<T> B = mk<T>(T(0.5) * (ck.y + cm.y), T(-0.5) * (ck.x - cm.x));
+        A = mk<T>(T(0.5) * (ck.x + cm.x), T(0.5) * (ck.y - cm.y));
+        B = mk<T>(T(0.5) * (ck.y + cm.y), T(-0.5) * (ck.x - cm.x));
         if (dkx > T(0)) {
             const T kx = (L % 2 == 0 && 2 * k == L) ? T(0) : T(k) * dkx;
             A = mk<T>(-kx * A.y, kx * A.x);
             B = mk<T>(-kx * B.y, kx * B.x);
         }
+    };
+    auto one = [&](int p, int k) {
+        cx<T> A, B;
+        coeffs(p, k, A, B);
+        const long long r0 = 2 * (pair0 + p);
         ct::gst(out + r0 * KX + k, A);
         if (r0 + 1 < rows) ct::gst(out + (r0 + 1) * KX + k, B);
     };
     if constexpr (F::WP) {
+        // lane b of a pencil writes k = b and b + L/4 of both rows; the Nyquist element k = L/2
+        // goes to row r0 from lane 0 and to row r0 + 1 from lane 1 (one store instead of two)
         constexpr int nb = L / 4;
         const int lane = (int)threadIdx.x % 64;
         const int p = ((int)threadIdx.x / 64) * (64 / nb) + lane / nb;
-        if (p < Pact)
-            for (int k = lane % nb; k < KX; k += nb) one(p, k);
+        const int b = lane % nb;
+        if (p < Pact) {
+            one(p, b);
+            one(p, b + nb);
+            if (b < 2) {
+                cx<T> A, B;
+                coeffs(p, 2 * nb, A, B);
+                const long long r = 2 * (pair0 + p) + b;
+                if (r < rows) ct::gst(out + r * KX + 2 * nb, b == 0 ? A : B);
+            }
+        }
     } else {
         for (int j = threadIdx.x; j < Pact * KX; j += (int)blockDim.x) {
             const int p = j / KX;
