@@ -136,3 +136,30 @@ def test_poisson_denominator_is_the_7_point_stencil_symbol():
         for ax, hd in ((2, h[0]), (1, h[1]), (0, h[2])):
             lap = lap + (np.roll(f, 1, ax) + np.roll(f, -1, ax) - 2 * f) / hd ** 2
         assert np.allclose(-lap, D[jz, jy, jx] * f, atol=1e-9 * abs(D[jz, jy, jx]) + 1e-9)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_screening_bracket_double_zero_at_lambda_sum(seed):
+    # The bulk-fluid kernel of eq. (CplusPsiFunc) must end smoothly where the MSA pair function
+    # c^(2) + beta psi ends, at r = lambda_i + lambda_j: value and slope vanish there.  r times
+    # the bracket is a quadratic in r (its linear, constant and 1/r coefficients become the
+    # r^2, r and constant ones), so a degree-4 fit through five samples of the oracle's kernel
+    # recovers it exactly; a dropped term or a wrong sign in any coefficient moves the double
+    # root.  Together with the Coulomb limit at equal lambdas this fixes all three coefficients.
+    rng = np.random.default_rng(seed)
+    lam_i, lam_j = rng.uniform(0.2, 1.5, 2)
+    lB, zi, zj = 0.714871584, float(rng.choice([1.0, 2.0])), -1.0
+    L = lam_i + lam_j
+    pref = 0.5 * zi * zj * lB
+    r = np.linspace(0.3 * L, 1.7 * L, 5)
+    g = r * spectra.screening_kernel_real(r, zi, zj, lam_i, lam_j, 10.0 * L, lB) / pref
+    c = np.polynomial.polynomial.polyfit(r / L, g, 4)      # powers of r / L
+    scale = np.max(np.abs(g))
+    assert abs(c[3]) < 1e-12 * scale and abs(c[4]) < 1e-12 * scale
+    poly = np.polynomial.Polynomial(c)
+    assert abs(poly(1.0)) < 1e-13 * scale                # bracket zero at r = lambda_i + lambda_j
+    assert abs(poly.deriv()(1.0)) < 1e-13 * scale        # and its r-derivative
+    # past the double root the bracket stays of one sign (a minimum of |bracket|, not a crossing)
+    rr = np.linspace(0.5 * L, 1.5 * L, 101)
+    b = spectra.screening_kernel_real(rr, zi, zj, lam_i, lam_j, 10.0 * L, lB) / pref
+    assert np.all(b >= -1e-14 * np.max(np.abs(b)))
