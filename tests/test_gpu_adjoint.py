@@ -212,3 +212,38 @@ def test_adjoint_and_newton_on_a_mixed_precision_context():
     err = float(np.max(np.abs(x.cpu().numpy() - rho)) / np.max(np.abs(rho)))
     _say(f"  Newton on the mixed context: {it} steps, r {r:.1e}, rho rel diff {err:.1e}")
     assert status == 0 and r <= 1e-11 and err < 1e-9
+
+
+@pytest.mark.parametrize("precision", [_abi.DFT_FP64, _abi.DFT_FP32_MIXED])
+def test_pore192_adjoint_matches_oracle_gradient(precision):
+    """The 192^3 differentiation workload against the FP64 oracle's own implicit-adjoint gradient
+    at its own converged density (tests/golden/oracle_gradient_pore192.json, written by
+    tests/golden/make_oracle_solutions.py): dO/d(beta V_k) at the 32 seeded voxels of every
+    species, dO/d sigma_k and dO/d rho_bulk_k.  Forward solves in FP64 (to 1e-13) and FP32-mixed
+    (to 1e-10); the adjoint evaluates in FP64 either way."""
+    import json
+    import os
+    ref = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "oracle_gradient_pore192.json")))
+    p = W.config_pore(n=192, tol=1e-10)
+    assert list(p.n) == ref["grid"]
+    vox = W.adjoint_voxels(p, count=32, seed=5)
+    assert [int(v) for v in vox] == ref["voxels"]
+    mask = W.pore_observable_mask(p)
+    h3 = float(np.prod(p.h))
+    sol = _solver(p, precision=precision)
+    x = _dev(p.initial_density())
+    tol = 1e-13 if precision == _abi.DFT_FP64 else 1e-10
+    it, r, stt = sol.solve(x, tol, 2000)
+    assert stt == 0 and r <= tol
+    mask_t = torch.from_numpy(mask).to("cuda")
+    O = float(x[0][mask_t].sum().item()) * h3
+    g = torch.zeros_like(x)
+    g[0][mask_t] = h3
+    out = sol.adjoint(x, g, tol=1e-12)
+    _say(f"pore192 precision {precision}: forward {it} iterations (oracle {ref['iterations']}), "
+         f"O = {O:.12e} (oracle {ref['observable_value']:.12e}); adjoint CG {out['iters']}")
+    assert O == pytest.approx(ref["observable_value"], rel=1e-9 if precision == _abi.DFT_FP64 else 1e-6)
+    gv = out["vext"].cpu().numpy().reshape(p.nspecies, -1)[:, vox]
+    _check("dO/dbetaV (96 voxel entries)", gv, ref["dO_dbetaV"])
+    _check("dO/dsigma", out["sigma"], ref["dO_dsigma"])
+    _check("dO/drho_b", out["rho_bulk"], ref["dO_drho_bulk"])

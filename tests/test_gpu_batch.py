@@ -56,6 +56,18 @@ def test_batched_electrolyte_workload_fp32_mixed():
     _say(f"  solved in {dt:.2f} s; iterations min/median/max {min(its)}/{int(np.median(its))}/{max(its)}")
     assert all(s == 0 for s in sts), sts
     assert max(norms) <= 1e-8
+    # one point of each grid size against the FP64 oracle's converged densities (sampled; written
+    # by tests/golden/make_oracle_solutions.py)
+    from test_gpu_fullsize import golden
+    for N in (64, 96, 128):
+        meta, idx, want = golden(f"batch{N}")
+        i = [p.name for p in pts].index(meta["problem"])
+        assert list(pts[i].n) == meta["grid"]
+        got = rhos[i].cpu().numpy().ravel()[idx]
+        err = float(np.max(np.abs(got - want)) / np.max(np.abs(want)))
+        _say(f"  point {i} ({N}^3): {its[i]} iterations (oracle {meta['iterations']} to 1e-12), "
+             f"rho vs oracle {err:.2e}")
+        assert err < 1e-5
 
 
 def test_batch_groups_split_by_functional():

@@ -107,3 +107,51 @@ def test_e1_contact_error_is_first_order_and_extrapolates(functional):
     assert errs[0] / errs[1] == pytest.approx(2.0, rel=0.03)
     assert errs[1] / errs[2] == pytest.approx(2.0, rel=0.03)
     assert abs(2 * errs[2] - errs[1]) < 5e-4
+
+
+@pytest.mark.parametrize("eta", [0.2, 0.3])
+def test_e1_wall_fp32_mixed_matches_1d_oracle(eta):
+    # Dense hard spheres in FP32-mixed: the nodewise FMT derivatives are formed in FP32 as
+    # differences from the FP64 reference state, and the factors 1 / (1 - n3)^k grow near the
+    # wall.  The solve must still reach 1e-10 (confirmed by an FP64 evaluation) and the
+    # densities equal the 1-D FP64 oracle's within the 1e-5 bar.
+    p = W.hs_wall_nm(eta)
+    sol = from_problem(p, precision=_abi.DFT_FP32_MIXED)
+    x = _dev(p.initial_density())
+    it, r, st = sol.solve(x, 1e-10, 3000)
+    assert st == 0 and r <= 1e-10
+    q = W.hs_wall_nm(eta, n=(p.n[0], 1, 1))
+    s1 = picard.solve(residual.Setup(q), q.initial_density(), 1e-11, max_iter=3000)
+    ref = s1.rho[0, 0, 0, :]
+    rho = x.cpu().numpy()[0]
+    dev = np.max(np.abs(rho - ref[None, None, :])) / np.max(ref)
+    stats = sol.stats()
+    _say(f"  E1 FP32-mixed eta {eta:g}: {it} iterations, {stats['fp64_refresh']} FP64 refreshes, "
+         f"max n3 {stats['max_n3']:.3f}, vs 1-D oracle {dev:.1e}")
+    assert dev <= 1e-5
+
+
+def test_fp32_mixed_evaluation_near_close_packing():
+    # Packing 0.4 at the wall (reached by Newton-Krylov continuation in FP64): the FP32-mixed
+    # residual evaluation 1 % away from its reference agrees with the oracle's G to 1e-6, where
+    # n3 near the wall is far above the bath's 0.4.
+    x = None
+    prev = None
+    for eta in (0.3, 0.35, 0.4):
+        p = W.hs_wall_nm(eta)
+        sol = from_problem(p)
+        x = _dev(p.initial_density()) if x is None else x * (p.rho_bulk[0] / prev.rho_bulk[0])
+        it, cg, r, status = sol.newton(x, 1e-10, 100)
+        assert status == 0 and r <= 1e-10
+        prev = p
+    m = from_problem(p, precision=_abi.DFT_FP32_MIXED)
+    m.set_reference(x)
+    ramp = torch.sin(torch.arange(x.numel(), device="cuda", dtype=torch.float64)).reshape(x.shape)
+    x2 = x * (1 + 0.01 * ramp)
+    st = residual.Setup(p)
+    ev = st.evaluate(x2.cpu().numpy())
+    Gm, _ = m.residual(x2)
+    e = float(np.max(np.abs(Gm.cpu().numpy() - ev["G"])) / np.max(np.abs(ev["G"])))
+    _say(f"  packing 0.4: max n3 {ev['n3max']:.3f}; FP32-mixed G 1 % from the reference vs the oracle {e:.1e}")
+    assert ev["n3max"] > 0.5
+    assert e < 1e-6
