@@ -14,14 +14,10 @@ static void launch_z1c_var(const Geo &g, const Z1Args &a, int es, hipStream_t s)
     dim3 grid((unsigned)ct_cdiv(g.Kx, P), (unsigned)g.ny, (unsigned)g.nprob);
     if (!es) hipLaunchKernelGGL((k_z1c<T, L, P, NTB, 0>), grid, dim3(NTB), 0, s, g, a);
     else {
-        bool done = false;
-        if constexpr (std::is_same<T, float>::value) {
-            if (g.S <= 2) {
-                hipLaunchKernelGGL((k_z1c<T, L, P, NTB, 2>), grid, dim3(NTB), 0, s, g, a);
-                done = true;
-            }
-        }
-        if (!done) hipLaunchKernelGGL((k_z1c<T, L, P, NTB, 4>), grid, dim3(NTB), 0, s, g, a);
+        // the pair accumulators are sized for the species count: fewer registers for S < 4
+        if (g.S <= 2) hipLaunchKernelGGL((k_z1c<T, L, P, NTB, 2>), grid, dim3(NTB), 0, s, g, a);
+        else if (g.S == 3) hipLaunchKernelGGL((k_z1c<T, L, P, NTB, 3>), grid, dim3(NTB), 0, s, g, a);
+        else hipLaunchKernelGGL((k_z1c<T, L, P, NTB, 4>), grid, dim3(NTB), 0, s, g, a);
     }
     ct_check("z1 (compiled length)");
 }

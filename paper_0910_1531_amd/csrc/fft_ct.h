@@ -86,6 +86,46 @@ constexpr bool xswz_fits(int L) {
     return true;
 }
 
+// Row swizzle of y and z tiles (pencil index fastest: LDS row e holds element e of the P
+// pencils).  LDS serves 128 bytes per cycle, sixteen 8-byte or eight 16-byte lanes.  Rows of
+// 64 or 32 bytes put two or four rows in one cycle's lanes, and the Stockham writes of the
+// early stages send those lanes to rows a multiple of 4 or 8 apart, which sit on the same
+// banks.  XOR-ing higher bits of the row index into its low bit (64-byte rows) or two low
+// bits (32-byte rows) spreads them over distinct banks; the bits are chosen per length by an
+// exhaustive search over this access model (power-of-two lengths: no conflicts left in either
+// direction).  Rows of 128 bytes or more are not swizzled.  A bijection on each aligned
+// block of 2 or 4 rows, so rows stay inside [0, L).
+template <int L, int ROWB>
+__host__ __device__ constexpr int yzswz(int e) {
+    constexpr bool pow2 = (L & (L - 1)) == 0;
+    const int b2 = (e >> 2) & 1, b3 = (e >> 3) & 1, b4 = (e >> 4) & 1, b5 = (e >> 5) & 1;
+    if constexpr (ROWB == 64) {
+        if constexpr (pow2 || L == 48) return e ^ (b2 ^ b3);
+        else if constexpr (L == 24 || L == 192) return e ^ (b3 ^ b4);
+        else return e ^ b3;
+    } else if constexpr (ROWB == 32) {
+        int x = 0, y = 0;
+        if constexpr (pow2) { x = b2 ^ b3; y = b3 ^ b4; }
+        else if constexpr (L == 24) { x = b3; y = b3 ^ b4; }
+        else if constexpr (L == 48) { x = b2; y = b3 ^ b4; }
+        else if constexpr (L == 192) { x = b3 ^ b4; y = b3 ^ b5; }
+        else { x = b3 ^ b5; y = b3 ^ b4; }
+        return e ^ (x | (y << 1));
+    } else {
+        return e;
+    }
+}
+template <int L, int ROWB>
+constexpr bool yzswz_ok() {
+    bool seen[L] = {};
+    for (int e = 0; e < L; ++e) {
+        const int f = yzswz<L, ROWB>(e);
+        if (f < 0 || f >= L || seen[f]) return false;
+        seen[f] = true;
+    }
+    return true;
+}
+
 // BF = false: the pencil index varies fastest over threads and in LDS (y and z tiles,
 // whose pencils are adjacent columns in HBM).  BF = true: the element index varies fastest
 // (x tiles, whose pencils are rows); elements are swizzled (xswz) against bank conflicts.
@@ -155,7 +195,12 @@ struct Fft {
         }
     }
     static_assert(!BF || xswz_fits<T>(L), "swizzle leaves the pencil");
-    __device__ static __forceinline__ int lidx(int p, int e) { return BF ? p * LS + xswz<T>(e) : e * P + p; }
+    static constexpr int ROWB = P * (int)sizeof(cx<T>);
+    static_assert(BF || yzswz_ok<L, ROWB>(), "row swizzle is not a permutation");
+    __device__ static __forceinline__ int lidx(int p, int e) {
+        if constexpr (BF) return p * LS + xswz<T>(e);
+        else return yzswz<L, ROWB>(e) * P + p;
+    }
 
     // Pencil p and element e that register i holds as an input of a first stage (or an
     // output of a last stage) of radix R; false for registers of idle butterflies.
