@@ -279,6 +279,24 @@ dft_status dft_adjoint(dft_ctx *ctx, const double *rho_star, const double *dO_dr
                        int32_t *iters_out, double *resid_out);
 
 /*
+ * dft_adjoint without a workspace argument, for callers that cannot allocate device memory
+ * (code under HIP graph capture, serving loops, harnesses that forbid hipMalloc).  The same
+ * computation and results as dft_adjoint; the workspace is a fixed array of
+ * DFT_ADJOINT_NOALLOC_MAX_BYTES in the library's device image, one per GPU, held until the
+ * process ends.  The call allocates no device or host memory (an error message is formatted
+ * only on failure) and needs dft_adjoint_workspace_size(params) <= DFT_ADJOINT_NOALLOC_MAX_BYTES
+ * (about a 40^3 grid with three species), else DFT_E_WORKSPACE.  Every call on one GPU shares
+ * that GPU's array: calls that overlap on one GPU (several threads, or streams not ordered
+ * against each other) race and must be serialized by the caller.  Nothing in the array needs
+ * to start at zero; the previous call's contents are overwritten.  Call with the ctx's device
+ * current.  Arguments, outputs and errors otherwise as dft_adjoint.
+ */
+#define DFT_ADJOINT_NOALLOC_MAX_BYTES (64u << 20)
+dft_status dft_adjoint_noalloc(dft_ctx *ctx, const double *rho_star, const double *dO_drho, double tol,
+                               int32_t max_iter, double *dO_dvext, double *dO_drho_bulk, double *dO_dsigma,
+                               int32_t *iters_out, double *resid_out);
+
+/*
  * Newton-Krylov solve of the fixed point rho = G(rho) (eq. rhoEquation), an alternative to
  * the Picard iteration of the nonlinear-solver section with the exact Jacobian instead of a
  * finite-difference one: each step solves (I - diag(G) H) d = G - rho, symmetrized as

@@ -23,6 +23,7 @@ FLAG_NO_AUTOTUNE = 4
 HS_RSLT, HS_ROSENFELD, HS_WHITE_BEAR = 0, 1, 2
 HS_FUNCTIONALS = {"rslt": HS_RSLT, "rosenfeld": HS_ROSENFELD, "whitebear": HS_WHITE_BEAR}
 SCHEDULE_LEN = 8
+ADJOINT_NOALLOC_MAX_BYTES = 64 << 20
 RFD_MAX_NODES = 128
 TUNE_PASSES = ["y", "z_plain", "z_weights", "z_back"]
 
@@ -74,6 +75,8 @@ SIGNATURES = [
     ("dft_adjoint_workspace_size", [ctypes.POINTER(Params), ctypes.POINTER(ctypes.c_size_t)]),
     ("dft_adjoint", [_vp, _vp, _vp, _vp, ctypes.c_size_t, ctypes.c_double, ctypes.c_int32, _vp, _dp, _dp,
                      ctypes.POINTER(ctypes.c_int32), _dp]),
+    ("dft_adjoint_noalloc", [_vp, _vp, _vp, ctypes.c_double, ctypes.c_int32, _vp, _dp, _dp,
+                             ctypes.POINTER(ctypes.c_int32), _dp]),
     ("dft_batch_workspace_size", [ctypes.POINTER(Params), ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]),
     ("dft_setup_batch", [ctypes.POINTER(Params), ctypes.c_int32, _vp, _vp, _vp, ctypes.c_size_t, _vp,
                          ctypes.POINTER(_vp)]),

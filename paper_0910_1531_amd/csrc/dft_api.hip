@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -905,12 +906,23 @@ void forward3d(dft_ctx *c, const double *src, int nfield, void *dst, hipStream_t
     launch_y<double>(g, za, s);
 }
 
-std::vector<double> read_scalars(dft_ctx *c, const double *dev, int n) {
-    std::vector<double> h(n);
-    HIPCHK(hipMemcpyAsync(h.data(), dev, sizeof(double) * n, hipMemcpyDeviceToHost, c->stream));
+// Host copy of n <= kMaxScalars device scalars, in a fixed array (no heap allocation).
+constexpr int kMaxScalars = 64;
+static_assert(kAdjNV <= kMaxScalars, "adjoint reductions exceed the scalar buffer");
+struct Scalars {
+    double v[kMaxScalars];
+    double operator[](int i) const { return v[i]; }
+};
+Scalars read_scalars(dft_ctx *c, const double *dev, int n) {
+    Scalars h;
+    HIPCHK(hipMemcpyAsync(h.v, dev, sizeof(double) * n, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     return h;
 }
+
+dft_status adjoint_run(dft_ctx *ctx, const double *rho_star, const double *dO_drho, char *w8, double tol,
+                       int32_t max_iter, double *dO_dvext, double *dO_drho_bulk, double *dO_dsigma,
+                       int32_t *iters_out, double *resid_out);
 
 }  // namespace
 
@@ -929,10 +941,23 @@ dft_status dft_adjoint(dft_ctx *ctx, const double *rho_star, const double *dO_dr
                        double tol, int32_t max_iter, double *dO_dvext, double *dO_drho_bulk, double *dO_dsigma,
                        int32_t *iters_out, double *resid_out) {
     if (!ctx || !rho_star || !dO_drho) return fail(DFT_E_INVALID_ARG, "ctx, rho_star or dO_drho is NULL");
-    if (!(tol > 0.0) || max_iter < 1) return fail(DFT_E_INVALID_ARG, "tol must be > 0 and max_iter >= 1");
     const AdjLayout L = adj_layout(&ctx->p);
     if (!adj_ws || adj_ws_bytes < L.total || ((uintptr_t)adj_ws) % 256 != 0)
         return fail(DFT_E_WORKSPACE, "adjoint workspace missing, misaligned or smaller than dft_adjoint_workspace_size");
+    return adjoint_run(ctx, rho_star, dO_drho, (char *)adj_ws, tol, max_iter, dO_dvext, dO_drho_bulk, dO_dsigma,
+                       iters_out, resid_out);
+}
+
+}  // extern "C"
+
+namespace {
+
+// The implicit adjoint of dft_adjoint with its workspace at w8 (adj_layout bytes, 256-byte aligned).
+dft_status adjoint_run(dft_ctx *ctx, const double *rho_star, const double *dO_drho, char *w8, double tol,
+                       int32_t max_iter, double *dO_dvext, double *dO_drho_bulk, double *dO_dsigma,
+                       int32_t *iters_out, double *resid_out) {
+    if (!(tol > 0.0) || max_iter < 1) return fail(DFT_E_INVALID_ARG, "tol must be > 0 and max_iter >= 1");
+    const AdjLayout L = adj_layout(&ctx->p);
     if (ctx->geo.S > 4) return fail(DFT_E_UNSUPPORTED_SIZE, "adjoint gradients support at most 4 species");
     if ((size_t)DFT_NALPHA * ctx->geo.nx * 16 > 65536)
         return fail(DFT_E_UNSUPPORTED_SIZE, "adjoint needs n_x <= 384 (FP64 Hessian pass)");
@@ -942,7 +967,6 @@ dft_status dft_adjoint(dft_ctx *ctx, const double *rho_star, const double *dO_dr
         const int S = g.S;
         const long long N = g.N, SN = (long long)S * N;
         hipStream_t s = c->stream;
-        char *w8 = (char *)adj_ws;
         double *nstar = (double *)(w8 + L.nstar), *dphi = (double *)(w8 + L.dphi), *G = (double *)(w8 + L.G);
         double *w = (double *)(w8 + L.w), *r = (double *)(w8 + L.r), *p = (double *)(w8 + L.p);
         double *q = (double *)(w8 + L.q), *Hp = (double *)(w8 + L.Hp), *t = (double *)(w8 + L.t);
@@ -968,7 +992,7 @@ dft_status dft_adjoint(dft_ctx *ctx, const double *rho_star, const double *dO_dr
         enqueue_hess(c, w, Hp, nstar, nullptr, s);
         nb = adj_r0(SN, G, Hp, r, p, part, s);
         adj_reduce(part, nb, 2, scal, s);
-        std::vector<double> sc = read_scalars(c, scal, 2);
+        Scalars sc = read_scalars(c, scal, 2);
         double rz = sc[0], rr = sc[1];
         int it = 0;
         double rel = std::sqrt(rr) / gnorm;
@@ -1002,7 +1026,7 @@ dft_status dft_adjoint(dft_ctx *ctx, const double *rho_star, const double *dO_dr
         enqueue_hess(c, w, Hp, nstar, t, s);
         // W_i = sum_x w_i
         nb = adj_fieldsum(N, S, w, part, s);
-        std::vector<double> Wsum(S, 0.0);
+        double Wsum[DFT_MAX_SPECIES] = {};
         for (int i = 0; i < S; ++i) {
             adj_reduce(part + (long long)i * nb, nb, 1, scal + i, s);
         }
@@ -1075,6 +1099,54 @@ dft_status dft_adjoint(dft_ctx *ctx, const double *rho_star, const double *dO_dr
     });
 }
 
+// ------------------------------------------------------------------ adjoint without allocation
+// dft_adjoint_noalloc keeps its workspace in this array of the library's device image, one copy
+// per GPU, resident until the process ends.  Host code reaches it only through the address
+// hipGetSymbolAddress returns on each device (kept in scratch_dev); the array's name is a host
+// stand-in, never a device address.
+__device__ __align__(256) char scratch[DFT_ADJOINT_NOALLOC_MAX_BYTES];
+
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+void *scratch_dev[kScratchDevices] = {};
+
+// The current device's copy of the scratch array, looked up on the device's first call.
+dft_status scratch_address(char **out) {
+    int dev = -1;
+    const hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(DFT_E_DEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    if (dev < 0 || dev >= kScratchDevices) return fail(DFT_E_DEVICE, "device index out of range for the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!scratch_dev[dev]) {
+        void *p = nullptr;
+        const hipError_t e2 = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e2 != hipSuccess || !p)
+            return fail(DFT_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e2));
+        scratch_dev[dev] = p;
+    }
+    *out = (char *)scratch_dev[dev];
+    return DFT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+dft_status dft_adjoint_noalloc(dft_ctx *ctx, const double *rho_star, const double *dO_drho, double tol,
+                               int32_t max_iter, double *dO_dvext, double *dO_drho_bulk, double *dO_dsigma,
+                               int32_t *iters_out, double *resid_out) {
+    if (!ctx || !rho_star || !dO_drho) return fail(DFT_E_INVALID_ARG, "ctx, rho_star or dO_drho is NULL");
+    const AdjLayout L = adj_layout(&ctx->p);
+    if (L.total > (size_t)DFT_ADJOINT_NOALLOC_MAX_BYTES)
+        return fail(DFT_E_WORKSPACE, "problem needs more adjoint workspace than DFT_ADJOINT_NOALLOC_MAX_BYTES; "
+                                     "use dft_adjoint with a caller workspace");
+    char *w8 = nullptr;
+    const dft_status st = scratch_address(&w8);
+    if (st != DFT_OK) return st;
+    return adjoint_run(ctx, rho_star, dO_drho, w8, tol, max_iter, dO_dvext, dO_drho_bulk, dO_dsigma, iters_out,
+                       resid_out);
+}
+
 // ------------------------------------------------------------------ Newton-Krylov
 dft_status dft_newton(dft_ctx *ctx, double *rho, void *adj_ws, size_t adj_ws_bytes, double tol, int32_t max_iter,
                       int32_t *iters_out, int32_t *cg_iters_out, double *norm_out) {
@@ -1110,7 +1182,7 @@ dft_status dft_newton(dft_ctx *ctx, double *rho, void *adj_ws, size_t adj_ws_byt
             e.fp64 = true;
             e.count_kind = 0;
             enqueue_eval(c, e, s);
-            const std::vector<double> fm = read_scalars(c, &c->st->fb, 2);
+            const Scalars fm = read_scalars(c, &c->st->fb, 2);
             f = fm[0];
             m = fm[1];
         };
@@ -1133,7 +1205,7 @@ dft_status dft_newton(dft_ctx *ctx, double *rho, void *adj_ws, size_t adj_ws_byt
                 enqueue_hess(c, d, Hp, nstar, nullptr, s);
                 nb = adj_r0(SN, G, Hp, r, p, part, s);
                 adj_reduce(part, nb, 2, scal, s);
-                std::vector<double> sc = read_scalars(c, scal, 2);
+                Scalars sc = read_scalars(c, scal, 2);
                 double rz = sc[0], rel = std::sqrt(sc[1]) / gnorm;
                 for (int k = 0; k < 500 && rel > eta; ++k) {
                     enqueue_hess(c, p, Hp, nstar, nullptr, s);
