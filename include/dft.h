@@ -128,7 +128,7 @@ typedef struct dft_stats {
     int64_t rejected;        /* line-search steps that did not lower the residual */
     int64_t g_evals;         /* full residual evaluations */
     int64_t n3_evals;        /* n3-only evaluations (step-cap path of the line search) */
-    int64_t fp64_refresh;    /* FP64 reference evaluations (FP32-mixed only) */
+    int64_t fp64_refresh;    /* FP64 reference evaluations (FP32-mixed only; counted since dft_setup) */
     double residual;         /* r at the current iterate */
     double alpha;            /* last accepted step */
     double max_n3;           /* max n3 at the current iterate */

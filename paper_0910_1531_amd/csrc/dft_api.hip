@@ -720,7 +720,7 @@ dft_status dft_solve(dft_ctx *ctx, double *rho_inout, double tol, int32_t max_it
             for (int k = 0; k < K; ++k) HIPCHK(hipGraphLaunch(ctx->gexec, ctx->stream));
             h = read_state(ctx);
             fp64_checked = !ctx->mixed;
-            if (ctx->mixed && !h.converged && !h.status && (h.r < 1e-3 * r_ref || !(h.r < 0.99 * r_prev))) {
+            if (ctx->mixed && !h.converged && !h.status && (h.r < 1e-4 * r_ref || !(h.r < 0.99 * r_prev))) {
                 // refresh the FP64 reference once the residual has fallen far below the
                 // reference's, or stalls at the FP32 noise floor
                 enqueue_prime(ctx, ctx->stream);
@@ -1333,9 +1333,22 @@ struct dft_batch {
         std::vector<int> idx;         // members sharing launch choices (see same_shape)
         dft_ctx *lead = nullptr;      // geometry covering the whole group (nprob, pstride)
         long long stride = 0;
+        int rec = 0;                  // the group's first record in the state mirror
+        hipStream_t stream = nullptr; // the group's work stream (one of gstreams)
     };
     std::vector<Group> groups;
-    hipStream_t stream = nullptr;
+    hipStream_t stream = nullptr;     // the caller's stream
+    // Groups run concurrently on up to kBatchStreams streams of default priority, ordered after
+    // the caller's stream at the start of a solve and before it at the end.
+    std::vector<hipStream_t> gstreams;
+    hipEvent_t fork = nullptr;
+    std::vector<hipEvent_t> joins;
+    // Line-search states of all members, group by group: gathered on the device into one array
+    // and read by the host with one copy per group (pinned host mirror); refresh gates the same way.
+    DevState *mirror_dev = nullptr;
+    int *gates_dev = nullptr;
+    DevState *mirror_host = nullptr;
+    int *gates_host = nullptr;
 };
 
 namespace {
@@ -1349,9 +1362,12 @@ bool same_shape(const dft_params &a, const dft_params &b) {
            (a.flags & DFT_FLAG_CUTOFF_LAMBDA) == (b.flags & DFT_FLAG_CUTOFF_LAMBDA);
 }
 
-// Groups (first-seen order) and the byte offset of every member in the batch workspace.
+constexpr int kBatchStreams = 4;
+
+// Groups (first-seen order), the byte offset of every member in the batch workspace, and the
+// offsets of the state mirror (count records) and refresh gates (count ints) after them.
 size_t batch_plan(const dft_params *params, int count, std::vector<dft_batch::Group> *groups,
-                  std::vector<size_t> *offsets) {
+                  std::vector<size_t> *offsets, size_t *mirror_off = nullptr, size_t *gates_off = nullptr) {
     groups->clear();
     offsets->assign(count, 0);
     for (int i = 0; i < count; ++i) {
@@ -1365,11 +1381,18 @@ size_t batch_plan(const dft_params *params, int count, std::vector<dft_batch::Gr
         }
     }
     size_t off = 0;
+    int rec = 0;
     for (auto &g : *groups) {
         g.stride = (long long)make_layout(&params[g.idx[0]]).total;
+        g.rec = rec;
+        rec += (int)g.idx.size();
         for (size_t m = 0; m < g.idx.size(); ++m) (*offsets)[g.idx[m]] = off + m * (size_t)g.stride;
         off += g.idx.size() * (size_t)g.stride;
     }
+    if (mirror_off) *mirror_off = off;
+    off = align_up(off + sizeof(DevState) * (size_t)count);
+    if (gates_off) *gates_off = off;
+    off = align_up(off + sizeof(int) * (size_t)count);
     return off;
 }
 
@@ -1401,7 +1424,10 @@ dft_status dft_setup_batch(const dft_params *params, int32_t count, const double
     dft_batch *b = new dft_batch();
     b->stream = (hipStream_t)stream;
     std::vector<size_t> offs;
-    batch_plan(params, count, &b->groups, &offs);
+    size_t moff = 0, goff = 0;
+    batch_plan(params, count, &b->groups, &offs, &moff, &goff);
+    b->mirror_dev = (DevState *)((char *)workspace + moff);
+    b->gates_dev = (int *)((char *)workspace + goff);
     for (int i = 0; i < count; ++i) {
         dft_ctx *c = nullptr;
         st = dft_setup(&params[i], beta_vext ? beta_vext[i] : nullptr, fixed_charge ? fixed_charge[i] : nullptr,
@@ -1422,8 +1448,22 @@ dft_status dft_setup_batch(const dft_params *params, int32_t count, const double
         lead->geo.pstride = g.stride;
         g.lead = lead;
     }
-    // launch shapes for the whole group (the members' spectra are scratch here)
+    // launch shapes for the whole group (the members' spectra are scratch here); group streams,
+    // events and the pinned state mirror
     st = guarded([&]() -> dft_status {
+        const int ns = std::min<int>((int)b->groups.size(), kBatchStreams);
+        for (int k = 0; k < ns; ++k) {
+            hipStream_t gs = nullptr;
+            HIPCHK(hipStreamCreateWithFlags(&gs, hipStreamNonBlocking));
+            b->gstreams.push_back(gs);
+            hipEvent_t ev = nullptr;
+            HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+            b->joins.push_back(ev);
+        }
+        HIPCHK(hipEventCreateWithFlags(&b->fork, hipEventDisableTiming));
+        for (size_t k = 0; k < b->groups.size(); ++k) b->groups[k].stream = b->gstreams[k % ns];
+        HIPCHK(hipHostMalloc((void **)&b->mirror_host, sizeof(DevState) * (size_t)count, hipHostMallocDefault));
+        HIPCHK(hipHostMalloc((void **)&b->gates_host, sizeof(int) * (size_t)count, hipHostMallocDefault));
         for (auto &g : b->groups) {
             dft_ctx *lead = g.lead;
             if (lead->geo.nprob > 1 && !(lead->p.flags & DFT_FLAG_NO_AUTOTUNE))
@@ -1456,28 +1496,49 @@ dft_status dft_solve_batch(dft_batch *batch, double *const *rho_inout, double to
         if (!rho_inout[i]) return fail(DFT_E_INVALID_ARG, "rho_inout has a NULL entry");
     return guarded([&]() -> dft_status {
         hipStream_t s = batch->stream;
+        DevState *hm = batch->mirror_host;
+        std::vector<int> rec(n);
+        for (auto &g : batch->groups)
+            for (size_t m = 0; m < g.idx.size(); ++m) rec[g.idx[m]] = g.rec + (int)m;
         std::vector<DevState> h(n);
         std::vector<double> r_ref(n), r_prev(n);
         std::vector<char> checked(n, 1), done(n, 0);
         std::vector<int> stat(n, DFT_OK);
+        auto first_state = [&](const dft_batch::Group &g) { return batch->members[g.idx[0]]->st; };
+        // every group's states: gathered on its stream, one copy per group, then one wait per stream
+        auto read_all = [&]() {
+            for (auto &g : batch->groups) {
+                const int m = (int)g.idx.size();
+                launch_copy_states(batch->mirror_dev + g.rec, (long long)sizeof(DevState), first_state(g), g.stride,
+                                   m, g.stream);
+                HIPCHK(hipMemcpyAsync(hm + g.rec, batch->mirror_dev + g.rec, sizeof(DevState) * m,
+                                      hipMemcpyDeviceToHost, g.stream));
+            }
+            for (hipStream_t gs : batch->gstreams) HIPCHK(hipStreamSynchronize(gs));
+            for (int i = 0; i < n; ++i) h[i] = hm[rec[i]];
+        };
+        // the group streams start after the caller's earlier work
+        HIPCHK(hipEventRecord(batch->fork, s));
+        for (hipStream_t gs : batch->gstreams) HIPCHK(hipStreamWaitEvent(gs, batch->fork, 0));
         for (auto &g : batch->groups) {
-            for (int i : g.idx) {
-                dft_ctx *c = batch->members[i];
-                c->stream = s;
-                write_state(c, fresh_state(c, tol, max_iter));
-                launch_copy(c->rho0, rho_inout[i], (long long)c->geo.S * c->geo.N, s);
+            const int m = (int)g.idx.size();
+            for (int k = 0; k < m; ++k) {
+                dft_ctx *c = batch->members[g.idx[k]];
+                hm[g.rec + k] = fresh_state(c, tol, max_iter);
+                launch_copy(c->rho0, rho_inout[g.idx[k]], (long long)c->geo.S * c->geo.N, g.stream);
                 c->step_rho = nullptr;
             }
-            g.lead->stream = s;
-            enqueue_prime(g.lead, s);
+            HIPCHK(hipMemcpyAsync(batch->mirror_dev + g.rec, hm + g.rec, sizeof(DevState) * m, hipMemcpyHostToDevice,
+                                  g.stream));
+            launch_copy_states(first_state(g), g.stride, batch->mirror_dev + g.rec, (long long)sizeof(DevState), m,
+                               g.stream);
+            enqueue_prime(g.lead, g.stream);
             for (int i : g.idx)
                 if (batch->members[i]->mixed) batch->members[i]->refreshes += 1;
             ensure_graph(g.lead);
         }
-        for (int i = 0; i < n; ++i) {
-            h[i] = read_state(batch->members[i]);
-            r_ref[i] = r_prev[i] = h[i].r;
-        }
+        read_all();
+        for (int i = 0; i < n; ++i) r_ref[i] = r_prev[i] = h[i].r;
         for (;;) {
             // classify, and choose the members that need an FP64 (reference) evaluation
             std::vector<char> refresh(n, 0);
@@ -1493,7 +1554,7 @@ dft_status dft_solve_batch(dft_batch *batch, double *const *rho_inout, double to
                     stat[i] = DFT_E_NOT_CONVERGED;
                     done[i] = 1;
                     continue;
-                } else if (mixed && !checked[i] && (h[i].r < 1e-3 * r_ref[i] || !(h[i].r < 0.99 * r_prev[i]))) {
+                } else if (mixed && !checked[i] && (h[i].r < 1e-4 * r_ref[i] || !(h[i].r < 0.99 * r_prev[i]))) {
                     refresh[i] = 1;
                 }
                 any_active = true;
@@ -1505,19 +1566,17 @@ dft_status dft_solve_batch(dft_batch *batch, double *const *rho_inout, double to
                 for (int i : g.idx) gr |= refresh[i] != 0;
                 if (!gr) continue;
                 any_refresh = true;
-                std::vector<int> flags(g.idx.size());
-                for (size_t m = 0; m < g.idx.size(); ++m) {
-                    flags[m] = refresh[g.idx[m]];
-                    HIPCHK(hipMemcpyAsync(&batch->members[g.idx[m]]->st->gate_refresh, &flags[m], sizeof(int),
-                                          hipMemcpyHostToDevice, s));
-                }
-                enqueue_prime(g.lead, s, true);
-                HIPCHK(hipStreamSynchronize(s));
+                const int m = (int)g.idx.size();
+                for (int k = 0; k < m; ++k) batch->gates_host[g.rec + k] = refresh[g.idx[k]];
+                HIPCHK(hipMemcpyAsync(batch->gates_dev + g.rec, batch->gates_host + g.rec, sizeof(int) * m,
+                                      hipMemcpyHostToDevice, g.stream));
+                launch_set_gates(first_state(g), g.stride, m, batch->gates_dev + g.rec, g.stream);
+                enqueue_prime(g.lead, g.stream, true);
             }
             if (any_refresh) {
+                read_all();
                 for (int i = 0; i < n; ++i) {
                     if (!refresh[i]) continue;
-                    h[i] = read_state(batch->members[i]);
                     r_ref[i] = h[i].r;
                     checked[i] = 1;
                     batch->members[i]->refreshes += 1;
@@ -1531,20 +1590,31 @@ dft_status dft_solve_batch(dft_batch *batch, double *const *rho_inout, double to
                 long long ntot = 0;
                 for (int i : g.idx) ntot += batch->members[i]->geo.N;
                 const int K = ntot >= (1LL << 22) ? 4 : 16;
-                for (int k = 0; k < K; ++k) HIPCHK(hipGraphLaunch(g.lead->gexec, s));
+                for (int k = 0; k < K; ++k) HIPCHK(hipGraphLaunch(g.lead->gexec, g.stream));
             }
+            std::vector<double> r_last(n);
+            for (int i = 0; i < n; ++i) r_last[i] = h[i].r;
+            read_all();
             for (int i = 0; i < n; ++i) {
                 if (done[i]) continue;
-                r_prev[i] = h[i].r;
-                h[i] = read_state(batch->members[i]);
+                r_prev[i] = r_last[i];
                 checked[i] = !batch->members[i]->mixed;
             }
         }
         dft_status out = DFT_OK;
+        for (auto &g : batch->groups)
+            for (int i : g.idx) {
+                dft_ctx *c = batch->members[i];
+                launch_copy(rho_inout[i], c->rho0, (long long)c->geo.S * c->geo.N, g.stream);
+                c->step_rho = rho_inout[i];
+                c->stream = s;
+            }
+        // the caller's stream continues after every group's work
+        for (size_t k = 0; k < batch->gstreams.size(); ++k) {
+            HIPCHK(hipEventRecord(batch->joins[k], batch->gstreams[k]));
+            HIPCHK(hipStreamWaitEvent(s, batch->joins[k], 0));
+        }
         for (int i = 0; i < n; ++i) {
-            dft_ctx *c = batch->members[i];
-            launch_copy(rho_inout[i], c->rho0, (long long)c->geo.S * c->geo.N, s);
-            c->step_rho = rho_inout[i];
             if (iters_out) iters_out[i] = (int32_t)h[i].iters;
             if (norm_out) norm_out[i] = h[i].r;
             if (status_out) status_out[i] = stat[i];
@@ -1558,6 +1628,11 @@ dft_status dft_solve_batch(dft_batch *batch, double *const *rho_inout, double to
 
 dft_status dft_batch_destroy(dft_batch *batch) {
     if (!batch) return DFT_OK;
+    for (hipStream_t gs : batch->gstreams) (void)hipStreamDestroy(gs);
+    for (hipEvent_t ev : batch->joins) (void)hipEventDestroy(ev);
+    if (batch->fork) (void)hipEventDestroy(batch->fork);
+    if (batch->mirror_host) (void)hipHostFree(batch->mirror_host);
+    if (batch->gates_host) (void)hipHostFree(batch->gates_host);
     for (auto &g : batch->groups) {
         if (!g.lead) continue;
         if (g.lead->gexec) (void)hipGraphExecDestroy(g.lead->gexec);

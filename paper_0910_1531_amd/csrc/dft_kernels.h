@@ -192,6 +192,11 @@ void launch_make_base(const Consts *cs, int S, long long N, const double *vext, 
                       double *base, const double *mu_host, const double *z_host, double *count_part, int nblk,
                       hipStream_t s);
 void launch_sum_to(const double *part, int n, double *dst, hipStream_t s);
+// Line-search state records: nrec copies between strided places (byte strides), and the
+// refresh gate of each record set from gates[i] (device ints).
+void launch_copy_states(void *dst, long long dst_stride, const void *src, long long src_stride, int nrec,
+                        hipStream_t s);
+void launch_set_gates(DevState *first, long long stride, int nrec, const int *gates, hipStream_t s);
 void launch_copy(double *dst, const double *src, long long count, hipStream_t s, int nprob = 1,
                  long long pstride = 0, const int *gate = nullptr);
 

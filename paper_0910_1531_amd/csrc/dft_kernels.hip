@@ -1270,4 +1270,36 @@ void launch_copy(double *dst, const double *src, long long count, hipStream_t s,
     check_launch("copy");
 }
 
+// Copies nrec line-search state records between strided places (byte strides): gathers the
+// states of a batch group's problems into one contiguous array for a single host read, and
+// writes them back.  With `gates`, only gate_refresh of every record is written, from gates[i].
+__global__ __launch_bounds__(NT) void k_copy_states(char *dst, long long dst_stride, const char *src,
+                                                    long long src_stride, int nrec, const int *gates) {
+    const int rec = blockIdx.x;
+    if (rec >= nrec) return;
+    DevState *d = reinterpret_cast<DevState *>(dst + rec * dst_stride);
+    if (gates) {
+        if (threadIdx.x == 0) d->gate_refresh = gates[rec];
+        return;
+    }
+    constexpr int W = (int)(sizeof(DevState) / sizeof(int));
+    static_assert(sizeof(DevState) % sizeof(int) == 0, "state record is not a whole number of ints");
+    const int *s = reinterpret_cast<const int *>(src + rec * src_stride);
+    int *dd = reinterpret_cast<int *>(d);
+    for (int i = threadIdx.x; i < W; i += NT) dd[i] = s[i];
+}
+
+void launch_copy_states(void *dst, long long dst_stride, const void *src, long long src_stride, int nrec,
+                        hipStream_t s) {
+    hipLaunchKernelGGL(k_copy_states, dim3((unsigned)nrec), dim3(NT), 0, s, (char *)dst, dst_stride,
+                       (const char *)src, src_stride, nrec, (const int *)nullptr);
+    check_launch("copy_states");
+}
+
+void launch_set_gates(DevState *first, long long stride, int nrec, const int *gates, hipStream_t s) {
+    hipLaunchKernelGGL(k_copy_states, dim3((unsigned)nrec), dim3(NT), 0, s, (char *)first, stride,
+                       (const char *)nullptr, 0LL, nrec, gates);
+    check_launch("set_gates");
+}
+
 }  // namespace dft
