@@ -381,7 +381,9 @@ dft_status dft_get_stats(dft_ctx *ctx, dft_stats *out);
  * Launch shapes of the FFT pass kernels (batched FFT schedules, Section 4's many
  * transforms per step): for each pass in {y, plain z, z weighted densities, z
  * back-convolution} and each transform precision {FP64, FP32}, the index of the tile
- * shape in use, as DFT_SCHEDULE_LEN int32 laid out [pass][precision].  dft_setup picks
+ * shape in use, as DFT_SCHEDULE_LEN int32 laid out [pass][precision].  y and plain z: 5
+ * shapes; z weighted densities: 6 (three tile widths fused with the forward z transform
+ * of the species, then the same widths after a separate plain z pass); z back-convolution: 3.  dft_setup picks
  * them by timing every shape on the device (the autotuner; DFT_FLAG_NO_AUTOTUNE keeps
  * shape 0).  Every shape of a pass performs the same arithmetic in the same order, so the
  * shapes change run time only, never results.  dft_set_schedule validates each index

@@ -456,6 +456,206 @@ __global__ __launch_bounds__(NTB) void k_z1c(Geo g_in, Z1Args a) {
     }
 }
 
+// Z1 from z spectra: the same products and inverse transforms as k_z1c, for species spectra
+// that the plain z pass has already transformed along z (the autotuner's split Z1 shapes).  With
+// the forward transform in its own kernel, this one needs neither the prefetched inputs nor the
+// forward twiddles in registers, and more waves fit per SIMD.  Each thread reads the species
+// values at the positions it starts the inverse transforms from, so the electrostatic spectra
+// overwrite species values only after the same thread has read them.
+template <typename T, int L, int P, int NTB, int MS>
+__global__ __launch_bounds__(NTB) void k_z1s(Geo g_in, Z1Args a) {
+    using F = ct::Fft<T, typename ct::Plan<L>::type, P, NTB, false, 2>;
+    constexpr int NO = F::template nin<1>();
+    constexpr bool TAB = std::is_same<T, double>::value;
+    constexpr int ME = MS > 0 ? MS : 1;
+    const int prob = (int)blockIdx.z;
+    if (prob > 0) {
+        const long long o = (long long)prob * g_in.pstride;
+        g_in = shift(g_in, o);
+        a = shift(a, o);
+    }
+    const Geo &g = g_in;
+    if (gated_off(a.gate)) return;
+    __shared__ cx<T> lds[F::LDS_ELEMS];
+    const Consts &c = *g.cs;
+    const int Kx = g.Kx, S = g.S;
+    const long long NC = g.NC;
+    int bx, y;
+    xcd_block(bx, y);
+    const int kx0 = bx * P;
+    const int Pact = min(P, Kx - kx0);
+    const long long rs = (long long)g.ny * Kx;
+    const long long off = (long long)y * Kx + kx0;
+    const cx<T> *tw = twp<T>(g, 2);
+    const bool es = MS > 0 && c.es && !a.n3only;
+    const ZWave<T> kw(c, kx0, y);
+    int pp[NO], ee[NO];
+    bool okk[NO];
+    long long ti[NO];
+    constexpr int NOF = TAB ? 1 : NO;
+    constexpr int MSF = (TAB || MS == 0) ? 1 : MS;
+    T kmag[NOF], invD[NOF], sn[MSF][NOF], cs[MSF][NOF];
+#pragma unroll
+    for (int i = 0; i < NO; ++i) {
+        okk[i] = F::template in_pos<1>(i, pp[i], ee[i]) && pp[i] < Pact;
+        ti[i] = okk[i] ? ee[i] * rs + pp[i] : 0;
+    }
+    if constexpr (!TAB) {
+        const Poisson<T> pd(g, c, y);
+#pragma unroll
+        for (int i = 0; i < NO; ++i) {
+            kmag[i] = kw.kmag(pp[i], ee[i]);
+            invD[i] = T(0);
+            if constexpr (MS > 0) {
+                if (es && !kw.zero(pp[i], ee[i])) invD[i] = T(c.four_pi_lB) * rcp_r(pd.denom(kx0 + pp[i], ee[i]));
+#pragma unroll
+                for (int is = 0; is < MS; ++is) {
+                    sn[is][i] = T(0);
+                    cs[is][i] = T(1);
+                    if (is < S) sincos_r(kmag[i] * T(c.R[is]), &sn[is][i], &cs[is][i]);
+                }
+            }
+        }
+    }
+    cx<T> acc[5][NO];
+    cx<T> esa[ME][NO];
+#pragma unroll
+    for (int i = 0; i < NO; ++i) {
+#pragma unroll
+        for (int m = 0; m < 5; ++m) acc[m][i] = mk<T>(T(0), T(0));
+#pragma unroll
+        for (int m = 0; m < ME; ++m) esa[m][i] = mk<T>(T(0), T(0));
+    }
+    for (int jsp = 0; jsp < S; ++jsp) {
+        const cx<T> *src = reinterpret_cast<const cx<T> *>(a.specA) + (long long)jsp * NC + off;
+        cx<T> uin[NO];
+#pragma unroll
+        for (int i = 0; i < NO; ++i) uin[i] = okk[i] ? ct::gld(src + ti[i]) : mk<T>(T(0), T(0));
+        const T Rj = T(c.R[jsp]), a0 = T(c.i4piR2[jsp]), a1 = T(c.i4piR[jsp]);
+        const T bath = T((double)c.N * c.rho_b[jsp]);
+#pragma unroll
+        for (int i = 0; i < NO; ++i) {
+            const cx<T> u = uin[i];
+            T w2, w3;
+            T ux = u.x;
+            if (MS > 0 && es && !a.diff && kw.zero(pp[i], ee[i])) ux -= bath;
+            if constexpr (TAB) {
+                const double *tab = g.tab64 + off;
+                w2 = ct::gld(tab + (long long)jsp * NC + ti[i]);
+                w3 = ct::gld(tab + (long long)(S + jsp) * NC + ti[i]);
+                if constexpr (MS > 0) {
+                    if (es) {
+#pragma unroll
+                        for (int is = 0; is < MS; ++is) {
+                            if (is < S) {
+                                const T kr = ct::gld(tab + (long long)pair_row(S, is, jsp) * NC + ti[i]);
+                                esa[is][i].x += kr * ux;
+                                esa[is][i].y += kr * u.y;
+                            }
+                        }
+                    }
+                }
+            } else if constexpr (MS > 0) {
+                T sj = sn[0][i], cj = cs[0][i];
+#pragma unroll
+                for (int is = 1; is < MS; ++is)
+                    if (is == jsp) { sj = sn[is][i]; cj = cs[is][i]; }
+                weight_w2_w3_sc<T>(kmag[i], Rj, sj, cj, w2, w3);
+                if (es) {
+#pragma unroll
+                    for (int is = 0; is < MS; ++is) {
+                        if (is < S) {
+                            const T sp = sn[is][i] * cj + cs[is][i] * sj;
+                            const T cp = cs[is][i] * cj - sn[is][i] * sj;
+                            const int ij = is * DFT_MAX_SPECIES + jsp;
+                            const T C = screening_hat_sc<T>(kmag[i], T(c.sc_R[ij]), sp, cp, T(c.sc_c1[ij]),
+                                                            T(c.sc_c0[ij]), T(c.sc_cm1[ij]));
+                            const T Pz = invD[i] * T(c.z[is] * c.z[jsp]);
+                            esa[is][i].x += C * ux - Pz * u.x;
+                            esa[is][i].y += (C - Pz) * u.y;
+                        }
+                    }
+                }
+            } else {
+                weight_w2_w3<T>(kmag[i], Rj, w2, w3);
+            }
+            const T m0 = w2 * a0, m1 = w2 * a1, m4 = w3 * a1;
+            acc[0][i].x += u.x * m0; acc[0][i].y += u.y * m0;
+            acc[1][i].x += u.x * m1; acc[1][i].y += u.y * m1;
+            acc[2][i].x += u.x * w2; acc[2][i].y += u.y * w2;
+            acc[3][i].x += u.x * w3; acc[3][i].y += u.y * w3;
+            acc[4][i].x += u.x * m4; acc[4][i].y += u.y * m4;
+        }
+    }
+    if constexpr (MS > 0) {
+        if (es) {
+#pragma unroll
+            for (int is = 0; is < MS; ++is) {
+                if (is >= S) break;
+                cx<T> *dst = reinterpret_cast<cx<T> *>(a.specA) + (long long)is * NC + off;
+#pragma unroll
+                for (int i = 0; i < NO; ++i)
+                    if (okk[i]) ct::gst(dst + ti[i], esa[is][i]);
+            }
+        }
+    }
+    // the seven inverse transforms and their stores, as in k_z1c
+    const int ntr = a.n3only ? 1 : 7;
+    const T invN = T(c.invN);
+    cx<T> v[F::V];
+    int ph = 0;
+    typename F::template TwReg<1> tri;
+    F::template load_tw<1>(tri, tw);
+    for (int t = 0; t < ntr; ++t) {
+        const int srcm = a.n3only ? 3 : (t < 5 ? t : (t == 5 ? 4 : 3));
+        const bool kzm = t >= 5;
+#pragma unroll
+        for (int i = 0; i < NO; ++i) {
+            cx<T> sm = acc[3][i];
+#pragma unroll
+            for (int m = 0; m < 5; ++m)
+                if (m == srcm) sm = acc[m][i];
+            if (kzm) {
+                const T kd = kw.comp(pp[i], ee[i], 2);
+                sm = mk<T>(kd * sm.y, -kd * sm.x);
+            }
+            v[i] = mk<T>(sm.x * invN, sm.y * invN);
+        }
+        F::template run<1>(v, lds, ph, tri);
+        auto store = [&](int o, int d) {
+            cx<T> *dst = reinterpret_cast<cx<T> *>(a.specB) + (long long)o * NC + off;
+#pragma unroll
+            for (int i = 0; i < F::template nout<1>(); ++i) {
+                int p, e;
+                const bool ok = F::template out_pos<1>(i, p, e);
+                if (!(ok && p < Pact)) continue;
+                cx<T> w = v[i];
+                if (d >= 0) {
+                    const T kd = kw.comp(p, e, d);
+                    w = mk<T>(kd * w.y, -kd * w.x);
+                }
+                ct::gst(dst + e * rs + p, w);
+            }
+        };
+        if (a.n3only) {
+            store(0, -1);
+        } else if (g.compact) {
+            store(t < 5 ? t : (t == 5 ? 6 : 9), -1);
+        } else if (t < 4) {
+            store(t, -1);
+            if (t == 3) {
+                store(7, 0);
+                store(8, 1);
+            }
+        } else if (t == 4) {
+            store(4, 0);
+            store(5, 1);
+        } else {
+            store(t == 5 ? 6 : 9, -1);
+        }
+    }
+}
+
 // Z2: forward z transform of the ten dPhi/dn spectra, back-convolution with conj(w_hat)
 // (eq. muHS; the vector parts enter as +i k_d times a w3 weight), plus the electrostatic
 // spectra Z1 left in specA, times 1/N, inverse z -> specA.  Z2_POISSON instead forms the
@@ -851,9 +1051,11 @@ __device__ __forceinline__ void split_rows(const cx<T> *split, cx<T> *out, long 
 enum X2Node { X2N_FP64 = 0, X2N_D32 = 1, X2N_ALT = 2 };
 
 // X2: ten weighted-density spectra after the y inverse -> inverse x -> pointwise dPhi/dn
-// (eq. Phi) -> forward x -> half spectra, in place in specB.
+// (eq. Phi) -> forward x -> half spectra, in place in specB.  Register budget of two waves per
+// SIMD: the FP64 kernel would otherwise take one (344 registers; a few spills are cheaper).
 template <typename T, int L, int NODE = X2N_FP64>
-__global__ __launch_bounds__(XTile<L>::NTB) void k_x2c(Geo g_in, X2Args a) {
+__global__ __launch_bounds__(XTile<L>::NTB) __attribute__((amdgpu_waves_per_eu(2))) void
+k_x2c(Geo g_in, X2Args a) {
     using XT = XTile<L>;
     constexpr int PB = XT::PB, NTB = XT::NTB, KX = XT::KX;
     using F = ct::Fft<T, typename ct::XPlan<L>::type, PB, NTB, true, 2, XT::PAD>;

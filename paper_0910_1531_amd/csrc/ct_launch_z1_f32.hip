@@ -22,10 +22,29 @@ static void launch_z1c_var(const Geo &g, const Z1Args &a, int es, hipStream_t s)
     ct_check("z1 (compiled length)");
 }
 
+// Split shapes (V = 3, 4, 5 for the tile widths of V - 3): the plain z pass transforms the
+// species spectra in place, then k_z1s forms the products and the inverse transforms.
+template <typename T, int L, int V>
+static void launch_z1s_var(const Geo &g, const Z1Args &a, int es, hipStream_t s) {
+    YArgs za{a.specA, g.S, -1, a.gate};
+    za.axis = 2;
+    launch_y<T>(g, za, s);
+    constexpr int P = z_width<T>(V), NTB = fit_threads(L, P, 4, 512);
+    dim3 grid((unsigned)ct_cdiv(g.Kx, P), (unsigned)g.ny, (unsigned)g.nprob);
+    if (!es) hipLaunchKernelGGL((k_z1s<T, L, P, NTB, 0>), grid, dim3(NTB), 0, s, g, a);
+    else if (g.S <= 2) hipLaunchKernelGGL((k_z1s<T, L, P, NTB, 2>), grid, dim3(NTB), 0, s, g, a);
+    else if (g.S == 3) hipLaunchKernelGGL((k_z1s<T, L, P, NTB, 3>), grid, dim3(NTB), 0, s, g, a);
+    else hipLaunchKernelGGL((k_z1s<T, L, P, NTB, 4>), grid, dim3(NTB), 0, s, g, a);
+    ct_check("z1 from z spectra (compiled length)");
+}
+
 template <typename T, int L>
 static void launch_z1c_len(const Geo &g, const Z1Args &a, int es, hipStream_t s, int v) {
     if (v == 1) launch_z1c_var<T, L, 1>(g, a, es, s);
     else if (v == 2) launch_z1c_var<T, L, 2>(g, a, es, s);
+    else if (v == 3) launch_z1s_var<T, L, 0>(g, a, es, s);
+    else if (v == 4) launch_z1s_var<T, L, 1>(g, a, es, s);
+    else if (v == 5) launch_z1s_var<T, L, 2>(g, a, es, s);
     else launch_z1c_var<T, L, 0>(g, a, es, s);
 }
 

@@ -79,6 +79,10 @@ int z_ct_variants(int L) {
     }
 }
 
+// Z1 shapes: the three fused tile widths, then the same widths split into the plain z pass and
+// k_z1s.
+int z1_ct_variants(int L) { return 2 * z_ct_variants(L); }
+
 int spec_table_rows(int nz, int S, int es) {
     if (z_ct_variants(nz) == 0) return 0;
     if (es && S > 4) return 0;   // electrostatic sums of more species: run-time-length kernels

@@ -1674,7 +1674,7 @@ dft_status dft_set_schedule(dft_ctx *ctx, const int32_t *shapes) {
     if (!ctx || !shapes) return fail(DFT_E_INVALID_ARG, "ctx or shapes is NULL");
     const Geo &g = ctx->geo;
     const int nv[4] = {g.ny > 1 ? y_ct_variants(g.ny, false) : 0, g.nz > 1 ? y_ct_variants(g.nz, false) : 0,
-                       z_ct_variants(g.nz), z_ct_variants(g.nz)};
+                       z1_ct_variants(g.nz), z_ct_variants(g.nz)};
     for (int p = 0; p < 4; ++p)
         for (int t = 0; t < 2; ++t) {
             const int v = shapes[2 * p + t];

@@ -158,6 +158,7 @@ template <typename T> bool launch_x3_ct(const Geo &g, const X3Args &a, hipStream
 int x_ct_pairs(int nx);   // row pairs per block of the compiled-length x kernels, 0 if none
 int y_ct_variants(int L, bool fp32);   // launch shapes of the y kernels of length L (0: none)
 int z_ct_variants(int L);              // launch shapes of the z kernels of length L (0: none)
+int z1_ct_variants(int L);             // launch shapes of the Z1 pass (fused and split)
 // Rows of the spectral tables for S species (0 when the compiled z kernels cannot run).
 int spec_table_rows(int nz, int S, int es);
 // Fill g.tab64 from the constants and twiddle tables.

@@ -32,6 +32,7 @@ int variants_of(const Geo &g, int pass) {
     switch (pass) {
         case TUNE_Y: return g.ny > 1 ? y_ct_variants(g.ny, false) : 0;
         case TUNE_YZ: return g.nz > 1 ? y_ct_variants(g.nz, false) : 0;
+        case TUNE_Z1: return z1_ct_variants(g.nz);
         default: return z_ct_variants(g.nz);
     }
 }

@@ -175,13 +175,41 @@ __device__ __forceinline__ void x2_node(const X2Args &a, long long N, long long 
     }
 }
 
-// FP32-mixed nodewise work of X2: the difference dPhi(nr + dn) - dPhi(nr) of eq. (Phi)
-// computed in FP32 term by term.  Every product is expanded by telescoping,
-// a b - ar br = (a - ar) b + ar (b - br), and every term carries one difference factor, so the
-// rounding error is proportional to |dn|, as in the FP32 transforms; log(1 - n3) enters only as
-// log1p(-dn3 / (1 - nr3)).  Reciprocals use the hardware's reciprocal instruction (about 1 ulp;
-// the coefficients need FP32 relative accuracy only).  n3 itself (the line-search bound) is formed
-// in FP64.  Flags and the n3 maximum as x2_node.
+// FP64 reciprocal: the hardware estimate refined by one Newton step (error about 1 ulp of FP64).
+__device__ __forceinline__ double rcp64(double x) {
+    const double r = __builtin_amdgcn_rcp(x);
+    return fma(r, fma(-x, r, 1.0), r);
+}
+
+// log(1 + u) in FP64.  For |u| <= 1/4, 2 atanh(s) with s = u / (2 + u) (|s| <= 1/7) summed to s^21,
+// which is below an FP64 ulp of the result (to s^5 when |s| < 2^-10: the next term is below
+// 2^-60 of s); otherwise the library's log1p.
+__device__ __forceinline__ double log1p64(double u) {
+    if (!(fabs(u) <= 0.25)) return log1p(u);
+    const double s = u * rcp64(2.0 + u), s2 = s * s;
+    if (fabs(s) < 0x1p-10) return 2.0 * fma(s * s2, fma(s2, 1.0 / 5.0, 1.0 / 3.0), s);
+    double p = 1.0 / 21.0;
+    p = fma(p, s2, 1.0 / 19.0);
+    p = fma(p, s2, 1.0 / 17.0);
+    p = fma(p, s2, 1.0 / 15.0);
+    p = fma(p, s2, 1.0 / 13.0);
+    p = fma(p, s2, 1.0 / 11.0);
+    p = fma(p, s2, 1.0 / 9.0);
+    p = fma(p, s2, 1.0 / 7.0);
+    p = fma(p, s2, 1.0 / 5.0);
+    p = fma(p, s2, 1.0 / 3.0);
+    return 2.0 * fma(s * s2, p, s);
+}
+
+// FP32-mixed nodewise work of X2: the difference dPhi(nr + dn) - dPhi(nr) of eq. (Phi).  The
+// factors that carry the packing singularity -- log(1 - n3) and the powers 1 / (1 - n3)^k with
+// their differences from the reference -- are formed in FP64 from the FP32 inputs; the rest in
+// FP32 term by term.  Every product is expanded by telescoping, a b - ar br = (a - ar) b +
+// ar (b - br), and every term carries one difference factor, so the rounding error is
+// proportional to |dn|, as in the FP32 transforms; log(1 - n3) enters only as
+// log1p(-dn3 / (1 - nr3)).  The FP32 reciprocals (the xi^2 ratio) use the hardware's reciprocal
+// instruction (about 1 ulp; the coefficients need FP32 relative accuracy only).  n3 itself (the
+// line-search bound) is formed in FP64.  Flags and the n3 maximum as x2_node.
 // nrv holds the reference values nref[f][idx], loaded by the caller ahead of time.
 __device__ __forceinline__ void x2_node_diff(const float (&nrv)[DFT_NALPHA], const float (&dn)[DFT_NALPHA],
                                              float (&dd)[DFT_NALPHA], double &mloc, int &flag) {
@@ -195,12 +223,14 @@ __device__ __forceinline__ void x2_node_diff(const float (&nrv)[DFT_NALPHA], con
     const float inv8pi = (float)(1.0 / (8.0 * 3.14159265358979323846));
     const float inv12pi = (float)(1.0 / (12.0 * 3.14159265358979323846));
     const float inv4pi = (float)(1.0 / (4.0 * 3.14159265358979323846));
-    // 1 / (1 - n3) and its powers, with their differences
-    const float Dr = 1.0f - nr[3], D = Dr - dn[3];
-    const float iDr = rcp_r(Dr), iD = rcp_r(D);
-    const float diD = dn[3] * iD * iDr;
-    const float iD2 = iD * iD, iDr2 = iDr * iDr, diD2 = diD * (iD + iDr);
-    const float iD3 = iD2 * iD, diD3 = diD * (iD2 + iD * iDr + iDr2);
+    // 1 / (1 - n3) and its powers, with their differences (FP64, rounded once to FP32)
+    const double dn3 = (double)dn[3];
+    const double Drd = 1.0 - (double)nr[3], Dd = Drd - dn3;
+    const double iDrd = rcp64(Drd), iDd = rcp64(Dd);
+    const double diDd = dn3 * iDd * iDrd;
+    const float iD = (float)iDd, diD = (float)diDd;
+    const float iD2 = (float)(iDd * iDd), diD2 = (float)(diDd * (iDd + iDrd));
+    const float iD3 = (float)(iDd * iDd * iDd), diD3 = (float)(diDd * (iDd * iDd + iDd * iDrd + iDrd * iDrd));
     // vector products and the xi^2 = nV2.nV2 / n2^2 ratio, clamped at 1
     float dot12r = 0.f, ddot12 = 0.f, dot22 = 0.f, dot22r = 0.f, ddot22 = 0.f;
 #pragma unroll
@@ -228,7 +258,7 @@ __device__ __forceinline__ void x2_node_diff(const float (&nrv)[DFT_NALPHA], con
     const float q3 = q2 * q, q3r = q2r * qr, dq3 = dq * (q2 + q * qr + q2r);
     if (!(x2 < 1.0f)) flag |= 2;
     // d0 = -log(1 - n3) + log(1 - nr3)
-    dd[0] = -log1pf(-dn[3] * iDr);
+    dd[0] = (float)(-log1p64(-dn3 * iDrd));
     // d1 = n2 / D
     dd[1] = dn[2] * iD + nr[2] * diD;
     // d2 = n1 / D + n2^2 q^2 (1 + xi^2) / (8 pi D^2)
@@ -260,7 +290,7 @@ __device__ __forceinline__ void x2_node_diff(const float (&nrv)[DFT_NALPHA], con
         dd[7 + d] = -t1 - t2 * inv4pi;
     }
     if (!isfinite(n3)) flag |= 5;                           // 1: evaluation non-finite, 4: n3 non-finite
-    if (!isfinite(dd[0]) || !isfinite(dd[3]) || !(D > 0.0f)) flag |= 1;
+    if (!isfinite(dd[0]) || !isfinite(dd[3]) || !(Dd > 0.0)) flag |= 1;
     mloc = fmax(mloc, n3);
 }
 

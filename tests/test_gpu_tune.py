@@ -37,7 +37,7 @@ def test_every_shape_gives_the_same_residual(precision):
             sol.set_reference(torch.tensor(p.initial_density(), dtype=torch.float64, device="cuda"))
         g0, r0 = sol.residual(rho)
         g0 = g0.clone()
-        nshape = {"y": 5, "z_plain": 5, "z_weights": 3, "z_back": 3}
+        nshape = {"y": 5, "z_plain": 5, "z_weights": 6, "z_back": 3}
         for ps, nv in nshape.items():
             for v in range(1, nv):
                 for t in (0, 1):
@@ -50,7 +50,7 @@ def test_every_shape_gives_the_same_residual(precision):
                          f"{'identical' if same else 'DIFFERENT'}")
                     assert same, (name, ps, v, t)
         with pytest.raises(RuntimeError):
-            sol.set_schedule({"z_weights": (3, 0)})
+            sol.set_schedule({"z_weights": (6, 0)})
         sol.close()
 
 
@@ -62,7 +62,7 @@ def test_tuned_solve_equals_untuned():
         sched = sol.schedule()
         _say(f"  flags {flags}: schedule {sched}")
         for v in sched.values():
-            assert 0 <= v[0] < 5 and 0 <= v[1] < 5
+            assert 0 <= v[0] < 6 and 0 <= v[1] < 6
         rho = torch.tensor(p.initial_density(), dtype=torch.float64, device="cuda")
         it, r, st = sol.solve(rho, 1e-8, 500)
         assert st == 0
