@@ -109,6 +109,9 @@ def test_validation_errors_without_gpu():
     assert lib.dft_solve(None, None, 1e-8, 10, None, None) == 1
     assert lib.dft_destroy(None) == 0
     assert lib.dft_rfd_reference(None, None, None, 8, None) == 1
+    assert lib.dft_adjoint(None, None, None, None, 0, 1e-10, 10, None, None, None, None, None) == 1
+    assert lib.dft_adjoint_noalloc(None, None, None, 1e-10, 10, None, None, None, None, None) == 1
+    assert lib.dft_last_error()
 
 
 def test_all_supported_axis_lengths_validate():
