@@ -934,7 +934,15 @@ __device__ __forceinline__ cx<T> lane_value(cx<T> v, int src) {
 // In a wave-private tile lane b of a pencil holds e = b + q L/4 (q = 0..3); the elements
 // e > L/2 are conj(A_{L-e}), and L - e is an element that lane (L/4 - b) mod L/4 of the same
 // pencil loads for q = 0 or 1, so they come by cross-lane permutes instead of second loads.
-template <typename T, int L, class F>
+// Paired x tiles (k_x2p): two waves share each row pair, so the pencil slot p of a wave-private
+// tile (ppw = 256 / L slots per wave) maps to row pair (p / (2 ppw)) ppw + p % ppw of the block.
+template <int L>
+__device__ __forceinline__ int paired_pair(int p) {
+    constexpr int ppw = 256 / L;
+    return (p / (2 * ppw)) * ppw + p % ppw;
+}
+
+template <typename T, int L, class F, bool PAIRED = false>
 __device__ __forceinline__ void load_row_pairs(const cx<T> *in, long long pair0, int Pact, long long rows, cx<T> *c) {
     constexpr int KX = L / 2 + 1;
     if constexpr (F::WP) {
@@ -942,6 +950,7 @@ __device__ __forceinline__ void load_row_pairs(const cx<T> *in, long long pair0,
         static_assert(F::template nin<1>() == 4, "one radix-4 butterfly per thread");
         int p, b;
         F::template in_pos<1>(0, p, b);
+        if constexpr (PAIRED) p = paired_pair<L>(p);
         const bool ok = p < Pact;
         const long long r0 = 2 * (pair0 + p);
         const bool okb = ok && r0 + 1 < rows;
@@ -977,6 +986,7 @@ __device__ __forceinline__ void load_row_pairs(const cx<T> *in, long long pair0,
         c[2] = mk<T>(A2.x - B2.y, A2.y + B2.x);
         c[3] = mk<T>(A3.x - B3.y, A3.y + B3.x);
     } else {
+        static_assert(!PAIRED, "paired tiles are wave-private");
 #pragma unroll
         for (int i = 0; i < F::template nin<1>(); ++i) {
             int p, e;
@@ -999,7 +1009,7 @@ __device__ __forceinline__ void load_row_pairs(const cx<T> *in, long long pair0,
 // wave-private tile each wave splits its own pencils (lanes along k); otherwise the block does
 // (split must have been synchronized accordingly by the caller).
 // With dkx > 0 both half spectra are multiplied by i k_x (k_x = k dkx, zero on the Nyquist column).
-template <typename T, int L, class F>
+template <typename T, int L, class F, bool PAIRED = false>
 __device__ __forceinline__ void split_rows(const cx<T> *split, cx<T> *out, long long pair0, int Pact, long long rows,
                                            T dkx = T(0)) {
     constexpr int KX = L / 2 + 1;
@@ -1014,10 +1024,10 @@ __device__ __forceinline__ void split_rows(const cx<T> *split, cx<T> *out, long 
             B = mk<T>(-kx * B.y, kx * B.x);
         }
     };
-    auto one = [&](int p, int k) {
+    auto one = [&](int p, int pr, int k) {
         cx<T> A, B;
         coeffs(p, k, A, B);
-        const long long r0 = 2 * (pair0 + p);
+        const long long r0 = 2 * (pair0 + pr);
         ct::gst(out + r0 * KX + k, A);
         if (r0 + 1 < rows) ct::gst(out + (r0 + 1) * KX + k, B);
     };
@@ -1027,21 +1037,23 @@ __device__ __forceinline__ void split_rows(const cx<T> *split, cx<T> *out, long 
         constexpr int nb = L / 4;
         const int lane = (int)threadIdx.x % 64;
         const int p = ((int)threadIdx.x / 64) * (64 / nb) + lane / nb;
+        const int pr = PAIRED ? paired_pair<L>(p) : p;
         const int b = lane % nb;
-        if (p < Pact) {
-            one(p, b);
-            one(p, b + nb);
+        if (pr < Pact) {
+            one(p, pr, b);
+            one(p, pr, b + nb);
             if (b < 2) {
                 cx<T> A, B;
                 coeffs(p, 2 * nb, A, B);
-                const long long r = 2 * (pair0 + p) + b;
+                const long long r = 2 * (pair0 + pr) + b;
                 if (r < rows) ct::gst(out + r * KX + 2 * nb, b == 0 ? A : B);
             }
         }
     } else {
+        static_assert(!PAIRED, "paired tiles are wave-private");
         for (int j = threadIdx.x; j < Pact * KX; j += (int)blockDim.x) {
             const int p = j / KX;
-            one(p, j - p * KX);
+            one(p, p, j - p * KX);
         }
     }
 }
@@ -1204,6 +1216,170 @@ k_x2c(Geo g_in, X2Args a) {
         // compact layout: the x components of the vector derivatives leave multiplied by i k_x
         const T dkx = (g.compact && (f == 4 || f == 7)) ? T(g.cs->dk[0]) : T(0);
         split_rows<T, L, F>(split, reinterpret_cast<cx<T> *>(a.specB) + (long long)f * NC, pair0, Pact, rows, dkx);
+    }
+}
+
+// X2 in FP32 differences from the reference (x2_node_diff) on wave-private tiles, with the ten
+// fields of every row pair shared by two waves of the block.  Wave h of a pair transforms five
+// fields, x2_half_field(h, 0..4) (h = 0: n0..n3 and nV2,x, so the compact layout forms
+// nV2,x = -i k_x n3 in the same wave; h = 1: the nV1 components and nV2,y, nV2,z), and does the
+// nodewise work at the nodes of its registers q = 2h, 2h + 1; the other five values of those nodes
+// come from the partner wave through LDS, and their derivatives go back the same way.  Half the
+// fields per wave halves the registers the transforms hold, so three waves fit per SIMD where
+// k_x2c<float, L, X2N_D32> fits two, for the same arithmetic in the same order.
+template <int L>
+struct XPairTile {
+    static constexpr int PF = 1024 / L;   // pencil slots of a block (four waves)
+    static constexpr int NTB = 256;
+    static constexpr int PB = PF / 2;     // row pairs of a block
+};
+
+__host__ __device__ constexpr int x2_half_field(int h, int j) {
+    return h == 0 ? (j < 4 ? j : 7) : (j < 3 ? 4 + j : 5 + j);
+}
+
+// Nodewise work of one paired wave (H: its half) with the swap through LDS: the own fields at the
+// partner's registers go out to the own slots; after a barrier the wave takes the partner's fields
+// at its own registers q = 2H + k from the partner's slots, one register at a time, and leaves the
+// partner's derivatives in the same place; after a second barrier it reads its own derivatives at
+// the partner's registers back.  Between the barriers only the partner touches a wave's slots.
+// Every wave of the block passes both barriers.
+template <int L, class F, int H>
+__device__ __forceinline__ void x2p_swap_and_nodes(const X2Args &a, long long N, long long pair0, int Pact,
+                                                   long long rows, cx<float> (*xch)[5][2][64], int wave, int lane,
+                                                   cx<float> (&vals)[5][4], double &mloc, int &flag) {
+    constexpr int QP = 2 * (1 - H);   // the partner's registers
+#pragma unroll
+    for (int j = 0; j < 5; ++j)
+#pragma unroll
+        for (int k = 0; k < 2; ++k) xch[wave][j][k][lane] = vals[j][QP + k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const int i = 2 * H + k;
+        int p, e;
+        F::template out_pos<1>(i, p, e);
+        const int pr = paired_pair<L>(p);
+        const long long r0 = 2 * (pair0 + pr);
+        cx<float> oth[5];
+#pragma unroll
+        for (int j = 0; j < 5; ++j) oth[j] = xch[wave ^ 1][j][k][lane];
+#pragma unroll
+        for (int hr = 0; hr < 2; ++hr) {
+            const bool ok = pr < Pact && r0 + hr < rows;
+            float nr[DFT_NALPHA], dn[DFT_NALPHA], dd[DFT_NALPHA];
+            const long long idx = (r0 + hr) * L + e;
+#pragma unroll
+            for (int f = 0; f < DFT_NALPHA; ++f) nr[f] = ok ? ct::gld(a.nref + f * N + idx) : 0.0f;
+#pragma unroll
+            for (int j = 0; j < 5; ++j) {
+                dn[x2_half_field(H, j)] = hr == 0 ? vals[j][i].x : vals[j][i].y;
+                dn[x2_half_field(1 - H, j)] = hr == 0 ? oth[j].x : oth[j].y;
+            }
+            if (ok) x2_node_diff(nr, dn, dd, mloc, flag);
+            else
+#pragma unroll
+                for (int f = 0; f < DFT_NALPHA; ++f) dd[f] = 0.0f;   // pairs past Pact and the missing partner row
+#pragma unroll
+            for (int j = 0; j < 5; ++j) {
+                if (hr == 0) {
+                    vals[j][i].x = dd[x2_half_field(H, j)];
+                    oth[j].x = dd[x2_half_field(1 - H, j)];
+                } else {
+                    vals[j][i].y = dd[x2_half_field(H, j)];
+                    oth[j].y = dd[x2_half_field(1 - H, j)];
+                }
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 5; ++j) xch[wave ^ 1][j][k][lane] = oth[j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 5; ++j)
+#pragma unroll
+        for (int k = 0; k < 2; ++k) vals[j][QP + k] = xch[wave][j][k][lane];
+}
+
+template <int L>
+__global__ __launch_bounds__(XPairTile<L>::NTB) __attribute__((amdgpu_waves_per_eu(3))) void
+k_x2p(Geo g_in, X2Args a) {
+    using T = float;
+    using XP = XPairTile<L>;
+    constexpr int PF = XP::PF, NTB = XP::NTB, PB = XP::PB;
+    using F = ct::Fft<T, typename ct::XPlan<L>::type, PF, NTB, true, 2, 0>;
+    static_assert(F::WP, "paired tiles are wave-private");
+    static_assert(F::template nout<1>() == 4 && F::template nin<-1>() == 4, "one radix-4 butterfly per thread");
+    const int prob = (int)blockIdx.z;
+    if (prob > 0) {
+        const long long o = (long long)prob * g_in.pstride;
+        g_in = shift(g_in, o);
+        a = shift(a, o);
+    }
+    const Geo &g = g_in;
+    if (gated_off(a.gate)) return;
+    __shared__ cx<T> lds[F::LDS_ELEMS + F::TILE];
+    __shared__ cx<T> xch[NTB / 64][5][2][64];   // each wave's values for its partner
+    cx<T> *split = lds + F::LDS_ELEMS;
+    const long long N = g.N, NC = g.NC;
+    const long long rows = (long long)g.ny * g.nz;
+    const long long npairs = (rows + 1) / 2;
+    const long long pair0 = (long long)blockIdx.x * PB;
+    const int Pact = (int)min((long long)PB, npairs - pair0);
+    const cx<T> *tw = twp<T>(g, 0);
+    typename F::Twiddles trw;
+    F::load_twiddles(trw, tw);
+    const int wave = (int)threadIdx.x / 64, lane = (int)threadIdx.x % 64, h = wave & 1;
+    cx<T> vals[5][4];
+    cx<T> v[F::V];
+    int ph = 0;
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+        const int f = x2_half_field(h, j);
+        if (f == 7 && g.compact) {
+            // compact layout: n_V2,x = -i k_x n3 (k_x zero on the Nyquist column), from field 3 (j = 3)
+            const T dkx = T(g.cs->dk[0]);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                int p, e;
+                F::template in_pos<1>(i, p, e);
+                const T kx = (L % 2 == 0 && 2 * e == L) ? T(0) : T(e <= L / 2 ? e : e - L) * dkx;
+                vals[j][i] = mk<T>(kx * vals[3][i].y, -kx * vals[3][i].x);
+            }
+            continue;
+        }
+        load_row_pairs<T, L, F, true>(reinterpret_cast<const cx<T> *>(a.specB) + (long long)f * NC, pair0, Pact, rows,
+                                      vals[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) v[i] = vals[j][i];
+        F::template run<1>(v, lds, ph, trw);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) vals[j][i] = v[i];
+    }
+    double mloc = -INFINITY;
+    int flag = 0;
+    // the halves take constant register indices (a run-time choice would put vals in scratch)
+    if (h == 0) x2p_swap_and_nodes<L, F, 0>(a, N, pair0, Pact, rows, xch, wave, lane, vals, mloc, flag);
+    else x2p_swap_and_nodes<L, F, 1>(a, N, pair0, Pact, rows, xch, wave, lane, vals, mloc, flag);
+    if (flag & 4) mloc = INFINITY;   // the n3 bound needs finite n3 only
+    block_reduce_nt<true, NTB>(mloc, flag, a.red.mpart + blockIdx.x, a.red.mflag + blockIdx.x);
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) v[i] = vals[j][i];
+        F::template run<-1>(v, lds, ph, trw);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            int p, e;
+            if (F::template out_pos<-1>(i, p, e)) split[F::lidx(p, e)] = v[i];
+        }
+        F::sync();
+        const int f = x2_half_field(h, j);
+        const T dkx = (g.compact && (f == 4 || f == 7)) ? T(g.cs->dk[0]) : T(0);
+        split_rows<T, L, F, true>(split, reinterpret_cast<cx<T> *>(a.specB) + (long long)f * NC, pair0, Pact, rows, dkx);
     }
 }
 

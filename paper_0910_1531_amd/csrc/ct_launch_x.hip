@@ -3,8 +3,13 @@
 
 namespace dft {
 
+// Lengths whose FP32-difference x2 runs the paired-wave kernel k_x2p (wave-private tiles).
+template <int L>
+constexpr bool x2_paired() { return L == 16 || L == 64 || L == 256; }
+
+// Launches the pass; returns the number of blocks (each writes one n3-maximum partial).
 template <typename T, int L>
-static void launch_x2c_len(const Geo &g, const X2Args &a, hipStream_t s) {
+static int launch_x2c_len(const Geo &g, const X2Args &a, hipStream_t s) {
     const long long npairs = ((long long)g.ny * g.nz + 1) / 2;
     const long long nb = ct_cdiv(npairs, XTile<L>::PB);
     if (nb > a.red.cap) throw std::runtime_error("x2: reduction buffer too small");
@@ -12,18 +17,28 @@ static void launch_x2c_len(const Geo &g, const X2Args &a, hipStream_t s) {
     if (a.hs != DFT_HS_RSLT && a.mode != X2_N3_ONLY) {
         // other functionals: FP64 nodewise work, kernels of their own (launch_x2_alt_ct)
         if (!launch_x2_alt_ct<T>(g, a, s)) throw std::runtime_error("x2: no kernel for this functional");
-        return;
+        return (int)nb;
     }
-    bool done = false;
     if constexpr (std::is_same<T, float>::value) {
         // FP32 differences from the reference with no FP64 copies requested: FP32 nodewise work
         if (a.mode == X2_FULL && a.nref && !a.n_out && !a.dphi_out && !a.nref_out) {
-            hipLaunchKernelGGL((k_x2c<T, L, X2N_D32>), grid, dim3(XTile<L>::NTB), 0, s, g, a);
-            done = true;
+            if constexpr (x2_paired<L>()) {
+                const long long nbp = ct_cdiv(npairs, XPairTile<L>::PB);
+                if (nbp > a.red.cap) throw std::runtime_error("x2: reduction buffer too small");
+                hipLaunchKernelGGL((k_x2p<L>), dim3((unsigned)nbp, 1, (unsigned)g.nprob), dim3(XPairTile<L>::NTB), 0, s,
+                                   g, a);
+                ct_check("x2 paired (compiled length)");
+                return (int)nbp;
+            } else {
+                hipLaunchKernelGGL((k_x2c<T, L, X2N_D32>), grid, dim3(XTile<L>::NTB), 0, s, g, a);
+                ct_check("x2 (compiled length)");
+                return (int)nb;
+            }
         }
     }
-    if (!done) hipLaunchKernelGGL((k_x2c<T, L, X2N_FP64>), grid, dim3(XTile<L>::NTB), 0, s, g, a);
+    hipLaunchKernelGGL((k_x2c<T, L, X2N_FP64>), grid, dim3(XTile<L>::NTB), 0, s, g, a);
     ct_check("x2 (compiled length)");
+    return (int)nb;
 }
 
 template <typename T, int L>
@@ -45,12 +60,12 @@ static void launch_x3c_len(const Geo &g, const X3Args &a, hipStream_t s) {
 }
 
 template <typename T>
-bool launch_x2_ct(const Geo &g, const X2Args &a, hipStream_t s) {
+int launch_x2_ct(const Geo &g, const X2Args &a, hipStream_t s) {
     switch (g.nx) {
-#define DFT_CASE(n) case n: launch_x2c_len<T, n>(g, a, s); return true;
+#define DFT_CASE(n) case n: return launch_x2c_len<T, n>(g, a, s);
         DFT_CT_LENGTHS(DFT_CASE)
 #undef DFT_CASE
-        default: return false;
+        default: return 0;
     }
 }
 
@@ -84,10 +99,21 @@ int x_ct_pairs(int nx) {
     }
 }
 
+// Fewest row pairs per block of any compiled-length x2 kernel of the length (paired tiles hold
+// half as many as the others): bounds the number of n3-maximum partials.
+int x2_ct_min_pairs(int nx) {
+    switch (nx) {
+#define DFT_CASE(n) case n: return x2_paired<n>() ? XPairTile<n>::PB : XTile<n>::PB;
+        DFT_CT_LENGTHS(DFT_CASE)
+#undef DFT_CASE
+        default: return 0;
+    }
+}
+
 template bool launch_x1_ct<double>(const Geo &, const XFwdArgs &, hipStream_t);
 template bool launch_x1_ct<float>(const Geo &, const XFwdArgs &, hipStream_t);
-template bool launch_x2_ct<double>(const Geo &, const X2Args &, hipStream_t);
-template bool launch_x2_ct<float>(const Geo &, const X2Args &, hipStream_t);
+template int launch_x2_ct<double>(const Geo &, const X2Args &, hipStream_t);
+template int launch_x2_ct<float>(const Geo &, const X2Args &, hipStream_t);
 template bool launch_x3_ct<double>(const Geo &, const X3Args &, hipStream_t);
 template bool launch_x3_ct<float>(const Geo &, const X3Args &, hipStream_t);
 

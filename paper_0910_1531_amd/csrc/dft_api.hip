@@ -191,7 +191,7 @@ void enqueue_eval_t(dft_ctx *c, const Eval &ev, hipStream_t s) {
     x2.dphi_out = ev.dphi_out;
     x2.red = c->red;
     x2.gate = ev.gate;
-    launch_x2<T>(g, x2, s);
+    const int nb2 = launch_x2<T>(g, x2, s);
     mark(ev, 5, s);
     YArgs yc{c->specB, DFT_NALPHA, -1, ev.gate};
     yc.vec = g.compact ? 2 : 0;
@@ -221,7 +221,7 @@ void enqueue_eval_t(dft_ctx *c, const Eval &ev, hipStream_t s) {
     x3.gate = ev.gate;
     launch_x3<T>(g, x3, s);
     mark(ev, 9, s);
-    launch_finalize(c->red, x3_nparts<T>(g), x2_nblocks<T>(g), ev.fslot, ev.mslot, c->st,
+    launch_finalize(c->red, x3_nparts<T>(g), nb2, ev.fslot, ev.mslot, c->st,
                     ev.count_kind, ev.gate, s, g.nprob, g.pstride);
     mark(ev, 10, s);
 }
@@ -260,8 +260,8 @@ void enqueue_n3_t(dft_ctx *c, const double *alpha, double *mslot, const int *gat
     x2.nref = diff ? c->nref : nullptr;
     x2.red = c->red;
     x2.gate = gate;
-    launch_x2<T>(g, x2, s);
-    launch_finalize(c->red, 0, x2_nblocks<T>(g), nullptr, mslot, c->st, 2, gate, s, g.nprob, g.pstride);
+    const int nb2 = launch_x2<T>(g, x2, s);
+    launch_finalize(c->red, 0, nb2, nullptr, mslot, c->st, 2, gate, s, g.nprob, g.pstride);
 }
 
 void enqueue_step(dft_ctx *c, hipStream_t s) {

@@ -151,11 +151,12 @@ template <typename T> void launch_y(const Geo &g, const YArgs &a, hipStream_t s)
 template <typename T> bool launch_y_ct(const Geo &g, const YArgs &a, hipStream_t s);
 template <typename T> bool launch_z1_ct(const Geo &g, const Z1Args &a, int es, hipStream_t s);
 template <typename T> bool launch_z2_ct(const Geo &g, const Z2Args &a, hipStream_t s);
-template <typename T> bool launch_x2_ct(const Geo &g, const X2Args &a, hipStream_t s);
+template <typename T> int launch_x2_ct(const Geo &g, const X2Args &a, hipStream_t s);   // blocks, 0: none
 template <typename T> bool launch_x2_alt_ct(const Geo &g, const X2Args &a, hipStream_t s);
 template <typename T> bool launch_x1_ct(const Geo &g, const XFwdArgs &a, hipStream_t s);
 template <typename T> bool launch_x3_ct(const Geo &g, const X3Args &a, hipStream_t s);
-int x_ct_pairs(int nx);   // row pairs per block of the compiled-length x kernels, 0 if none
+int x_ct_pairs(int nx);        // row pairs per block of the compiled-length x kernels, 0 if none
+int x2_ct_min_pairs(int nx);   // fewest row pairs per block of the length's x2 kernels, 0 if none
 int y_ct_variants(int L, bool fp32);   // launch shapes of the y kernels of length L (0: none)
 int z_ct_variants(int L);              // launch shapes of the z kernels of length L (0: none)
 int z1_ct_variants(int L);             // launch shapes of the Z1 pass (fused and split)
@@ -165,12 +166,12 @@ int spec_table_rows(int nz, int S, int es);
 void launch_spec_tables(const Geo &g, hipStream_t s);
 template <typename T> void launch_z1(const Geo &g, const Z1Args &a, hipStream_t s);
 template <typename T> void launch_z2(const Geo &g, const Z2Args &a, hipStream_t s);
-template <typename T> void launch_x2(const Geo &g, const X2Args &a, hipStream_t s);
+template <typename T> int launch_x2(const Geo &g, const X2Args &a, hipStream_t s);   // returns the blocks
 template <typename T> void launch_x3(const Geo &g, const X3Args &a, hipStream_t s);
 
 // Number of blocks the reductions of X2 / X3 produce (sizes the partial arrays).
 int x2_blocks(const Geo &g);
-template <typename T> int x2_nblocks(const Geo &g);   // partials written by launch_x2<T>
+template <typename T> int x2_nblocks(const Geo &g);   // most partials a launch_x2<T> can write
 int x3_blocks(const Geo &g);
 template <typename T> int x3_nparts(const Geo &g);   // partials written by launch_x3<T> (all species)
 

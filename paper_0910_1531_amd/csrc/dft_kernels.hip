@@ -909,7 +909,7 @@ static bool x2b_geometry(const Geo &g, int *ntb, int *pb) {
 template <typename T>
 int x2_nblocks(const Geo &g) {
     const long long npairs = ((long long)g.ny * g.nz + 1) / 2;
-    if (const int pb = x_ct_pairs(g.nx)) return (int)ceil_div(npairs, pb);
+    if (const int pb = x2_ct_min_pairs(g.nx)) return (int)ceil_div(npairs, pb);
     int ntb, pb;
     if (x2b_geometry<T>(g, &ntb, &pb)) return (int)ceil_div(npairs, pb);
     const int P = x_pairs<T, Cfg<T>::X2E>(g);
@@ -917,8 +917,8 @@ int x2_nblocks(const Geo &g) {
 }
 
 template <typename T>
-void launch_x2(const Geo &g, const X2Args &a, hipStream_t s) {
-    if (launch_x2_ct<T>(g, a, s)) return;
+int launch_x2(const Geo &g, const X2Args &a, hipStream_t s) {
+    if (const int nb = launch_x2_ct<T>(g, a, s)) return nb;
     if (g.compact) throw std::runtime_error("x2: compact vector layout without a compiled-length kernel");
     const long long npairs = ((long long)g.ny * g.nz + 1) / 2;
     int ntb, pb;
@@ -933,7 +933,7 @@ void launch_x2(const Geo &g, const X2Args &a, hipStream_t s) {
             hipLaunchKernelGGL((k_x2b<T, 512, kX2bE>), dim3((unsigned)nb, 1, (unsigned)g.nprob), dim3(512), sh, s, g, a,
                                pb);
         check_launch("x2b");
-        return;
+        return (int)nb;
     }
     if (a.mode == X2_HESS) throw std::runtime_error("x2: Hessian mode needs the batched kernel (n_x <= 384)");
     constexpr int E = Cfg<T>::X2E;
@@ -943,6 +943,7 @@ void launch_x2(const Geo &g, const X2Args &a, hipStream_t s) {
     const size_t sh = (size_t)P * g.nx * sizeof(cx<T>);
     hipLaunchKernelGGL((k_x2<T, E>), dim3((unsigned)nb, 1, (unsigned)g.nprob), dim3(NT), sh, s, g, a, P);
     check_launch("x2");
+    return (int)nb;
 }
 
 template int x2_nblocks<double>(const Geo &);
@@ -972,8 +973,8 @@ template void launch_z1<double>(const Geo &, const Z1Args &, hipStream_t);
 template void launch_z1<float>(const Geo &, const Z1Args &, hipStream_t);
 template void launch_z2<double>(const Geo &, const Z2Args &, hipStream_t);
 template void launch_z2<float>(const Geo &, const Z2Args &, hipStream_t);
-template void launch_x2<double>(const Geo &, const X2Args &, hipStream_t);
-template void launch_x2<float>(const Geo &, const X2Args &, hipStream_t);
+template int launch_x2<double>(const Geo &, const X2Args &, hipStream_t);
+template int launch_x2<float>(const Geo &, const X2Args &, hipStream_t);
 template void launch_x3<double>(const Geo &, const X3Args &, hipStream_t);
 template void launch_x3<float>(const Geo &, const X3Args &, hipStream_t);
 
