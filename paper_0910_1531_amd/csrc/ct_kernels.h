@@ -1219,40 +1219,54 @@ k_x2c(Geo g_in, X2Args a) {
     }
 }
 
-// X2 in FP32 differences from the reference (x2_node_diff) on wave-private tiles, with the ten
-// fields of every row pair shared by two waves of the block.  Wave h of a pair transforms five
-// fields, x2_half_field(h, 0..4) (h = 0: n0..n3 and nV2,x, so the compact layout forms
-// nV2,x = -i k_x n3 in the same wave; h = 1: the nV1 components and nV2,y, nV2,z), and does the
-// nodewise work at the nodes of its registers q = 2h, 2h + 1; the other five values of those nodes
-// come from the partner wave through LDS, and their derivatives go back the same way.  Half the
-// fields per wave halves the registers the transforms hold, so three waves fit per SIMD where
-// k_x2c<float, L, X2N_D32> fits two, for the same arithmetic in the same order.
-template <int L>
+// X2 on wave-private tiles with the ten fields of every row pair shared by two waves of the
+// block.  Wave h of a pair transforms five fields, x2_half_field(h, 0..4) (h = 0: n0..n3 and
+// nV2,x, so the compact layout forms nV2,x = -i k_x n3 in the same wave; h = 1: the nV1
+// components and nV2,y, nV2,z), and does the nodewise work at the nodes of its registers
+// q = 2h, 2h + 1; the other five values of those nodes come from the partner wave through LDS,
+// and their derivatives go back the same way.  Half the fields per wave halves the registers the
+// transforms hold (FP32: three waves fit per SIMD where k_x2c fits two; FP64: two without the
+// spills of k_x2c), for the same arithmetic in the same order.  Nodewise work: FP32, the
+// difference from the reference (x2_node_diff, FP32-mixed evaluations); FP64, x2_node with
+// eq. (Phi), every mode but the n3-only one.
+template <typename T, int L>
 struct XPairTile {
     static constexpr int PF = 1024 / L;   // pencil slots of a block (four waves)
     static constexpr int NTB = 256;
     static constexpr int PB = PF / 2;     // row pairs of a block
+    static constexpr int WPE = sizeof(T) == 4 ? 3 : 2;   // waves per SIMD the registers allow
 };
 
 __host__ __device__ constexpr int x2_half_field(int h, int j) {
     return h == 0 ? (j < 4 ? j : 7) : (j < 3 ? 4 + j : 5 + j);
 }
 
+// Exchange slot s (0..639: field j, register k, lane as (2 j + k) 64 + lane) of wave w in the
+// wave's own LDS regions of the transform tile: pencils w 256/L.. of the two transform buffers
+// and of the split buffer, 256 elements each (whole pencils of a wave-private tile).
+template <class F, typename T>
+__device__ __forceinline__ cx<T> *x2p_slot(cx<T> *lds, int w, int s) {
+    static_assert(F::TILE == 1024 && F::LDS_ELEMS == 2 * F::TILE, "four waves of 256 elements per buffer");
+    return lds + (s >> 8) * F::TILE + w * 256 + (s & 255);
+}
+
 // Nodewise work of one paired wave (H: its half) with the swap through LDS: the own fields at the
 // partner's registers go out to the own slots; after a barrier the wave takes the partner's fields
 // at its own registers q = 2H + k from the partner's slots, one register at a time, and leaves the
 // partner's derivatives in the same place; after a second barrier it reads its own derivatives at
-// the partner's registers back.  Between the barriers only the partner touches a wave's slots.
-// Every wave of the block passes both barriers.
-template <int L, class F, int H>
+// the partner's registers back.  Between the barriers only the partner touches a wave's slots;
+// outside them the slots are the wave's own transform regions.  Every wave of the block passes
+// both barriers.
+template <typename T, int L, class F, int H>
 __device__ __forceinline__ void x2p_swap_and_nodes(const X2Args &a, long long N, long long pair0, int Pact,
-                                                   long long rows, cx<float> (*xch)[5][2][64], int wave, int lane,
-                                                   cx<float> (&vals)[5][4], double &mloc, int &flag) {
+                                                   long long rows, cx<T> *lds, int wave, int lane,
+                                                   cx<T> (&vals)[5][4], double &mloc, int &flag) {
     constexpr int QP = 2 * (1 - H);   // the partner's registers
+    F::sync();   // the forward transforms' reads of the same regions precede the writes below
 #pragma unroll
     for (int j = 0; j < 5; ++j)
 #pragma unroll
-        for (int k = 0; k < 2; ++k) xch[wave][j][k][lane] = vals[j][QP + k];
+        for (int k = 0; k < 2; ++k) *x2p_slot<F>(lds, wave, (2 * j + k) * 64 + lane) = vals[j][QP + k];
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
@@ -1261,25 +1275,32 @@ __device__ __forceinline__ void x2p_swap_and_nodes(const X2Args &a, long long N,
         F::template out_pos<1>(i, p, e);
         const int pr = paired_pair<L>(p);
         const long long r0 = 2 * (pair0 + pr);
-        cx<float> oth[5];
+        cx<T> oth[5];
 #pragma unroll
-        for (int j = 0; j < 5; ++j) oth[j] = xch[wave ^ 1][j][k][lane];
+        for (int j = 0; j < 5; ++j) oth[j] = *x2p_slot<F>(lds, wave ^ 1, (2 * j + k) * 64 + lane);
 #pragma unroll
         for (int hr = 0; hr < 2; ++hr) {
             const bool ok = pr < Pact && r0 + hr < rows;
-            float nr[DFT_NALPHA], dn[DFT_NALPHA], dd[DFT_NALPHA];
             const long long idx = (r0 + hr) * L + e;
-#pragma unroll
-            for (int f = 0; f < DFT_NALPHA; ++f) nr[f] = ok ? ct::gld(a.nref + f * N + idx) : 0.0f;
+            T dn[DFT_NALPHA], dd[DFT_NALPHA];
 #pragma unroll
             for (int j = 0; j < 5; ++j) {
                 dn[x2_half_field(H, j)] = hr == 0 ? vals[j][i].x : vals[j][i].y;
                 dn[x2_half_field(1 - H, j)] = hr == 0 ? oth[j].x : oth[j].y;
             }
-            if (ok) x2_node_diff(nr, dn, dd, mloc, flag);
-            else
+            if (ok) {
+                if constexpr (sizeof(T) == 4) {
+                    float nr[DFT_NALPHA];
 #pragma unroll
-                for (int f = 0; f < DFT_NALPHA; ++f) dd[f] = 0.0f;   // pairs past Pact and the missing partner row
+                    for (int f = 0; f < DFT_NALPHA; ++f) nr[f] = ct::gld(a.nref + f * N + idx);
+                    x2_node_diff(nr, dn, dd, mloc, flag);
+                } else {
+                    x2_node<false>(a, N, idx, dn, dd, mloc, flag);
+                }
+            } else {
+#pragma unroll
+                for (int f = 0; f < DFT_NALPHA; ++f) dd[f] = T(0);   // pairs past Pact, the missing partner row
+            }
 #pragma unroll
             for (int j = 0; j < 5; ++j) {
                 if (hr == 0) {
@@ -1292,23 +1313,24 @@ __device__ __forceinline__ void x2p_swap_and_nodes(const X2Args &a, long long N,
             }
         }
 #pragma unroll
-        for (int j = 0; j < 5; ++j) xch[wave ^ 1][j][k][lane] = oth[j];
+        for (int j = 0; j < 5; ++j) *x2p_slot<F>(lds, wave ^ 1, (2 * j + k) * 64 + lane) = oth[j];
     }
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < 5; ++j)
 #pragma unroll
-        for (int k = 0; k < 2; ++k) vals[j][QP + k] = xch[wave][j][k][lane];
+        for (int k = 0; k < 2; ++k) vals[j][QP + k] = *x2p_slot<F>(lds, wave, (2 * j + k) * 64 + lane);
+    F::sync();   // the reads above precede the inverse transforms' writes to the same regions
 }
 
-template <int L>
-__global__ __launch_bounds__(XPairTile<L>::NTB) __attribute__((amdgpu_waves_per_eu(3))) void
+template <typename T, int L>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(XPairTile<T, L>::WPE))) void
 k_x2p(Geo g_in, X2Args a) {
-    using T = float;
-    using XP = XPairTile<L>;
+    using XP = XPairTile<T, L>;
     constexpr int PF = XP::PF, NTB = XP::NTB, PB = XP::PB;
     using F = ct::Fft<T, typename ct::XPlan<L>::type, PF, NTB, true, 2, 0>;
     static_assert(F::WP, "paired tiles are wave-private");
+    static_assert(NTB == 256, "the launch bound above");
     static_assert(F::template nout<1>() == 4 && F::template nin<-1>() == 4, "one radix-4 butterfly per thread");
     const int prob = (int)blockIdx.z;
     if (prob > 0) {
@@ -1319,7 +1341,6 @@ k_x2p(Geo g_in, X2Args a) {
     const Geo &g = g_in;
     if (gated_off(a.gate)) return;
     __shared__ cx<T> lds[F::LDS_ELEMS + F::TILE];
-    __shared__ cx<T> xch[NTB / 64][5][2][64];   // each wave's values for its partner
     cx<T> *split = lds + F::LDS_ELEMS;
     const long long N = g.N, NC = g.NC;
     const long long rows = (long long)g.ny * g.nz;
@@ -1362,8 +1383,8 @@ k_x2p(Geo g_in, X2Args a) {
     double mloc = -INFINITY;
     int flag = 0;
     // the halves take constant register indices (a run-time choice would put vals in scratch)
-    if (h == 0) x2p_swap_and_nodes<L, F, 0>(a, N, pair0, Pact, rows, xch, wave, lane, vals, mloc, flag);
-    else x2p_swap_and_nodes<L, F, 1>(a, N, pair0, Pact, rows, xch, wave, lane, vals, mloc, flag);
+    if (h == 0) x2p_swap_and_nodes<T, L, F, 0>(a, N, pair0, Pact, rows, lds, wave, lane, vals, mloc, flag);
+    else x2p_swap_and_nodes<T, L, F, 1>(a, N, pair0, Pact, rows, lds, wave, lane, vals, mloc, flag);
     if (flag & 4) mloc = INFINITY;   // the n3 bound needs finite n3 only
     block_reduce_nt<true, NTB>(mloc, flag, a.red.mpart + blockIdx.x, a.red.mflag + blockIdx.x);
 #pragma unroll

@@ -3,7 +3,8 @@
 
 namespace dft {
 
-// Lengths whose FP32-difference x2 runs the paired-wave kernel k_x2p (wave-private tiles).
+// Lengths whose x2 runs the paired-wave kernel k_x2p (wave-private tiles of four values per thread):
+// FP32 differences from the reference without FP64 copies, and FP64 in every mode but the n3-only.
 template <int L>
 constexpr bool x2_paired() { return L == 16 || L == 64 || L == 256; }
 
@@ -19,21 +20,23 @@ static int launch_x2c_len(const Geo &g, const X2Args &a, hipStream_t s) {
         if (!launch_x2_alt_ct<T>(g, a, s)) throw std::runtime_error("x2: no kernel for this functional");
         return (int)nb;
     }
-    if constexpr (std::is_same<T, float>::value) {
-        // FP32 differences from the reference with no FP64 copies requested: FP32 nodewise work
-        if (a.mode == X2_FULL && a.nref && !a.n_out && !a.dphi_out && !a.nref_out) {
-            if constexpr (x2_paired<L>()) {
-                const long long nbp = ct_cdiv(npairs, XPairTile<L>::PB);
-                if (nbp > a.red.cap) throw std::runtime_error("x2: reduction buffer too small");
-                hipLaunchKernelGGL((k_x2p<L>), dim3((unsigned)nbp, 1, (unsigned)g.nprob), dim3(XPairTile<L>::NTB), 0, s,
-                                   g, a);
-                ct_check("x2 paired (compiled length)");
-                return (int)nbp;
-            } else {
-                hipLaunchKernelGGL((k_x2c<T, L, X2N_D32>), grid, dim3(XTile<L>::NTB), 0, s, g, a);
-                ct_check("x2 (compiled length)");
-                return (int)nb;
-            }
+    constexpr bool fp32 = std::is_same<T, float>::value;
+    // FP32: differences from the reference with no FP64 copies requested (FP32 nodewise work)
+    const bool d32 = fp32 && a.mode == X2_FULL && a.nref && !a.n_out && !a.dphi_out && !a.nref_out;
+    if constexpr (x2_paired<L>()) {
+        if (fp32 ? d32 : a.mode != X2_N3_ONLY) {
+            const long long nbp = ct_cdiv(npairs, XPairTile<T, L>::PB);
+            if (nbp > a.red.cap) throw std::runtime_error("x2: reduction buffer too small");
+            hipLaunchKernelGGL((k_x2p<T, L>), dim3((unsigned)nbp, 1, (unsigned)g.nprob), dim3(XPairTile<T, L>::NTB), 0,
+                               s, g, a);
+            ct_check("x2 paired (compiled length)");
+            return (int)nbp;
+        }
+    } else if constexpr (fp32) {
+        if (d32) {
+            hipLaunchKernelGGL((k_x2c<T, L, X2N_D32>), grid, dim3(XTile<L>::NTB), 0, s, g, a);
+            ct_check("x2 (compiled length)");
+            return (int)nb;
         }
     }
     hipLaunchKernelGGL((k_x2c<T, L, X2N_FP64>), grid, dim3(XTile<L>::NTB), 0, s, g, a);
@@ -103,7 +106,7 @@ int x_ct_pairs(int nx) {
 // half as many as the others): bounds the number of n3-maximum partials.
 int x2_ct_min_pairs(int nx) {
     switch (nx) {
-#define DFT_CASE(n) case n: return x2_paired<n>() ? XPairTile<n>::PB : XTile<n>::PB;
+#define DFT_CASE(n) case n: return x2_paired<n>() ? XPairTile<float, n>::PB : XTile<n>::PB;
         DFT_CT_LENGTHS(DFT_CASE)
 #undef DFT_CASE
         default: return 0;
