@@ -7,6 +7,7 @@
 #include <stdexcept>
 #include <string>
 #include <type_traits>
+#include <utility>
 
 #include "dft_kernels.h"
 #include "fft_ct.h"
@@ -27,6 +28,17 @@ inline void ct_check(const char *what) {
 }
 
 inline long long ct_cdiv(long long a, long long b) { return (a + b - 1) / b; }
+
+// f(integral_constant<int, i>) for i = 0..N-1: a loop whose index is a constant in every body,
+// whatever the body's size (register arrays indexed by it stay in registers).
+template <class Fn, int... I>
+__device__ __forceinline__ void static_for_impl(Fn &&f, std::integer_sequence<int, I...>) {
+    (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, class Fn>
+__device__ __forceinline__ void static_for(Fn &&f) {
+    static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
 
 #define DFT_CT_LENGTHS(X) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384)
 
@@ -155,7 +167,7 @@ struct ZWave {
     T dkx, dkz, ky;
     int jx0, nx, nz;
     bool yzero, ynyq;
-    __device__ ZWave(const Consts &c, int kx0, int y) {
+    __device__ __forceinline__ ZWave(const Consts &c, int kx0, int y) {
         dkx = T(c.dk[0]);
         dkz = T(c.dk[2]);
         const int my = signed_mode(y, c.ny);
@@ -166,15 +178,15 @@ struct ZWave {
         yzero = y == 0;
         ynyq = (c.ny % 2 == 0) && (2 * y == c.ny);
     }
-    __device__ T kx(int p) const { return T(jx0 + p) * dkx; }
-    __device__ T kz(int e) const { return T(signed_mode(e, nz)) * dkz; }
-    __device__ T kmag(int p, int e) const {
+    __device__ __forceinline__ T kx(int p) const { return T(jx0 + p) * dkx; }
+    __device__ __forceinline__ T kz(int e) const { return T(signed_mode(e, nz)) * dkz; }
+    __device__ __forceinline__ T kmag(int p, int e) const {
         const T a = kx(p), b = kz(e);
         return sqrt_r(a * a + ky * ky + b * b);
     }
-    __device__ bool zero(int p, int e) const { return yzero && jx0 + p == 0 && e == 0; }
+    __device__ __forceinline__ bool zero(int p, int e) const { return yzero && jx0 + p == 0 && e == 0; }
     // component d of k, zero on the Nyquist plane of axis d
-    __device__ T comp(int p, int e, int d) const {
+    __device__ __forceinline__ T comp(int p, int e, int d) const {
         if (d == 0) return ((nx % 2 == 0) && 2 * (jx0 + p) == nx) ? T(0) : kx(p);
         if (d == 1) return ynyq ? T(0) : ky;
         return ((nz % 2 == 0) && 2 * e == nz) ? T(0) : kz(e);
@@ -187,7 +199,8 @@ template <typename T>
 struct Poisson {
     const cx<T> *tx, *tz;
     T ih2x, ih2z, dy;
-    __device__ Poisson(const Geo &g, const Consts &c, int y) {
+    __device__ __forceinline__ Poisson() : tx(nullptr), tz(nullptr), ih2x(0), ih2z(0), dy(0) {}
+    __device__ __forceinline__ Poisson(const Geo &g, const Consts &c, int y) {
         tx = twp<T>(g, 0);
         tz = twp<T>(g, 2);
         ih2x = T(1.0 / (c.h[0] * c.h[0]));
@@ -195,7 +208,7 @@ struct Poisson {
         const cx<T> wy = ct::gld(twp<T>(g, 1) + y);
         dy = two_omc<T>(wy.x, wy.y) * T(1.0 / (c.h[1] * c.h[1]));
     }
-    __device__ T denom(int jx, int e) const {
+    __device__ __forceinline__ T denom(int jx, int e) const {
         const cx<T> wx = ct::gld(tx + jx), wz = ct::gld(tz + e);
         return two_omc<T>(wx.x, wx.y) * ih2x + dy + two_omc<T>(wz.x, wz.y) * ih2z;
     }
@@ -216,191 +229,154 @@ __device__ __forceinline__ int pair_row(int S, int i, int j) {
 //       unnormalized over rho_hat in specA (z spectral order).
 // FP64 takes the spectral factors from the setup-time tables; FP32 (differences from the
 // reference) evaluates them on the fly: sin and cos of k R once per species, the pair
-// terms by the addition theorem, the Poisson denominator from the twiddle tables — in
+// terms by the addition theorem, the Poisson denominator from the twiddle tables -- in
 // FP32 that is cheaper than moving the tables.  The products act on registers between
-// the forward and inverse transforms.
-template <typename T, int L, int P, int NTB, int MS>
-__global__ __launch_bounds__(NTB) void k_z1c(Geo g_in, Z1Args a) {
-    using F = ct::Fft<T, typename ct::Plan<L>::type, P, NTB, false, 2>;
-    constexpr int NO = F::template nout<-1>();
-    static_assert(NO == F::template nin<1>(), "inverse must start where the forward ends");
+// the forward and inverse transforms.  Every Z1 kernel (fused or split, any tile width) does
+// the same arithmetic in the same order, so the autotuner's choice does not change a result.
+
+// Slot of the unordered species pair a <= b < MS.
+template <int MS>
+__device__ __forceinline__ constexpr int pair_slot(int a, int b) {
+    return a * MS - (a * (a - 1)) / 2 + (b - a);
+}
+
+// Products of one node with electrostatics (S <= MS): the species values u at the node (k_x
+// column p of the tile, z element e; ti its offset in a spectrum, ok whether it is a real
+// column), the five weighted sums out in acc, and the node's sums over j of K_ij times the
+// species spectra stored at dst + i NC.  Each unordered pair factor is formed once (K_ij = K_ji).
+template <typename T, int MS>
+__device__ __forceinline__ void z1_node(const Consts &c, bool diff, const ZWave<T> &kw, const Poisson<T> &pd,
+                                        const double *tab, long long NC, int S, bool es, int kx0, int p, int e,
+                                        bool ok, long long ti, const cx<T> (&u)[MS], cx<T> (&acc)[5], cx<T> *dst) {
     constexpr bool TAB = std::is_same<T, double>::value;
-    constexpr int ME = MS > 0 ? MS : 1;
-    const int prob = (int)blockIdx.z;
-    if (prob > 0) {
-        const long long o = (long long)prob * g_in.pstride;
-        g_in = shift(g_in, o);
-        a = shift(a, o);
+    constexpr int NPR = MS * (MS + 1) / 2;
+    T w2[MS], w3[MS], K[NPR];
+    // every loop over species or pairs has constant indices (static_for), whatever its size
+    if constexpr (TAB) {
+        static_for<MS>([&](auto J) __attribute__((always_inline)) {
+            constexpr int j = J;
+            w2[j] = (ok && j < S) ? ct::gld(tab + (long long)j * NC + ti) : T(0);
+            w3[j] = (ok && j < S) ? ct::gld(tab + (long long)(S + j) * NC + ti) : T(0);
+        });
+        static_for<MS>([&](auto IA) __attribute__((always_inline)) {
+            static_for<MS>([&](auto IB) __attribute__((always_inline)) {
+                constexpr int ia = IA, ib = IB;
+                if constexpr (ib >= ia)
+                    K[pair_slot<MS>(ia, ib)] =
+                        (ok && es && ib < S) ? ct::gld(tab + (long long)pair_row(S, ia, ib) * NC + ti) : T(0);
+            });
+        });
+    } else {
+        const T km = kw.kmag(p, e);
+        T sn[MS], cs[MS];
+        static_for<MS>([&](auto J) __attribute__((always_inline)) {
+            constexpr int j = J;
+            sn[j] = T(0);
+            cs[j] = T(1);
+            w2[j] = w3[j] = T(0);
+            if (j < S) {
+                sincos_r(km * T(c.R[j]), &sn[j], &cs[j]);
+                weight_w2_w3_sc<T>(km, T(c.R[j]), sn[j], cs[j], w2[j], w3[j]);
+            }
+        });
+        static_for<MS>([&](auto IA) __attribute__((always_inline)) {
+            static_for<MS>([&](auto IB) __attribute__((always_inline)) {
+                constexpr int ia = IA, ib = IB;
+                if constexpr (ib >= ia) {
+                    T Kv = T(0);
+                    if (es && ib < S) {
+                        // sin, cos of k (R_a + R_b) by the addition theorem: the contact cutoff (the
+                        // launcher sends the cutoff at lambda_a + lambda_b to the run-time-length kernel)
+                        const T sp = sn[ia] * cs[ib] + cs[ia] * sn[ib];
+                        const T cp = cs[ia] * cs[ib] - sn[ia] * sn[ib];
+                        const int ij = ia * DFT_MAX_SPECIES + ib;
+                        Kv = screening_hat_sc<T>(km, T(c.sc_R[ij]), sp, cp, T(c.sc_c1[ij]), T(c.sc_c0[ij]),
+                                                 T(c.sc_cm1[ij]));
+                    }
+                    K[pair_slot<MS>(ia, ib)] = Kv;
+                }
+            });
+        });
     }
-    const Geo &g = g_in;
-    if (gated_off(a.gate)) return;
-    __shared__ cx<T> lds[F::LDS_ELEMS];
+#pragma unroll
+    for (int m = 0; m < 5; ++m) acc[m] = mk<T>(T(0), T(0));
+    static_for<MS>([&](auto J) __attribute__((always_inline)) {
+        constexpr int j = J;
+        if (j < S) {
+            const T a0 = T(c.i4piR2[j]), a1 = T(c.i4piR[j]);
+            const T m0 = w2[j] * a0, m1 = w2[j] * a1, m4 = w3[j] * a1;
+            acc[0].x += u[j].x * m0; acc[0].y += u[j].y * m0;
+            acc[1].x += u[j].x * m1; acc[1].y += u[j].y * m1;
+            acc[2].x += u[j].x * w2[j]; acc[2].y += u[j].y * w2[j];
+            acc[3].x += u[j].x * w3[j]; acc[3].y += u[j].y * w3[j];
+            acc[4].x += u[j].x * m4; acc[4].y += u[j].y * m4;
+        }
+    });
+    if (!(es && ok)) return;
+    // the bath term enters the k = 0 element of the pair-correlation part only
+    const bool z0 = !diff && kw.zero(p, e);
+    T invD = T(0);
+    if constexpr (!TAB)
+        if (!kw.zero(p, e)) invD = T(c.four_pi_lB) * rcp_r(pd.denom(kx0 + p, e));
+    static_for<MS>([&](auto IS) __attribute__((always_inline)) {
+        constexpr int is = IS;
+        if (is < S) {
+            cx<T> ea = mk<T>(T(0), T(0));
+            static_for<MS>([&](auto J) __attribute__((always_inline)) {
+                constexpr int j = J;
+                if (j < S) {
+                    const T Kij = K[is <= j ? pair_slot<MS>(is, j) : pair_slot<MS>(j, is)];
+                    const T ux = z0 ? u[j].x - T((double)c.N * c.rho_b[j]) : u[j].x;
+                    if constexpr (TAB) {
+                        ea.x += Kij * ux;
+                        ea.y += Kij * u[j].y;
+                    } else {
+                        const T Pz = invD * T(c.z[is] * c.z[j]);
+                        ea.x += Kij * ux - Pz * u[j].x;
+                        ea.y += (Kij - Pz) * u[j].y;
+                    }
+                }
+            });
+            ct::gst(dst + (long long)is * NC, ea);
+        }
+    });
+}
+
+// Products of one species at one node without electrostatics (species by species).
+template <typename T>
+__device__ __forceinline__ void z1_species(const Consts &c, const ZWave<T> &kw, const double *tab, long long NC, int S,
+                                           int jsp, int p, int e, bool ok, long long ti, cx<T> u, cx<T> (&acc)[5]) {
+    T w2, w3;
+    if constexpr (std::is_same<T, double>::value) {
+        w2 = ok ? ct::gld(tab + (long long)jsp * NC + ti) : T(0);
+        w3 = ok ? ct::gld(tab + (long long)(S + jsp) * NC + ti) : T(0);
+    } else {
+        weight_w2_w3<T>(kw.kmag(p, e), T(c.R[jsp]), w2, w3);
+    }
+    const T a0 = T(c.i4piR2[jsp]), a1 = T(c.i4piR[jsp]);
+    const T m0 = w2 * a0, m1 = w2 * a1, m4 = w3 * a1;
+    acc[0].x += u.x * m0; acc[0].y += u.y * m0;
+    acc[1].x += u.x * m1; acc[1].y += u.y * m1;
+    acc[2].x += u.x * w2; acc[2].y += u.y * w2;
+    acc[3].x += u.x * w3; acc[3].y += u.y * w3;
+    acc[4].x += u.x * m4; acc[4].y += u.y * m4;
+}
+
+// The seven inverse transforms of Z1 and their stores.  Along a z pencil k_x and k_y are
+// constant, so the x and y components of the vector densities are -i k_x and -i k_y times the
+// transform of their scalar sum; only n0..n3, the two vector sums' k_z multiples and the nV1 sum
+// are transformed.  Transform t, its source sum and whether it is multiplied by -i k_z:
+//   t = 0..3: acc[t] (n0..n3; t = 3 also gives the x, y components of nV2)
+//   t = 4: acc[4] (x, y components of nV1);  t = 5: -i k_z acc[4] (nV1_z);  t = 6: -i k_z acc[3] (nV2_z)
+template <typename T, class F, int NO>
+__device__ __forceinline__ void z1_inverse(const Geo &g, const Z1Args &a, const ZWave<T> &kw, cx<T> *lds, int &ph,
+                                           const cx<T> *tw, int Pact, long long rs, long long off,
+                                           const cx<T> (&acc)[NO][5]) {
     const Consts &c = *g.cs;
-    const int Kx = g.Kx, S = g.S;
     const long long NC = g.NC;
-    int bx, y;
-    xcd_block(bx, y);
-    const int kx0 = bx * P;
-    const int Pact = min(P, Kx - kx0);
-    const long long rs = (long long)g.ny * Kx;
-    const long long off = (long long)y * Kx + kx0;
-    const cx<T> *tw = twp<T>(g, 2);
-    const bool es = MS > 0 && c.es && !a.n3only;
-    const ZWave<T> kw(c, kx0, y);
-    int pp[NO], ee[NO];
-    bool okk[NO];
-    long long ti[NO];   // element offsets in a table row / spectrum
-    constexpr int NOF = TAB ? 1 : NO;             // on-the-fly factors (FP32 only)
-    constexpr int MSF = (TAB || MS == 0) ? 1 : MS;
-    T kmag[NOF], invD[NOF], sn[MSF][NOF], cs[MSF][NOF];
-#pragma unroll
-    for (int i = 0; i < NO; ++i) {
-        okk[i] = F::template out_pos<-1>(i, pp[i], ee[i]) && pp[i] < Pact;
-        ti[i] = okk[i] ? ee[i] * rs + pp[i] : 0;
-    }
-    if constexpr (!TAB) {
-        const Poisson<T> pd(g, c, y);
-#pragma unroll
-        for (int i = 0; i < NO; ++i) {
-            kmag[i] = kw.kmag(pp[i], ee[i]);
-            invD[i] = T(0);
-            if constexpr (MS > 0) {
-                if (es && !kw.zero(pp[i], ee[i])) invD[i] = T(c.four_pi_lB) * rcp_r(pd.denom(kx0 + pp[i], ee[i]));
-#pragma unroll
-                for (int is = 0; is < MS; ++is) {
-                    sn[is][i] = T(0);
-                    cs[is][i] = T(1);
-                    if (is < S) sincos_r(kmag[i] * T(c.R[is]), &sn[is][i], &cs[is][i]);
-                }
-            }
-        }
-    }
-    cx<T> acc[5][NO];
-    cx<T> esa[ME][NO];
-#pragma unroll
-    for (int i = 0; i < NO; ++i) {
-#pragma unroll
-        for (int m = 0; m < 5; ++m) acc[m][i] = mk<T>(T(0), T(0));
-#pragma unroll
-        for (int m = 0; m < ME; ++m) esa[m][i] = mk<T>(T(0), T(0));
-    }
-    cx<T> v[F::V];
-    int ph = 0;
-    typename F::template TwReg<-1> trs;   // forward twiddles, shared by the species transforms
-    F::template load_tw<-1>(trs, tw);
-    // each species' inputs are fetched while the previous species transforms
-    constexpr int NIN = F::template nin<-1>();
-    cx<T> vin[NIN];
-    auto load_species = [&](int jsp) {
-        const cx<T> *src = reinterpret_cast<const cx<T> *>(a.specA) + (long long)jsp * NC + off;
-#pragma unroll
-        for (int i = 0; i < NIN; ++i) {
-            int p, e;
-            const bool ok = F::template in_pos<-1>(i, p, e);
-            vin[i] = (ok && p < Pact) ? ct::gld(src + e * rs + p) : mk<T>(T(0), T(0));
-        }
-    };
-    load_species(0);
-    for (int jsp = 0; jsp < S; ++jsp) {
-#pragma unroll
-        for (int i = 0; i < NIN; ++i) v[i] = vin[i];
-        if (jsp + 1 < S) load_species(jsp + 1);
-        // FP64: this species' table values, fetched before the transform hides their latency
-        constexpr int NOT = TAB ? NO : 1;
-        T w2r[NOT], w3r[NOT], kr[ME][NOT];
-        if constexpr (TAB) {
-            const double *tab = g.tab64 + off;
-            const double *t2 = tab + (long long)jsp * NC, *t3 = tab + (long long)(S + jsp) * NC;
-#pragma unroll
-            for (int i = 0; i < NO; ++i) {
-                w2r[i] = ct::gld(t2 + ti[i]);
-                w3r[i] = ct::gld(t3 + ti[i]);
-#pragma unroll
-                for (int is = 0; is < ME; ++is) {
-                    kr[is][i] = T(0);
-                    if (MS > 0 && es && is < S) kr[is][i] = ct::gld(tab + (long long)pair_row(S, is, jsp) * NC + ti[i]);
-                }
-            }
-        }
-        F::template run<-1>(v, lds, ph, trs);
-        const T Rj = T(c.R[jsp]), a0 = T(c.i4piR2[jsp]), a1 = T(c.i4piR[jsp]);
-        const T bath = T((double)c.N * c.rho_b[jsp]);
-#pragma unroll
-        for (int i = 0; i < NO; ++i) {
-            const cx<T> u = v[i];
-            T w2, w3;
-            T ux = u.x;
-            if (MS > 0 && es && !a.diff && kw.zero(pp[i], ee[i])) ux -= bath;
-            if constexpr (TAB) {
-                w2 = w2r[i];
-                w3 = w3r[i];
-                if constexpr (MS > 0) {
-                    if (es) {
-#pragma unroll
-                        for (int is = 0; is < MS; ++is) {
-                            if (is < S) {
-                                esa[is][i].x += kr[is][i] * ux;
-                                esa[is][i].y += kr[is][i] * u.y;
-                            }
-                        }
-                    }
-                }
-            } else if constexpr (MS > 0) {
-                // sin, cos of k R_j picked with constant register indices
-                T sj = sn[0][i], cj = cs[0][i];
-#pragma unroll
-                for (int is = 1; is < MS; ++is)
-                    if (is == jsp) { sj = sn[is][i]; cj = cs[is][i]; }
-                weight_w2_w3_sc<T>(kmag[i], Rj, sj, cj, w2, w3);
-                if (es) {
-#pragma unroll
-                    for (int is = 0; is < MS; ++is) {
-                        if (is < S) {
-                            // sin, cos of k (R_i + R_j) by the addition theorem: the contact
-                            // cutoff (the launcher sends the cutoff at lambda_i + lambda_j to the
-                            // run-time-length kernel)
-                            const T sp = sn[is][i] * cj + cs[is][i] * sj;
-                            const T cp = cs[is][i] * cj - sn[is][i] * sj;
-                            const int ij = is * DFT_MAX_SPECIES + jsp;
-                            const T C = screening_hat_sc<T>(kmag[i], T(c.sc_R[ij]), sp, cp, T(c.sc_c1[ij]),
-                                                            T(c.sc_c0[ij]), T(c.sc_cm1[ij]));
-                            const T Pz = invD[i] * T(c.z[is] * c.z[jsp]);
-                            esa[is][i].x += C * ux - Pz * u.x;
-                            esa[is][i].y += (C - Pz) * u.y;
-                        }
-                    }
-                }
-            } else {
-                weight_w2_w3<T>(kmag[i], Rj, w2, w3);
-            }
-            const T m0 = w2 * a0, m1 = w2 * a1, m4 = w3 * a1;
-            acc[0][i].x += u.x * m0; acc[0][i].y += u.y * m0;
-            acc[1][i].x += u.x * m1; acc[1][i].y += u.y * m1;
-            acc[2][i].x += u.x * w2; acc[2][i].y += u.y * w2;
-            acc[3][i].x += u.x * w3; acc[3][i].y += u.y * w3;
-            acc[4][i].x += u.x * m4; acc[4][i].y += u.y * m4;
-        }
-    }
-    if constexpr (MS > 0) {
-        if (es) {
-#pragma unroll
-            for (int is = 0; is < MS; ++is) {
-                if (is >= S) break;
-                cx<T> *dst = reinterpret_cast<cx<T> *>(a.specA) + (long long)is * NC + off;
-#pragma unroll
-                for (int i = 0; i < NO; ++i)
-                    if (okk[i]) ct::gst(dst + ti[i], esa[is][i]);
-            }
-        }
-    }
-    // Seven inverse transforms give the ten outputs: along a z pencil k_x and k_y are constant, so
-    // the x and y components of the vector densities are -i k_x and -i k_y times the transform of
-    // their scalar sum; only n0..n3, the two vector sums' k_z multiples and the nV1 sum are
-    // transformed.  Transform t, its source sum and whether it is multiplied by -i k_z:
-    //   t = 0..3: acc[t] (n0..n3; t = 3 also gives the x, y components of nV2)
-    //   t = 4: acc[4] (x, y components of nV1);  t = 5: -i k_z acc[4] (nV1_z);  t = 6: -i k_z acc[3] (nV2_z)
     const int ntr = a.n3only ? 1 : 7;
     const T invN = T(c.invN);
+    cx<T> v[F::V];
     typename F::template TwReg<1> tri;   // inverse twiddles, shared by the output transforms
     F::template load_tw<1>(tri, tw);
     for (int t = 0; t < ntr; ++t) {
@@ -409,15 +385,17 @@ __global__ __launch_bounds__(NTB) void k_z1c(Geo g_in, Z1Args a) {
 #pragma unroll
         for (int i = 0; i < NO; ++i) {
             // source sum selected with compile-time register indices
-            cx<T> s = acc[3][i];
+            cx<T> sm = acc[i][3];
 #pragma unroll
             for (int m = 0; m < 5; ++m)
-                if (m == src) s = acc[m][i];
+                if (m == src) sm = acc[i][m];
             if (kzm) {
-                const T kd = kw.comp(pp[i], ee[i], 2);
-                s = mk<T>(kd * s.y, -kd * s.x);   // -i k_z s
+                int p, e;
+                F::template in_pos<1>(i, p, e);
+                const T kd = kw.comp(p, e, 2);
+                sm = mk<T>(kd * sm.y, -kd * sm.x);   // -i k_z s
             }
-            v[i] = mk<T>(s.x * invN, s.y * invN);
+            v[i] = mk<T>(sm.x * invN, sm.y * invN);
         }
         F::template run<1>(v, lds, ph, tri);
         // store the transform as output o, times -i k_d for d = 0 (x) or 1 (y), plain for d < 0
@@ -456,18 +434,12 @@ __global__ __launch_bounds__(NTB) void k_z1c(Geo g_in, Z1Args a) {
     }
 }
 
-// Z1 from z spectra: the same products and inverse transforms as k_z1c, for species spectra
-// that the plain z pass has already transformed along z (the autotuner's split Z1 shapes).  With
-// the forward transform in its own kernel, this one needs neither the prefetched inputs nor the
-// forward twiddles in registers, and more waves fit per SIMD.  Each thread reads the species
-// values at the positions it starts the inverse transforms from, so the electrostatic spectra
-// overwrite species values only after the same thread has read them.
 template <typename T, int L, int P, int NTB, int MS>
-__global__ __launch_bounds__(NTB) void k_z1s(Geo g_in, Z1Args a) {
+__global__ __launch_bounds__(NTB) void k_z1c(Geo g_in, Z1Args a) {
     using F = ct::Fft<T, typename ct::Plan<L>::type, P, NTB, false, 2>;
-    constexpr int NO = F::template nin<1>();
+    constexpr int NO = F::template nout<-1>();
+    static_assert(NO == F::template nin<1>(), "inverse must start where the forward ends");
     constexpr bool TAB = std::is_same<T, double>::value;
-    constexpr int ME = MS > 0 ? MS : 1;
     const int prob = (int)blockIdx.z;
     if (prob > 0) {
         const long long o = (long long)prob * g_in.pstride;
@@ -489,171 +461,148 @@ __global__ __launch_bounds__(NTB) void k_z1s(Geo g_in, Z1Args a) {
     const cx<T> *tw = twp<T>(g, 2);
     const bool es = MS > 0 && c.es && !a.n3only;
     const ZWave<T> kw(c, kx0, y);
-    int pp[NO], ee[NO];
-    bool okk[NO];
-    long long ti[NO];
-    constexpr int NOF = TAB ? 1 : NO;
-    constexpr int MSF = (TAB || MS == 0) ? 1 : MS;
-    T kmag[NOF], invD[NOF], sn[MSF][NOF], cs[MSF][NOF];
-#pragma unroll
-    for (int i = 0; i < NO; ++i) {
-        okk[i] = F::template in_pos<1>(i, pp[i], ee[i]) && pp[i] < Pact;
-        ti[i] = okk[i] ? ee[i] * rs + pp[i] : 0;
-    }
-    if constexpr (!TAB) {
-        const Poisson<T> pd(g, c, y);
-#pragma unroll
-        for (int i = 0; i < NO; ++i) {
-            kmag[i] = kw.kmag(pp[i], ee[i]);
-            invD[i] = T(0);
-            if constexpr (MS > 0) {
-                if (es && !kw.zero(pp[i], ee[i])) invD[i] = T(c.four_pi_lB) * rcp_r(pd.denom(kx0 + pp[i], ee[i]));
-#pragma unroll
-                for (int is = 0; is < MS; ++is) {
-                    sn[is][i] = T(0);
-                    cs[is][i] = T(1);
-                    if (is < S) sincos_r(kmag[i] * T(c.R[is]), &sn[is][i], &cs[is][i]);
-                }
-            }
-        }
-    }
-    cx<T> acc[5][NO];
-    cx<T> esa[ME][NO];
-#pragma unroll
-    for (int i = 0; i < NO; ++i) {
-#pragma unroll
-        for (int m = 0; m < 5; ++m) acc[m][i] = mk<T>(T(0), T(0));
-#pragma unroll
-        for (int m = 0; m < ME; ++m) esa[m][i] = mk<T>(T(0), T(0));
-    }
-    for (int jsp = 0; jsp < S; ++jsp) {
-        const cx<T> *src = reinterpret_cast<const cx<T> *>(a.specA) + (long long)jsp * NC + off;
-        cx<T> uin[NO];
-#pragma unroll
-        for (int i = 0; i < NO; ++i) uin[i] = okk[i] ? ct::gld(src + ti[i]) : mk<T>(T(0), T(0));
-        const T Rj = T(c.R[jsp]), a0 = T(c.i4piR2[jsp]), a1 = T(c.i4piR[jsp]);
-        const T bath = T((double)c.N * c.rho_b[jsp]);
-#pragma unroll
-        for (int i = 0; i < NO; ++i) {
-            const cx<T> u = uin[i];
-            T w2, w3;
-            T ux = u.x;
-            if (MS > 0 && es && !a.diff && kw.zero(pp[i], ee[i])) ux -= bath;
-            if constexpr (TAB) {
-                const double *tab = g.tab64 + off;
-                w2 = ct::gld(tab + (long long)jsp * NC + ti[i]);
-                w3 = ct::gld(tab + (long long)(S + jsp) * NC + ti[i]);
-                if constexpr (MS > 0) {
-                    if (es) {
-#pragma unroll
-                        for (int is = 0; is < MS; ++is) {
-                            if (is < S) {
-                                const T kr = ct::gld(tab + (long long)pair_row(S, is, jsp) * NC + ti[i]);
-                                esa[is][i].x += kr * ux;
-                                esa[is][i].y += kr * u.y;
-                            }
-                        }
-                    }
-                }
-            } else if constexpr (MS > 0) {
-                T sj = sn[0][i], cj = cs[0][i];
-#pragma unroll
-                for (int is = 1; is < MS; ++is)
-                    if (is == jsp) { sj = sn[is][i]; cj = cs[is][i]; }
-                weight_w2_w3_sc<T>(kmag[i], Rj, sj, cj, w2, w3);
-                if (es) {
-#pragma unroll
-                    for (int is = 0; is < MS; ++is) {
-                        if (is < S) {
-                            const T sp = sn[is][i] * cj + cs[is][i] * sj;
-                            const T cp = cs[is][i] * cj - sn[is][i] * sj;
-                            const int ij = is * DFT_MAX_SPECIES + jsp;
-                            const T C = screening_hat_sc<T>(kmag[i], T(c.sc_R[ij]), sp, cp, T(c.sc_c1[ij]),
-                                                            T(c.sc_c0[ij]), T(c.sc_cm1[ij]));
-                            const T Pz = invD[i] * T(c.z[is] * c.z[jsp]);
-                            esa[is][i].x += C * ux - Pz * u.x;
-                            esa[is][i].y += (C - Pz) * u.y;
-                        }
-                    }
-                }
-            } else {
-                weight_w2_w3<T>(kmag[i], Rj, w2, w3);
-            }
-            const T m0 = w2 * a0, m1 = w2 * a1, m4 = w3 * a1;
-            acc[0][i].x += u.x * m0; acc[0][i].y += u.y * m0;
-            acc[1][i].x += u.x * m1; acc[1][i].y += u.y * m1;
-            acc[2][i].x += u.x * w2; acc[2][i].y += u.y * w2;
-            acc[3][i].x += u.x * w3; acc[3][i].y += u.y * w3;
-            acc[4][i].x += u.x * m4; acc[4][i].y += u.y * m4;
-        }
-    }
-    if constexpr (MS > 0) {
-        if (es) {
-#pragma unroll
-            for (int is = 0; is < MS; ++is) {
-                if (is >= S) break;
-                cx<T> *dst = reinterpret_cast<cx<T> *>(a.specA) + (long long)is * NC + off;
-#pragma unroll
-                for (int i = 0; i < NO; ++i)
-                    if (okk[i]) ct::gst(dst + ti[i], esa[is][i]);
-            }
-        }
-    }
-    // the seven inverse transforms and their stores, as in k_z1c
-    const int ntr = a.n3only ? 1 : 7;
-    const T invN = T(c.invN);
+    const double *tab = TAB ? g.tab64 + off : nullptr;
+    cx<T> acc[NO][5];
     cx<T> v[F::V];
     int ph = 0;
-    typename F::template TwReg<1> tri;
-    F::template load_tw<1>(tri, tw);
-    for (int t = 0; t < ntr; ++t) {
-        const int srcm = a.n3only ? 3 : (t < 5 ? t : (t == 5 ? 4 : 3));
-        const bool kzm = t >= 5;
+    typename F::template TwReg<-1> trs;   // forward twiddles, shared by the species transforms
+    F::template load_tw<-1>(trs, tw);
+    // each species' inputs are fetched while the previous species transforms
+    constexpr int NIN = F::template nin<-1>();
+    cx<T> vin[NIN];
+    auto load_species = [&](int jsp) {
+        const cx<T> *src = reinterpret_cast<const cx<T> *>(a.specA) + (long long)jsp * NC + off;
 #pragma unroll
-        for (int i = 0; i < NO; ++i) {
-            cx<T> sm = acc[3][i];
-#pragma unroll
-            for (int m = 0; m < 5; ++m)
-                if (m == srcm) sm = acc[m][i];
-            if (kzm) {
-                const T kd = kw.comp(pp[i], ee[i], 2);
-                sm = mk<T>(kd * sm.y, -kd * sm.x);
-            }
-            v[i] = mk<T>(sm.x * invN, sm.y * invN);
+        for (int i = 0; i < NIN; ++i) {
+            int p, e;
+            const bool ok = F::template in_pos<-1>(i, p, e);
+            vin[i] = (ok && p < Pact) ? ct::gld(src + e * rs + p) : mk<T>(T(0), T(0));
         }
-        F::template run<1>(v, lds, ph, tri);
-        auto store = [&](int o, int d) {
-            cx<T> *dst = reinterpret_cast<cx<T> *>(a.specB) + (long long)o * NC + off;
+    };
+    load_species(0);
+    if constexpr (MS == 0) {
 #pragma unroll
-            for (int i = 0; i < F::template nout<1>(); ++i) {
+        for (int i = 0; i < NO; ++i)
+#pragma unroll
+            for (int m = 0; m < 5; ++m) acc[i][m] = mk<T>(T(0), T(0));
+        for (int jsp = 0; jsp < S; ++jsp) {
+#pragma unroll
+            for (int i = 0; i < NIN; ++i) v[i] = vin[i];
+            if (jsp + 1 < S) load_species(jsp + 1);
+            F::template run<-1>(v, lds, ph, trs);
+#pragma unroll
+            for (int i = 0; i < NO; ++i) {
                 int p, e;
-                const bool ok = F::template out_pos<1>(i, p, e);
-                if (!(ok && p < Pact)) continue;
-                cx<T> w = v[i];
-                if (d >= 0) {
-                    const T kd = kw.comp(p, e, d);
-                    w = mk<T>(kd * w.y, -kd * w.x);
-                }
-                ct::gst(dst + e * rs + p, w);
+                const bool ok = F::template out_pos<-1>(i, p, e) && p < Pact;
+                z1_species<T>(c, kw, tab, NC, S, jsp, p, e, ok, ok ? e * rs + p : 0, v[i], acc[i]);
             }
-        };
-        if (a.n3only) {
-            store(0, -1);
-        } else if (g.compact) {
-            store(t < 5 ? t : (t == 5 ? 6 : 9), -1);
-        } else if (t < 4) {
-            store(t, -1);
-            if (t == 3) {
-                store(7, 0);
-                store(8, 1);
-            }
-        } else if (t == 4) {
-            store(4, 0);
-            store(5, 1);
-        } else {
-            store(t == 5 ? 6 : 9, -1);
         }
+    } else {
+        // all species transformed first (S <= MS), then the products node by node
+        cx<T> us[MS][NO];
+        static_for<MS>([&](auto J) __attribute__((always_inline)) {
+            constexpr int jsp = J;
+#pragma unroll
+            for (int i = 0; i < NO; ++i) us[jsp][i] = mk<T>(T(0), T(0));
+            if (jsp < S) {
+#pragma unroll
+                for (int i = 0; i < NIN; ++i) v[i] = vin[i];
+                if (jsp + 1 < S) load_species(jsp + 1);
+                F::template run<-1>(v, lds, ph, trs);
+#pragma unroll
+                for (int i = 0; i < NO; ++i) us[jsp][i] = v[i];
+            }
+        });
+        Poisson<T> pd;
+        if constexpr (!TAB) pd = Poisson<T>(g, c, y);
+        static_for<NO>([&](auto I) __attribute__((always_inline)) {
+            constexpr int i = I;
+            int p, e;
+            const bool ok = F::template out_pos<-1>(i, p, e) && p < Pact;
+            const long long ti = ok ? e * rs + p : 0;
+            cx<T> u[MS];
+#pragma unroll
+            for (int j = 0; j < MS; ++j) u[j] = us[j][i];
+            z1_node<T, MS>(c, a.diff != 0, kw, pd, tab, NC, S, es, kx0, p, e, ok, ti, u, acc[i],
+                           reinterpret_cast<cx<T> *>(a.specA) + off + ti);
+        });
     }
+    z1_inverse<T, F, NO>(g, a, kw, lds, ph, tw, Pact, rs, off, acc);
+}
+
+// Z1 from z spectra: the same products and inverse transforms as k_z1c, for species spectra
+// that the plain z pass has already transformed along z (the autotuner's split Z1 shapes).  With
+// the forward transform in its own kernel, this one needs neither the prefetched inputs nor the
+// forward twiddles in registers.  Each thread reads the species values at the positions it
+// starts the inverse transforms from and overwrites them with the electrostatic spectra only
+// after reading them.
+template <typename T, int L, int P, int NTB, int MS>
+__global__ __launch_bounds__(NTB) void k_z1s(Geo g_in, Z1Args a) {
+    using F = ct::Fft<T, typename ct::Plan<L>::type, P, NTB, false, 2>;
+    constexpr int NO = F::template nin<1>();
+    constexpr bool TAB = std::is_same<T, double>::value;
+    const int prob = (int)blockIdx.z;
+    if (prob > 0) {
+        const long long o = (long long)prob * g_in.pstride;
+        g_in = shift(g_in, o);
+        a = shift(a, o);
+    }
+    const Geo &g = g_in;
+    if (gated_off(a.gate)) return;
+    __shared__ cx<T> lds[F::LDS_ELEMS];
+    const Consts &c = *g.cs;
+    const int Kx = g.Kx, S = g.S;
+    const long long NC = g.NC;
+    int bx, y;
+    xcd_block(bx, y);
+    const int kx0 = bx * P;
+    const int Pact = min(P, Kx - kx0);
+    const long long rs = (long long)g.ny * Kx;
+    const long long off = (long long)y * Kx + kx0;
+    const cx<T> *tw = twp<T>(g, 2);
+    const bool es = MS > 0 && c.es && !a.n3only;
+    const ZWave<T> kw(c, kx0, y);
+    const double *tab = TAB ? g.tab64 + off : nullptr;
+    cx<T> acc[NO][5];
+    if constexpr (MS == 0) {
+        // species by species, every node's input of a species in flight together
+#pragma unroll
+        for (int i = 0; i < NO; ++i)
+#pragma unroll
+            for (int m = 0; m < 5; ++m) acc[i][m] = mk<T>(T(0), T(0));
+        for (int jsp = 0; jsp < S; ++jsp) {
+            const cx<T> *src = reinterpret_cast<const cx<T> *>(a.specA) + (long long)jsp * NC + off;
+            cx<T> uin[NO];
+#pragma unroll
+            for (int i = 0; i < NO; ++i) {
+                int p, e;
+                const bool ok = F::template in_pos<1>(i, p, e) && p < Pact;
+                uin[i] = ok ? ct::gld(src + e * rs + p) : mk<T>(T(0), T(0));
+            }
+#pragma unroll
+            for (int i = 0; i < NO; ++i) {
+                int p, e;
+                const bool ok = F::template in_pos<1>(i, p, e) && p < Pact;
+                z1_species<T>(c, kw, tab, NC, S, jsp, p, e, ok, ok ? e * rs + p : 0, uin[i], acc[i]);
+            }
+        }
+    } else {
+        Poisson<T> pd;
+        if constexpr (!TAB) pd = Poisson<T>(g, c, y);
+        static_for<NO>([&](auto I) __attribute__((always_inline)) {
+            constexpr int i = I;
+            int p, e;
+            const bool ok = F::template in_pos<1>(i, p, e) && p < Pact;
+            const long long ti = ok ? e * rs + p : 0;
+            cx<T> *src = reinterpret_cast<cx<T> *>(a.specA) + off + ti;
+            cx<T> u[MS];
+#pragma unroll
+            for (int j = 0; j < MS; ++j) u[j] = (ok && j < S) ? ct::gld(src + (long long)j * NC) : mk<T>(T(0), T(0));
+            z1_node<T, MS>(c, a.diff != 0, kw, pd, tab, NC, S, es, kx0, p, e, ok, ti, u, acc[i], src);
+        });
+    }
+    int ph = 0;
+    z1_inverse<T, F, NO>(g, a, kw, lds, ph, tw, Pact, rs, off, acc);
 }
 
 // Z2: forward z transform of the ten dPhi/dn spectra, back-convolution with conj(w_hat)
