@@ -356,6 +356,39 @@ def functionals_leg(n):
     return out
 
 
+def two_ion_leg(n, steps, warmup, tol):
+    """The two-ion chemistry of the 128^3 sphere workload (1:1 RPM electrolyte, 0.3 nm ions at
+    0.1 M around a charged sphere, h = 0.025 nm) at n^3: the headline's measurements for S = 2 --
+    a solve from the bath to tol and the timed window of iterations -- in FP32-mixed and FP64."""
+    import torch
+    import workloads as W
+    from paper_0910_1531_amd import _abi
+    from paper_0910_1531_amd import solver as sv
+
+    p = W.charged_sphere(n=n, h=0.025, tol=tol, name=f"sphere_{n}")
+    out = {"workload": f"1:1 electrolyte (0.3 nm, 0.1 M) around a charged sphere (R 0.5 nm, -4e), {n}^3, "
+                       f"h = 0.025 nm, S = 2"}
+    for pname, prec in (("mixed", _abi.DFT_FP32_MIXED), ("fp64", _abi.DFT_FP64)):
+        sol = sv.from_problem(p, precision=prec)
+        rho0 = torch.tensor(p.initial_density(), dtype=torch.float64, device="cuda")
+        x = rho0.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        it, r, st = sol.solve(x, tol, 5000, raise_on_fail=False)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        if warmup > 0:
+            _solve_window(sol, rho0, warmup, tol)
+        wdt, nsolve, acc, rej, gev, ref64, conv = _solve_window(sol, rho0, steps, tol)
+        out[pname] = {"its": round(steps / wdt, 3), "ms_per_step": round(1e3 * wdt / steps, 4),
+                      "window": {"iterations": acc, "solves": nsolve, "solves_converged": conv, "rejected": rej,
+                                 "residual_evals": gev, "fp64_evals": ref64},
+                      "solve_to_tol": {"iters": it, "seconds": round(dt, 4), "its": round(it / dt, 2),
+                                       "r": float(f"{r:.4g}"), "status": st}}
+        sol.close()
+    return out
+
+
 def screening_leg(n):
     """The RFD screening operator (ball averages with a radius R_SC(x) that varies over 0.3-0.6 nm)
     of the pore's three species at n^3, by Chebyshev interpolation in the radius (the paper's
@@ -498,7 +531,8 @@ def main():
     cpu = None if args.no_cpu_baseline else cpu_baseline(args.n, evals_per_iter, None if args.no_extras else args.n)
     extras = None
     if not args.no_extras:
-        extras = {"batch_64_points_fp32_mixed": batch_leg(), "pore192_adjoint": adjoint_leg(),
+        extras = {"two_ion_256": two_ion_leg(args.n, args.steps, args.warmup, args.tol),
+                  "batch_64_points_fp32_mixed": batch_leg(), "pore192_adjoint": adjoint_leg(),
                   "paper_workloads": paper_workloads_leg(), "newton_krylov_fp64": newton_leg(args.n),
                   "hs_functionals": functionals_leg(args.n), "rfd_screening": screening_leg(args.n)}
 

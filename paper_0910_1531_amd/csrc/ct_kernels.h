@@ -1369,6 +1369,7 @@ __global__ __launch_bounds__(XTile<L>::NTB) void k_x1c(Geo g_in, XFwdArgs a) {
     }
     const Geo &g = g_in;
     if (gated_off(a.gate)) return;
+    resolve_roles(a);
     // wave-private tiles: twiddles fetched up front, with the data
     typename F::Twiddles trw;
     if constexpr (F::WP) F::load_twiddles(trw, twp<T>(g_in, 0));
@@ -1437,6 +1438,7 @@ __global__ __launch_bounds__(XTile<L>::NTB) void k_x3c(Geo g_in, X3Args a) {
     }
     const Geo &g = g_in;
     if (gated_off(a.gate)) return;
+    resolve_roles(a);
     // wave-private tiles: twiddles fetched up front, with the data
     typename F::Twiddles trw;
     if constexpr (F::WP) F::load_twiddles(trw, twp<T>(g_in, 0));

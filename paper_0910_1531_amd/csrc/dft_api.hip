@@ -42,7 +42,7 @@ struct HipError : std::runtime_error {
 // ------------------------------------------------------------------ workspace layout
 struct Layout {
     size_t consts, state, tw64[3], tw32[3], fpart, mpart, fflag, mflag, specA, specB;
-    size_t base, rho0, g0, ga, gb, gs, rho_t, rho_ref, lp, nref, phi_fix, count_part;
+    size_t base, rho0, g0, ga, gb, gs, rho_t, rho_t2, rho_t3, rho_ref, lp, nref, phi_fix, count_part;
     size_t tab64;
     int ntab;
     size_t total;
@@ -88,6 +88,8 @@ Layout make_layout(const dft_params *p) {
     L.gb = take(F);
     L.gs = take(F);
     L.rho_t = take(F);
+    L.rho_t2 = take(F);
+    L.rho_t3 = take(F);
     L.phi_fix = take(sizeof(double) * (size_t)N);
     if (p->precision == DFT_FP32_MIXED) {
         L.rho_ref = take(F);
@@ -119,11 +121,14 @@ struct dft_ctx {
     double *base = nullptr, *rho0 = nullptr, *g0 = nullptr, *ga = nullptr, *gb = nullptr, *gs = nullptr;
     double *rho_t = nullptr, *rho_ref = nullptr, *lp = nullptr, *phi_fix = nullptr;
     float *nref = nullptr;
+    // line-search buffers by role: densities {rho0, rho_t, rho_t2, rho_t3}, images {g0, gb, ga, gs};
+    // the state's sel names the current iterate's (role 0 after a fresh state)
+    Roles roles{};
     RedBufs red{};
     int nf_parts = 0, nm_parts = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
-    const double *step_rho = nullptr;   // caller buffer whose iterate rho0 currently holds
+    const double *step_rho = nullptr;   // caller buffer whose iterate the current role holds
     long long refreshes = 0;
     bool mixed = false;
 };
@@ -133,6 +138,8 @@ namespace {
 // Options of one residual evaluation.
 struct Eval {
     bool trial = false;            // rho_t = rho0 + alpha (g0 - rho0)
+    int kind = -1;                 // >= 0: a line-search pass on the rotating buffers (RoleKind);
+                                   // src, g0, rho_t and g_out then come from the roles
     const double *src = nullptr;   // plain: rho; trial: rho0
     const double *g0 = nullptr;
     const double *alpha = nullptr;
@@ -168,6 +175,10 @@ void enqueue_eval_t(dft_ctx *c, const Eval &ev, hipStream_t s) {
     xa.nfield = g.S;
     xa.mode = ev.trial ? XF_TRIAL : XF_PLAIN;
     xa.gate = ev.gate;
+    if (ev.kind >= 0) {
+        xa.roles = c->roles;
+        xa.kind = ev.kind;
+    }
     mark(ev, 0, s);
     launch_x_forward<T>(g, xa, s);
     mark(ev, 1, s);
@@ -219,6 +230,10 @@ void enqueue_eval_t(dft_ctx *c, const Eval &ev, hipStream_t s) {
     x3.lp_out = ev.refresh ? c->lp : nullptr;
     x3.red = c->red;
     x3.gate = ev.gate;
+    if (ev.kind >= 0) {
+        x3.roles = c->roles;
+        x3.kind = ev.kind;
+    }
     launch_x3<T>(g, x3, s);
     mark(ev, 9, s);
     launch_finalize(c->red, x3_nparts<T>(g), nb2, ev.fslot, ev.mslot, c->st,
@@ -237,10 +252,9 @@ void enqueue_n3_t(dft_ctx *c, const double *alpha, double *mslot, const int *gat
     const Geo &g = c->geo;
     const bool diff = c->mixed;
     XFwdArgs xa{};
-    xa.src = c->rho0;
-    xa.g0 = c->g0;
     xa.alpha = alpha;
-    xa.rho_t = c->rho_t;
+    xa.roles = c->roles;
+    xa.kind = ROLE_N3;
     xa.ref = diff ? c->rho_ref : nullptr;
     xa.spec = c->specA;
     xa.nfield = g.S;
@@ -269,10 +283,8 @@ void enqueue_step(dft_ctx *c, hipStream_t s) {
     launch_ctl(st, CTL_BEGIN, s, c->geo.nprob, c->geo.pstride);
     Eval e1;
     e1.trial = true;
-    e1.src = c->rho0;
-    e1.g0 = c->g0;
+    e1.kind = ROLE_B;
     e1.alpha = &st->alpha_trial;
-    e1.g_out = c->gb;
     e1.fslot = &st->f1;
     e1.mslot = &st->m1;
     e1.gate = &st->gate_full1;
@@ -282,28 +294,27 @@ void enqueue_step(dft_ctx *c, hipStream_t s) {
     else enqueue_n3_t<double>(c, &st->alpha_trial, &st->m1, &st->gate_part1, s);
     launch_ctl(st, CTL_AMAX, s, c->geo.nprob, c->geo.pstride);
     Eval ea = e1;
-    ea.g_out = c->ga;
+    ea.kind = ROLE_A;
     ea.fslot = &st->fa;
     ea.mslot = &st->ma;
     ea.gate = &st->gate_a;
     enqueue_eval(c, ea, s);
     launch_ctl(st, CTL_B, s, c->geo.nprob, c->geo.pstride);
     Eval eb = e1;
-    eb.g_out = c->gb;
+    eb.kind = ROLE_B;
     eb.fslot = &st->fb;
     eb.mslot = &st->mb;
     eb.gate = &st->gate_b;
     enqueue_eval(c, eb, s);
     launch_ctl(st, CTL_FIT, s, c->geo.nprob, c->geo.pstride);
     Eval es = e1;
-    es.g_out = c->gs;
+    es.kind = ROLE_S;
     es.fslot = &st->fs;
     es.mslot = &st->ms;
     es.gate = &st->gate_s;
     enqueue_eval(c, es, s);
+    // acceptance rotates the roles: no arrays move
     launch_ctl(st, CTL_ACCEPT, s, c->geo.nprob, c->geo.pstride);
-    launch_update(st, c->rho0, c->g0, c->gb, c->ga, c->gs, (long long)c->geo.S * c->geo.N, s, c->geo.nprob,
-                  c->geo.pstride);
     launch_ctl(st, CTL_END, s, c->geo.nprob, c->geo.pstride);
 }
 
@@ -315,15 +326,14 @@ void enqueue_prime(dft_ctx *c, hipStream_t s, bool gated = false) {
     Eval e;
     e.gate = gate;
     e.trial = true;
-    e.src = c->rho0;
-    e.g0 = c->rho0;      // alpha = 0: rho_t = rho0 exactly
+    e.kind = ROLE_PRIME;   // the current iterate itself (alpha = 0), its image into its role
     e.alpha = &st->alpha_zero;
-    e.g_out = c->g0;
     e.fslot = &st->f0;
     e.mslot = &st->m0;
     e.fp64 = true;
     if (c->mixed) {
-        launch_copy(c->rho_ref, c->rho0, (long long)c->geo.S * c->geo.N, s, c->geo.nprob, c->geo.pstride, gate);
+        launch_copy_current(c->rho_ref, c->roles, (long long)c->geo.S * c->geo.N, s, c->geo.nprob, c->geo.pstride,
+                            gate);
         e.refresh = true;
     }
     enqueue_eval(c, e, s);
@@ -454,6 +464,15 @@ dft_status dft_setup(const dft_params *params, const double *beta_vext, const do
         c->gb = (double *)(w + lay.gb);
         c->gs = (double *)(w + lay.gs);
         c->rho_t = (double *)(w + lay.rho_t);
+        c->roles.rho[0] = c->rho0;
+        c->roles.rho[1] = c->rho_t;
+        c->roles.rho[2] = (double *)(w + lay.rho_t2);
+        c->roles.rho[3] = (double *)(w + lay.rho_t3);
+        c->roles.G[0] = c->g0;
+        c->roles.G[1] = c->gb;
+        c->roles.G[2] = c->ga;
+        c->roles.G[3] = c->gs;
+        c->roles.sel = &c->st->sel;
         c->phi_fix = (double *)(w + lay.phi_fix);
         if (c->mixed) {
             c->rho_ref = (double *)(w + lay.rho_ref);
@@ -569,10 +588,11 @@ dft_status dft_set_reference(dft_ctx *ctx, const double *rho) {
     if (!ctx || !rho) return fail(DFT_E_INVALID_ARG, "ctx or rho is NULL");
     if (!ctx->mixed) return DFT_OK;
     return guarded([&]() -> dft_status {
-        launch_copy(ctx->rho0, rho, (long long)ctx->geo.S * ctx->geo.N, ctx->stream);
         DevState h = read_state(ctx);
         h.tol = 0.0;
+        h.sel = 0;
         write_state(ctx, h);
+        launch_copy(ctx->rho0, rho, (long long)ctx->geo.S * ctx->geo.N, ctx->stream);
         enqueue_prime(ctx, ctx->stream);
         ctx->refreshes += 1;
         ctx->step_rho = nullptr;
@@ -674,8 +694,9 @@ dft_status dft_picard_step(dft_ctx *ctx, double *rho_inout, double *alpha_out, d
         h0.converged = 0;
         write_state(ctx, h0);
         enqueue_step(ctx, ctx->stream);
-        launch_copy(rho_inout, ctx->rho0, SN, ctx->stream);
         DevState h = read_state(ctx);
+        launch_copy(rho_inout, ctx->roles.rho[h.sel & 3], SN, ctx->stream);
+        HIPCHK(hipStreamSynchronize(ctx->stream));
         if (alpha_out) *alpha_out = h.alpha_acc;
         if (norm_out) *norm_out = h.r;
         return status_from(h);
@@ -731,7 +752,7 @@ dft_status dft_solve(dft_ctx *ctx, double *rho_inout, double tol, int32_t max_it
             }
             r_prev = h.r;
         }
-        launch_copy(rho_inout, ctx->rho0, SN, ctx->stream);
+        launch_copy(rho_inout, ctx->roles.rho[h.sel & 3], SN, ctx->stream);
         HIPCHK(hipStreamSynchronize(ctx->stream));
         ctx->step_rho = rho_inout;
         if (iters_out) *iters_out = (int32_t)h.iters;
@@ -763,8 +784,9 @@ dft_status dft_run(dft_ctx *ctx, double *rho_inout, int32_t nsteps, int32_t *ite
         write_state(ctx, h0);
         ensure_graph(ctx);
         for (int k = 0; k < nsteps; ++k) HIPCHK(hipGraphLaunch(ctx->gexec, ctx->stream));
-        launch_copy(rho_inout, ctx->rho0, SN, ctx->stream);
         DevState h = read_state(ctx);
+        launch_copy(rho_inout, ctx->roles.rho[h.sel & 3], SN, ctx->stream);
+        HIPCHK(hipStreamSynchronize(ctx->stream));
         if (iters_out) *iters_out = (int32_t)(h.iters - it0);
         if (norm_out) *norm_out = h.r;
         return status_from(h);
@@ -1300,6 +1322,8 @@ dft_status dft_rfd_reference(dft_ctx *ctx, const double *f, const double *rsc, i
         launch_x_forward<double>(g, xa, s);
         YArgs ya{c->specA, g.S, -1, nullptr};
         launch_y<double>(g, ya, s);
+        // the line-search buffers serve as scratch: the iterate they may hold is given up
+        c->step_rho = nullptr;
         double *inv_den = c->gs;
         int *hit = reinterpret_cast<int *>(c->ga);
         cheb_prep(g.N, rsc, M, cc, dd, inv_den, hit, s);
@@ -1605,7 +1629,7 @@ dft_status dft_solve_batch(dft_batch *batch, double *const *rho_inout, double to
         for (auto &g : batch->groups)
             for (int i : g.idx) {
                 dft_ctx *c = batch->members[i];
-                launch_copy(rho_inout[i], c->rho0, (long long)c->geo.S * c->geo.N, g.stream);
+                launch_copy(rho_inout[i], c->roles.rho[h[i].sel & 3], (long long)c->geo.S * c->geo.N, g.stream);
                 c->step_rho = rho_inout[i];
                 c->stream = s;
             }

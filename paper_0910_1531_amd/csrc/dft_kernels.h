@@ -22,7 +22,7 @@ struct DevState {
     int src;                // accepted sample: 0 = amax, 1 = amax/2, 2 = vertex
     int status;             // dft_status of the device loop (NONFINITE, PACKING)
     int converged;
-    int pad;
+    int sel;                // role of the current iterate's buffers (Roles); accepted samples rotate it
 };
 
 // Pointers every pass kernel needs (device memory inside the workspace).
@@ -73,6 +73,19 @@ enum XFwdMode { XF_PLAIN = 0, XF_TRIAL = 1 };
 enum X2Mode { X2_FULL = 0, X2_N3_ONLY = 1, X2_HESS = 2 };
 enum Z2Mode { Z2_EL = 0, Z2_POISSON = 1, Z2_BALL = 2 };
 
+// Rotating buffers of the line search (one set per problem): densities rho[k] and Picard images
+// G[k], k = 0..3.  The current iterate and its image sit in role *sel; the sample of kind q
+// (ROLE_B: alpha = amax, or 1; ROLE_A: amax / 2; ROLE_S: the fitted step) writes its trial
+// density and image to role (*sel + 1 + q) mod 4, so accepting a sample moves *sel instead of
+// copying the arrays.  ROLE_PRIME evaluates the iterate itself (image into role *sel); ROLE_N3
+// forms the trial point at alpha without writing it.
+enum RoleKind { ROLE_B = 0, ROLE_A = 1, ROLE_S = 2, ROLE_PRIME = 3, ROLE_N3 = 4 };
+struct Roles {
+    double *rho[4];
+    double *G[4];
+    const int *sel;           // null: the plain pointers of the pass arguments are used
+};
+
 struct XFwdArgs {
     const double *src;        // [S][N] input (plain) or rho0 (trial)
     const double *g0;         // [S][N] Picard image (trial)
@@ -83,6 +96,8 @@ struct XFwdArgs {
     int nfield;               // fields to transform
     int mode;
     const int *gate;
+    Roles roles;              // trial mode with roles.sel: src, g0 and rho_t from the roles (kind)
+    int kind;
 };
 
 struct YArgs {
@@ -142,6 +157,8 @@ struct X3Args {
     double *lp_out;           // FP64 refresh: base + E, may be null
     RedBufs red;
     const int *gate;
+    Roles roles;              // with roles.sel: rho_t and g_out from the roles (kind)
+    int kind;
 };
 
 // Launchers (precision T = double or float of the transforms).
@@ -184,10 +201,6 @@ void launch_finalize(const RedBufs &r, int nf, int nm, double *fslot, double *ms
 enum CtlOp { CTL_BEGIN = 0, CTL_AMAX = 1, CTL_B = 2, CTL_FIT = 3, CTL_ACCEPT = 4, CTL_END = 5, CTL_PRIME = 6 };
 void launch_ctl(DevState *st, int op, hipStream_t s, int nprob = 1, long long pstride = 0);
 
-// rho0 <- rho0 + alpha (G0 - rho0); G0 <- G_src (src chosen on device).
-void launch_update(DevState *st, double *rho0, double *g0, const double *gb, const double *ga, const double *gs,
-                   long long count, hipStream_t s, int nprob = 1, long long pstride = 0);
-
 // Setup helpers: base_k = mu_k - beta V_k - z_k phi_fixed (-inf where V = +inf), and
 // per-block counts of fluid nodes.
 void launch_make_base(const Consts *cs, int S, long long N, const double *vext, const double *phi_fixed,
@@ -199,6 +212,9 @@ void launch_sum_to(const double *part, int n, double *dst, hipStream_t s);
 void launch_copy_states(void *dst, long long dst_stride, const void *src, long long src_stride, int nrec,
                         hipStream_t s);
 void launch_set_gates(DevState *first, long long stride, int nrec, const int *gates, hipStream_t s);
+// dst <- the current iterate's density (role *sel) of every problem (gated as launch_copy).
+void launch_copy_current(double *dst, const Roles &roles, long long count, hipStream_t s, int nprob,
+                         long long pstride, const int *gate);
 void launch_copy(double *dst, const double *src, long long count, hipStream_t s, int nprob = 1,
                  long long pstride = 0, const int *gate = nullptr);
 

@@ -94,6 +94,7 @@ __global__ __launch_bounds__(NT) void k_x_forward(Geo g_in, XFwdArgs a, int P) {
     }
     const Geo &g = g_in;
     if (gated_off(a.gate)) return;
+    resolve_roles(a);
     extern __shared__ unsigned char smem_raw[];
     cx<T> *tile = reinterpret_cast<cx<T> *>(smem_raw);
     const int f = blockIdx.y;
@@ -744,6 +745,7 @@ __global__ __launch_bounds__(NT) void k_x3(Geo g_in, X3Args a, int P) {
     }
     const Geo &g = g_in;
     if (gated_off(a.gate)) return;
+    resolve_roles(a);
     extern __shared__ unsigned char smem_raw[];
     cx<T> *tile = reinterpret_cast<cx<T> *>(smem_raw);
     const Consts &c = *g.cs;
@@ -1130,6 +1132,9 @@ __global__ void k_ctl(DevState *st, int op, int nprob, long long pstride) {
             s.m0 = bm;
             s.src = src;
             s.gate_upd = 1;
+            // the accepted sample's trial density (rho0 + alpha_acc (g0 - rho0), formed by the x
+            // pass as the update would form it) and its image become the iterate: a role change
+            s.sel = (s.sel + 1 + src) & 3;
             if (s.alpha_acc >= 0.5 * s.cap) s.cap = fmin(1.0, 2.0 * s.cap);
             s.iters += 1;
         } else {
@@ -1152,46 +1157,6 @@ __global__ void k_ctl(DevState *st, int op, int nprob, long long pstride) {
 void launch_ctl(DevState *st, int op, hipStream_t s, int nprob, long long pstride) {
     hipLaunchKernelGGL(k_ctl, dim3((nprob + 63) / 64), dim3(64), 0, s, st, op, nprob, pstride);
     check_launch("ctl");
-}
-
-__global__ __launch_bounds__(NT) void k_update(const DevState *st, double *rho0, double *g0, const double *gb,
-                                               const double *ga, const double *gs, long long count, long long pstride) {
-    const long long off = (long long)blockIdx.y * pstride;
-    st = shp(st, off);
-    if (!st->gate_upd) return;
-    rho0 = shp(rho0, off);
-    g0 = shp(g0, off);
-    const double alpha = st->alpha_acc;
-    const int src = st->src;
-    const double *gsrc = shp(src == 0 ? gb : (src == 1 ? ga : gs), off);
-    // pairs of values per thread (16-byte accesses; the arrays are 256-byte aligned), odd tail last
-    typedef double d2 __attribute__((ext_vector_type(2)));
-    const long long npair = count / 2;
-    d2 *r2 = reinterpret_cast<d2 *>(rho0);
-    d2 *g2 = reinterpret_cast<d2 *>(g0);
-    const d2 *s2 = reinterpret_cast<const d2 *>(gsrc);
-    for (long long i = (long long)blockIdx.x * NT + threadIdx.x; i < npair; i += (long long)gridDim.x * NT) {
-        const d2 r = r2[i], g = g2[i], n = s2[i];
-        d2 o;
-        o.x = fma(alpha, g.x - r.x, r.x);
-        o.y = fma(alpha, g.y - r.y, r.y);
-        r2[i] = o;
-        g2[i] = n;
-    }
-    if ((count & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
-        const long long i = count - 1;
-        const double r = rho0[i];
-        rho0[i] = fma(alpha, g0[i] - r, r);
-        g0[i] = gsrc[i];
-    }
-}
-
-void launch_update(DevState *st, double *rho0, double *g0, const double *gb, const double *ga, const double *gs,
-                   long long count, hipStream_t s, int nprob, long long pstride) {
-    const long long nb = std::max<long long>(1, std::min<long long>(ceil_div(count / 2, NT), 16384));
-    hipLaunchKernelGGL(k_update, dim3((unsigned)nb, (unsigned)nprob), dim3(NT), 0, s, st, rho0, g0, gb, ga, gs, count,
-                       pstride);
-    check_launch("update");
 }
 
 struct BaseArgs {
@@ -1262,6 +1227,24 @@ __global__ __launch_bounds__(NT) void k_copy(double *dst, const double *src, lon
     dst = shp(dst, off);
     src = shp(src, off);
     for (long long i = (long long)blockIdx.x * NT + threadIdx.x; i < n; i += (long long)gridDim.x * NT) dst[i] = src[i];
+}
+
+__global__ __launch_bounds__(NT) void k_copy_current(double *dst, Roles roles, long long n, long long pstride,
+                                                     const int *gate) {
+    const long long off = (long long)blockIdx.y * pstride;
+    if (gated_off(shp(gate, off))) return;
+    dst = shp(dst, off);
+    roles = shift(roles, off);
+    const double *src = role_pick(roles.rho, role_sel(roles.sel));
+    for (long long i = (long long)blockIdx.x * NT + threadIdx.x; i < n; i += (long long)gridDim.x * NT) dst[i] = src[i];
+}
+
+void launch_copy_current(double *dst, const Roles &roles, long long count, hipStream_t s, int nprob,
+                         long long pstride, const int *gate) {
+    const long long nb = std::min<long long>(ceil_div(count, NT), 8192);
+    hipLaunchKernelGGL(k_copy_current, dim3((unsigned)nb, (unsigned)nprob), dim3(NT), 0, s, dst, roles, count, pstride,
+                       gate);
+    check_launch("copy current");
 }
 
 void launch_copy(double *dst, const double *src, long long count, hipStream_t s, int nprob, long long pstride,

@@ -33,10 +33,41 @@ __device__ __forceinline__ RedBufs shift(RedBufs r, long long o) {
     r.fpart = shp(r.fpart, o); r.mpart = shp(r.mpart, o); r.fflag = shp(r.fflag, o); r.mflag = shp(r.mflag, o);
     return r;
 }
+__device__ __forceinline__ Roles shift(Roles r, long long o) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        r.rho[k] = shp(r.rho[k], o);
+        r.G[k] = shp(r.G[k], o);
+    }
+    r.sel = shp(r.sel, o);
+    return r;
+}
 __device__ __forceinline__ XFwdArgs shift(XFwdArgs a, long long o) {
     a.src = shp(a.src, o); a.g0 = shp(a.g0, o); a.alpha = shp(a.alpha, o); a.rho_t = shp(a.rho_t, o);
-    a.ref = shp(a.ref, o); a.spec = shp(a.spec, o); a.gate = shp(a.gate, o);
+    a.ref = shp(a.ref, o); a.spec = shp(a.spec, o); a.gate = shp(a.gate, o); a.roles = shift(a.roles, o);
     return a;
+}
+// Entry k of a role table, chosen by selects (a run-time index into the argument array would
+// put the arguments in scratch memory); k is uniform over the launch.
+template <typename P>
+__device__ __forceinline__ P *role_pick(P *const (&t)[4], int k) {
+    return k == 0 ? t[0] : (k == 1 ? t[1] : (k == 2 ? t[2] : t[3]));
+}
+// The problem's current role, read once per wave into a scalar register.
+__device__ __forceinline__ int role_sel(const int *sel) { return __builtin_amdgcn_readfirstlane(*sel) & 3; }
+
+// The buffers of a line-search pass from the problem's roles (after shift, past the gate).
+__device__ __forceinline__ void resolve_roles(XFwdArgs &a) {
+    if (!a.roles.sel) return;
+    const int s = role_sel(a.roles.sel);
+    a.src = role_pick(a.roles.rho, s);
+    if (a.kind == ROLE_PRIME) {
+        a.g0 = role_pick(a.roles.rho, s);
+        a.rho_t = nullptr;
+    } else {
+        a.g0 = role_pick(a.roles.G, s);
+        a.rho_t = a.kind == ROLE_N3 ? nullptr : role_pick(a.roles.rho, (s + 1 + a.kind) & 3);
+    }
 }
 __device__ __forceinline__ YArgs shift(YArgs a, long long o) {
     a.spec = shp(a.spec, o); a.gate = shp(a.gate, o);
@@ -60,7 +91,15 @@ __device__ __forceinline__ X3Args shift(X3Args a, long long o) {
     a.specA = shp(a.specA, o); a.addend = shp(a.addend, o); a.raw_out = shp(a.raw_out, o);
     a.base = shp(a.base, o); a.rho_t = shp(a.rho_t, o); a.g_out = shp(a.g_out, o); a.e_out = shp(a.e_out, o);
     a.e_phi = shp(a.e_phi, o); a.lp_out = shp(a.lp_out, o); a.red = shift(a.red, o); a.gate = shp(a.gate, o);
+    a.roles = shift(a.roles, o);
     return a;
+}
+__device__ __forceinline__ void resolve_roles(X3Args &a) {
+    if (!a.roles.sel) return;
+    const int s = role_sel(a.roles.sel);
+    const int t = a.kind == ROLE_PRIME ? s : (s + 1 + a.kind) & 3;
+    a.rho_t = role_pick(a.roles.rho, t);
+    a.g_out = role_pick(a.roles.G, t);
 }
 // Geometry of problem `prob`: its constants and spectral tables move with its workspace;
 // twiddles are shared.
