@@ -179,16 +179,45 @@ def _kernel_sources_sha256():
     return h.hexdigest()
 
 
-def measured_traffic(pass_name, fp32, n):
+def _fit_threads(L, P, per, cap):
+    t = 64
+    while 2 * t <= cap and 2 * t * per <= L * P:
+        t *= 2
+    return t
+
+
+def pass_kernel(pass_name, fp32, n, schedule, S):
+    """Name of the kernel that runs the pass at n^3 (compiled length n) under the autotuned schedule,
+    as rocprofv3 reports it; None for passes with several kernels or shapes not covered."""
+    T = "float" if fp32 else "double"
+    if pass_name == "x_fwd":
+        return f"dft::k_x1c<{T}, {n}>"
+    if pass_name == "x_el":
+        return f"dft::k_x3c<{T}, {n}>"
+    if pass_name == "x_fmt":
+        if n in (16, 64, 256):   # paired-wave tiles
+            return f"dft::k_x2p<{T}, {n}>"
+        return f"dft::k_x2c<{T}, {n}, {1 if fp32 else 0}>"
+    widths = {0: 8, 1: 4, 2: 16} if fp32 else {0: 4, 1: 2, 2: 8}
+    if pass_name == "z_weights":
+        v = schedule["z_weights"][1 if fp32 else 0]
+        if v >= 3:
+            return None   # split shapes: a plain z pass and k_z1s
+        P = widths[v]
+        return f"dft::k_z1c<{T}, {n}, {P}, {_fit_threads(n, P, 4, 512)}, {S}>"
+    if pass_name == "z_back_es":
+        P = widths[schedule["z_back"][1 if fp32 else 0]]
+        return f"dft::k_z2c<{T}, {n}, {P}, {_fit_threads(n, P, 4, 512)}>"
+    return None
+
+
+def measured_traffic(pass_name, fp32, n, schedule, S):
     """HBM bytes per launch of the pass's kernel from the committed rocprofv3 counters
     (profiles/traffic_pore256.txt), or None when they were taken on other kernel sources."""
-    kern = {"x_fwd": "k_x1c", "x_fmt": "k_x2c", "x_el": "k_x3c"}.get(pass_name)
+    want = pass_kernel(pass_name, fp32, n, schedule, S)
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "traffic_pore256.txt")
-    if kern is None or n != 256 or not os.path.exists(path):
+    if want is None or n != 256 or not os.path.exists(path):
         return None
-    want = f"dft::{kern}<{'float' if fp32 else 'double'}, {n}>"
-    if kern == "k_x2c":   # the FP32-mixed evaluation runs the FP32 nodewise-difference instantiation
-        want = f"dft::k_x2c<{'float' if fp32 else 'double'}, {n}, {1 if fp32 else 0}>"
     sha, found = None, None
     with open(path) as fh:
         for line in fh:
@@ -575,7 +604,9 @@ def main():
         "rho_rel_diff_mixed_vs_fp64": rho_err,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic(dom, fp32, args.n), "traffic_unit": "bytes per launch",
+                     "traffic": measured_traffic(dom, fp32, args.n, head["schedule"], prob.nspecies),
+                     "traffic_unit": "bytes per launch",
+                     "kernel_name": pass_kernel(dom, fp32, args.n, head["schedule"], prob.nspecies),
                      "algorithmic_bytes": pb[dom], "copy_ceiling_GBs": round(ceiling, 1),
                      "frac_of_copy_ceiling": round(achieved / ceiling, 4)},
         "passes": passes,
