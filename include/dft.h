@@ -331,10 +331,11 @@ dft_status dft_newton(dft_ctx *ctx, double *rho, void *adj_ws, size_t adj_ws_byt
  *   rsc    device [N] FP64, R_SC(x) in the length unit, positive and finite.
  *   nodes  1 .. DFT_RFD_MAX_NODES.
  *   f_ref  device [S][N] FP64 out; may be the same buffer as f.
- * FP64 in either precision.  Uses the ctx's spectral and line-search scratch buffers (the
- * iterate, its G and the captured step are kept); reads the R_SC range back to the host, so it
- * synchronizes the ctx stream once.  Errors: DFT_E_INVALID_ARG (NULL pointers, nodes out of
- * range, an R_SC that is not positive and finite, a batch group ctx).
+ * FP64 in either precision.  Uses the ctx's spectral buffers and the line-search buffers that do
+ * not hold the current iterate (the iterate, its G and the captured step are kept); reads the
+ * line-search state and the R_SC range back to the host, so it synchronizes the ctx stream.
+ * Errors: DFT_E_INVALID_ARG (NULL pointers, nodes out of range, an R_SC that is not positive and
+ * finite, a batch group ctx).
  */
 #define DFT_RFD_MAX_NODES 128
 dft_status dft_rfd_reference(dft_ctx *ctx, const double *f, const double *rsc, int32_t nodes, double *f_ref);

@@ -1322,10 +1322,11 @@ dft_status dft_rfd_reference(dft_ctx *ctx, const double *f, const double *rsc, i
         launch_x_forward<double>(g, xa, s);
         YArgs ya{c->specA, g.S, -1, nullptr};
         launch_y<double>(g, ya, s);
-        // the line-search buffers serve as scratch: the iterate they may hold is given up
-        c->step_rho = nullptr;
-        double *inv_den = c->gs;
-        int *hit = reinterpret_cast<int *>(c->ga);
+        // scratch in the line-search roles that do not hold the current iterate (kept)
+        const int sel = read_state(c).sel & 3;
+        double *inv_den = c->roles.G[(sel + 1) & 3];
+        int *hit = reinterpret_cast<int *>(c->roles.G[(sel + 2) & 3]);
+        double *raw = c->roles.rho[(sel + 1) & 3];
         cheb_prep(g.N, rsc, M, cc, dd, inv_den, hit, s);
         for (int m = 0; m < M; ++m) {
             const double Rm = cc + dd * std::cos(M_PI * (2.0 * m + 1.0) / (2.0 * M));
@@ -1342,9 +1343,9 @@ dft_status dft_rfd_reference(dft_ctx *ctx, const double *f, const double *rsc, i
             x3.specA = c->specB;
             x3.nfield = g.S;
             x3.raw = 1;
-            x3.raw_out = c->rho_t;
+            x3.raw_out = raw;
             launch_x3<double>(g, x3, s);
-            cheb_accum(g.N, g.S, m, M, cc, dd, rsc, inv_den, hit, c->rho_t, f_ref, m == 0, s);
+            cheb_accum(g.N, g.S, m, M, cc, dd, rsc, inv_den, hit, raw, f_ref, m == 0, s);
         }
         return DFT_OK;
     });

@@ -117,3 +117,21 @@ def test_pore128_sampled_points():
     err = np.abs(got - want).max() / np.abs(f).max()
     _say(f"pore128: {M} nodes, max error at {len(pts)} sampled points {err:.1e}")
     assert err < 1e-11
+
+
+def test_picard_run_continues_across_the_screening_call():
+    # The screening operator borrows the line-search buffers that do not hold the current iterate,
+    # so a Picard run continued after it equals one without it (the buffers' roles have rotated
+    # during the first steps).
+    p = W.charged_sphere(n=32, h=0.1)
+    a, b = from_problem(p), from_problem(p)
+    xa = _dev(p.initial_density())
+    xb = xa.clone()
+    a.run(xa, 4)
+    b.run(xb, 4)
+    R = W.screening_radius(p, 0.3, 0.6, seed=1)
+    b.rfd_reference(_dev(p.initial_density()), _dev(R), 8)
+    acc_a, ra = a.run(xa, 4)
+    acc_b, rb = b.run(xb, 4)
+    _say(f"sphere32: 4 + 4 steps, accepted {acc_a} / {acc_b}, r {ra:.3e} / {rb:.3e}")
+    assert acc_a == acc_b and ra == rb and torch.equal(xa, xb)
