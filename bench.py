@@ -623,8 +623,11 @@ def main():
         "cpu_baseline": cpu,
         "extras": extras,
         "fft_schedule": {"shapes": {k: {"fp64": v[0], "fp32": v[1]} for k, v in head["schedule"].items()},
-                         "legend": "autotuned tile shape per pass; y: 0/1/2/3/4 = 16/8/32/16/8 (FP32) or 8/4/16/8/4 (FP64) "
-                                   "columns per tile, shapes 3-4 with half the threads; z: 0/1/2 = 8/4/16 (FP32) or 4/2/8 (FP64) columns per tile, "
+                         "legend": "autotuned tile shape per pass (y: inverse y of the weighted densities; y_fwd2: forward "
+                                   "y of their derivatives; y_species: y passes of the species; z_plain: plain z pass); "
+                                   "y passes and z_plain: 0/1/2/3/4 = 16/8/32/16/8 (FP32) or 8/4/16/8/4 (FP64) "
+                                   "columns per tile, shapes 3-4 with half the threads, 5-9 the same with one LDS buffer "
+                                   "instead of two; z: 0/1/2 = 8/4/16 (FP32) or 4/2/8 (FP64) columns per tile, "
                                    "z_weights 3/4/5 = the same widths after a separate plain z pass of the species"},
     }
     print(json.dumps(line), flush=True)

@@ -380,17 +380,21 @@ dft_status dft_get_stats(dft_ctx *ctx, dft_stats *out);
 
 /*
  * Launch shapes of the FFT pass kernels (batched FFT schedules, Section 4's many
- * transforms per step): for each pass in {y, plain z, z weighted densities, z
- * back-convolution} and each transform precision {FP64, FP32}, the index of the tile
- * shape in use, as DFT_SCHEDULE_LEN int32 laid out [pass][precision].  y and plain z: 5
- * shapes; z weighted densities: 6 (three tile widths fused with the forward z transform
- * of the species, then the same widths after a separate plain z pass); z back-convolution: 3.  dft_setup picks
- * them by timing every shape on the device (the autotuner; DFT_FLAG_NO_AUTOTUNE keeps
+ * transforms per step): for each tunable pass and each transform precision {FP64, FP32},
+ * the index of the tile shape in use, as DFT_SCHEDULE_LEN int32 laid out [pass][precision].
+ * Passes, in order: 0 the inverse y pass of the ten weighted-density spectra, 1 the plain z
+ * pass, 2 the z pass of the weighted densities (Z1), 3 the z back-convolution (Z2), 4 the
+ * forward y pass of the ten derivative spectra, 5 the y passes of the species spectra.
+ * y passes and plain z: 10 shapes (five tile widths / thread counts with two LDS buffers,
+ * then the same five with one); Z1: 6 (three tile widths fused with the forward z transform
+ * of the species, then the same widths after a separate plain z pass); Z2: 3.  dft_setup
+ * picks them by timing every shape on the device (the autotuner; DFT_FLAG_NO_AUTOTUNE keeps
  * shape 0).  Every shape of a pass performs the same arithmetic in the same order, so the
  * shapes change run time only, never results.  dft_set_schedule validates each index
  * (DFT_E_INVALID_ARG if out of range) and drops the ctx's captured step graph.
  */
-#define DFT_SCHEDULE_LEN 8
+#define DFT_TUNE_PASSES 6
+#define DFT_SCHEDULE_LEN (2 * DFT_TUNE_PASSES)
 dft_status dft_get_schedule(const dft_ctx *ctx, int32_t *shapes_out);
 dft_status dft_set_schedule(dft_ctx *ctx, const int32_t *shapes);
 

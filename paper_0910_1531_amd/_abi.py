@@ -22,10 +22,10 @@ FLAG_CUTOFF_LAMBDA = 2
 FLAG_NO_AUTOTUNE = 4
 HS_RSLT, HS_ROSENFELD, HS_WHITE_BEAR = 0, 1, 2
 HS_FUNCTIONALS = {"rslt": HS_RSLT, "rosenfeld": HS_ROSENFELD, "whitebear": HS_WHITE_BEAR}
-SCHEDULE_LEN = 8
+SCHEDULE_LEN = 12
 ADJOINT_NOALLOC_MAX_BYTES = 64 << 20
 RFD_MAX_NODES = 128
-TUNE_PASSES = ["y", "z_plain", "z_weights", "z_back"]
+TUNE_PASSES = ["y", "z_plain", "z_weights", "z_back", "y_fwd2", "y_species"]
 
 D8 = ctypes.c_double * MAX_SPECIES
 

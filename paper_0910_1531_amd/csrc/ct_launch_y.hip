@@ -5,26 +5,32 @@
 
 namespace dft {
 
-// Shape v of the y kernel for precision T: tile width, and values per thread (8, or 16 for
-// shapes 3 and 4: half the threads, two butterflies per thread and stage).
+// Shape v of the y kernel for precision T: tile width, values per thread (8, or 16 for shapes
+// 3 and 4: half the threads, two butterflies per thread and stage) and LDS buffers (shapes 5-9:
+// shapes 0-4 with one buffer, so more tiles fit per CU at a second barrier per exchange).
 template <typename T> constexpr int y_width(int v);
-template <> constexpr int y_width<float>(int v) { return (v == 0 || v == 3) ? 16 : (v == 1 || v == 4) ? 8 : 32; }
-template <> constexpr int y_width<double>(int v) { return (v == 0 || v == 3) ? 8 : (v == 1 || v == 4) ? 4 : 16; }
-constexpr int y_per_thread(int v) { return v >= 3 ? 16 : 8; }
-constexpr int kYVariants = 5;
+template <> constexpr int y_width<float>(int v) {
+    return (v % 5 == 0 || v % 5 == 3) ? 16 : (v % 5 == 1 || v % 5 == 4) ? 8 : 32;
+}
+template <> constexpr int y_width<double>(int v) {
+    return (v % 5 == 0 || v % 5 == 3) ? 8 : (v % 5 == 1 || v % 5 == 4) ? 4 : 16;
+}
+constexpr int y_per_thread(int v) { return v % 5 >= 3 ? 16 : 8; }
+constexpr int kYVariants = 10;
 constexpr int kLdsCap = 65536;
 
-// LDS buffers of shape (T, L, P): 2 when two tiles fit, else 1, 0 when not even one does.
-template <typename T, int L, int P>
+// LDS buffers of shape v (T, L, P): 2 when two tiles fit and the shape asks for two, else 1, 0
+// when not even one tile does.
+template <typename T, int L, int P, int V>
 constexpr int y_buffers() {
     constexpr int tile = L * P * (int)sizeof(cx<T>);
-    return 2 * tile <= kLdsCap ? 2 : (tile <= kLdsCap ? 1 : 0);
+    return (V < 5 && 2 * tile <= kLdsCap) ? 2 : (tile <= kLdsCap ? 1 : 0);
 }
 
 template <typename T, int L, int V>
 static bool launch_yc_var(const Geo &g, const YArgs &a, hipStream_t s) {
     constexpr int P = y_width<T>(V);
-    constexpr int NB = y_buffers<T, L, P>();
+    constexpr int NB = y_buffers<T, L, P, V>();
     if constexpr (NB == 0) {
         return false;
     } else {
@@ -50,6 +56,11 @@ static bool launch_yc_len(const Geo &g, const YArgs &a, hipStream_t s, int v) {
         case 2: if (launch_yc_var<T, L, 2>(g, a, s)) return true; break;
         case 3: if (launch_yc_var<T, L, 3>(g, a, s)) return true; break;
         case 4: if (launch_yc_var<T, L, 4>(g, a, s)) return true; break;
+        case 5: if (launch_yc_var<T, L, 5>(g, a, s)) return true; break;
+        case 6: if (launch_yc_var<T, L, 6>(g, a, s)) return true; break;
+        case 7: if (launch_yc_var<T, L, 7>(g, a, s)) return true; break;
+        case 8: if (launch_yc_var<T, L, 8>(g, a, s)) return true; break;
+        case 9: if (launch_yc_var<T, L, 9>(g, a, s)) return true; break;
         default: break;
     }
     return launch_yc_var<T, L, 0>(g, a, s);
@@ -57,7 +68,9 @@ static bool launch_yc_len(const Geo &g, const YArgs &a, hipStream_t s, int v) {
 
 template <typename T>
 bool launch_y_ct(const Geo &g, const YArgs &a, hipStream_t s) {
-    const int pass = a.axis == 2 ? TUNE_YZ : TUNE_Y;
+    // the ten weighted-density / derivative spectra (compact or not) or the species spectra
+    const bool ten = a.vec != 0 || a.nfield == DFT_NALPHA;
+    const int pass = a.axis == 2 ? TUNE_YZ : (ten ? (a.dir > 0 ? TUNE_Y : TUNE_YF) : TUNE_YS);
     const int v = g.tune[pass][std::is_same<T, float>::value ? 1 : 0];
     switch (a.axis == 2 ? g.nz : g.ny) {
 #define DFT_CASE(n) case n: return launch_yc_len<T, n>(g, a, s, v);

@@ -1690,7 +1690,7 @@ dft_status dft_get_stats(dft_ctx *ctx, dft_stats *out) {
 
 dft_status dft_get_schedule(const dft_ctx *ctx, int32_t *shapes_out) {
     if (!ctx || !shapes_out) return fail(DFT_E_INVALID_ARG, "ctx or shapes_out is NULL");
-    for (int p = 0; p < 4; ++p)
+    for (int p = 0; p < DFT_TUNE_PASSES; ++p)
         for (int t = 0; t < 2; ++t) shapes_out[2 * p + t] = ctx->geo.tune[p][t];
     return DFT_OK;
 }
@@ -1698,9 +1698,10 @@ dft_status dft_get_schedule(const dft_ctx *ctx, int32_t *shapes_out) {
 dft_status dft_set_schedule(dft_ctx *ctx, const int32_t *shapes) {
     if (!ctx || !shapes) return fail(DFT_E_INVALID_ARG, "ctx or shapes is NULL");
     const Geo &g = ctx->geo;
-    const int nv[4] = {g.ny > 1 ? y_ct_variants(g.ny, false) : 0, g.nz > 1 ? y_ct_variants(g.nz, false) : 0,
-                       z1_ct_variants(g.nz), z_ct_variants(g.nz)};
-    for (int p = 0; p < 4; ++p)
+    const int ny_v = g.ny > 1 ? y_ct_variants(g.ny, false) : 0;
+    const int nv[DFT_TUNE_PASSES] = {ny_v, g.nz > 1 ? y_ct_variants(g.nz, false) : 0, z1_ct_variants(g.nz),
+                                     z_ct_variants(g.nz), ny_v, ny_v};
+    for (int p = 0; p < DFT_TUNE_PASSES; ++p)
         for (int t = 0; t < 2; ++t) {
             const int v = shapes[2 * p + t];
             if (v < 0 || v >= std::max(nv[p], 1)) {
@@ -1710,7 +1711,7 @@ dft_status dft_set_schedule(dft_ctx *ctx, const int32_t *shapes) {
             }
         }
     return guarded([&]() -> dft_status {
-        for (int p = 0; p < 4; ++p)
+        for (int p = 0; p < DFT_TUNE_PASSES; ++p)
             for (int t = 0; t < 2; ++t) ctx->geo.tune[p][t] = shapes[2 * p + t];
         // the captured step graph holds the old launches
         if (ctx->gexec) HIPCHK(hipGraphExecDestroy(ctx->gexec));

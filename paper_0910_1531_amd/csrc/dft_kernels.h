@@ -17,7 +17,7 @@ struct DevState {
     double r, tol, nfluid, eta_cap;
     double best_f;
     long long iters, rejected, gevals, n3evals, max_iter;
-    int gate_full1, gate_part1, gate_a, gate_b, gate_s, gate_upd, gate_run, gate_one;
+    int gate_full1, gate_part1, gate_a, gate_b, gate_s, gate_run, gate_one;
     int gate_refresh;       // batches: this problem takes the next FP64 reference evaluation
     int src;                // accepted sample: 0 = amax, 1 = amax/2, 2 = vertex
     int status;             // dft_status of the device loop (NONFINITE, PACKING)
@@ -53,11 +53,13 @@ struct Geo {
     int ntab = 0;
     // Launch shape of the compiled-length kernels per tunable pass and precision
     // ([pass][0] FP64, [pass][1] FP32); 0 is the default shape.
-    int tune[4][2] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+    int tune[DFT_TUNE_PASSES][2] = {};
 };
 
 // Passes whose launch shape the autotuner picks.
-enum TunePass { TUNE_Y = 0, TUNE_YZ = 1, TUNE_Z1 = 2, TUNE_Z2 = 3 };
+// Tunable passes: the inverse y pass of the ten weighted-density spectra, the plain z pass, Z1,
+// Z2, the forward y pass of the ten derivative spectra, the y passes of the species spectra.
+enum TunePass { TUNE_Y = 0, TUNE_YZ = 1, TUNE_Z1 = 2, TUNE_Z2 = 3, TUNE_YF = 4, TUNE_YS = 5 };
 
 // Where the reductions of one residual evaluation go.
 struct RedBufs {

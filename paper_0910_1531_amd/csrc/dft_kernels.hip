@@ -1088,7 +1088,6 @@ __global__ void k_ctl(DevState *st, int op, int nprob, long long pstride) {
         s.gate_a = run;
         s.gate_b = 0;
         s.gate_s = 0;
-        s.gate_upd = 0;
         s.alpha_trial = 1.0;
         break;
     }
@@ -1126,12 +1125,11 @@ __global__ void k_ctl(DevState *st, int op, int nprob, long long pstride) {
         if (s.gate_s && (s.fs < bf || (s.fs == bf && s.t > bt))) { bf = s.fs; bt = s.t; bm = s.ms; src = 2; }
         s.best_f = bf;
         if (bf < s.f0 || s.amax <= kCapFloor) {
-            if (!isfinite(bf)) { s.status = DFT_E_NONFINITE; s.gate_upd = 0; s.gate_run = 0; break; }
+            if (!isfinite(bf)) { s.status = DFT_E_NONFINITE; s.gate_run = 0; break; }
             s.alpha_acc = bt * s.amax;
             s.f0 = bf;
             s.m0 = bm;
             s.src = src;
-            s.gate_upd = 1;
             // the accepted sample's trial density (rho0 + alpha_acc (g0 - rho0), formed by the x
             // pass as the update would form it) and its image become the iterate: a role change
             s.sel = (s.sel + 1 + src) & 3;
@@ -1139,7 +1137,6 @@ __global__ void k_ctl(DevState *st, int op, int nprob, long long pstride) {
             s.iters += 1;
         } else {
             s.alpha_acc = 0.0;
-            s.gate_upd = 0;
             s.cap = fmax(0.25 * s.amax, kCapFloor);
             s.rejected += 1;
         }

@@ -30,7 +30,9 @@ std::mutex g_mu;
 
 int variants_of(const Geo &g, int pass) {
     switch (pass) {
-        case TUNE_Y: return g.ny > 1 ? y_ct_variants(g.ny, false) : 0;
+        case TUNE_Y:
+        case TUNE_YF:
+        case TUNE_YS: return g.ny > 1 ? y_ct_variants(g.ny, false) : 0;
         case TUNE_YZ: return g.nz > 1 ? y_ct_variants(g.nz, false) : 0;
         case TUNE_Z1: return z1_ct_variants(g.nz);
         default: return z_ct_variants(g.nz);
@@ -42,12 +44,24 @@ void launch_pass(const Geo &g, const TuneBufs &b, int pass, hipStream_t s) {
     const bool fp32 = sizeof(T) == 4;
     switch (pass) {
         case TUNE_Y: {
-            // the y passes of the weighted densities and their derivatives, the largest ones
+            // the inverse y pass of the weighted densities
             YArgs a{b.specB, DFT_NALPHA, 1, nullptr};
             a.vec = g.compact ? 1 : 0;
             launch_y<T>(g, a, s);
+            break;
+        }
+        case TUNE_YF: {
+            // the forward y pass of their derivatives
             YArgs c{b.specB, DFT_NALPHA, -1, nullptr};
             c.vec = g.compact ? 2 : 0;
+            launch_y<T>(g, c, s);
+            break;
+        }
+        case TUNE_YS: {
+            // the forward and inverse y passes of the species spectra
+            YArgs a{b.specA, g.S, -1, nullptr};
+            launch_y<T>(g, a, s);
+            YArgs c{b.specA, g.S, 1, nullptr};
             launch_y<T>(g, c, s);
             break;
         }
@@ -76,7 +90,7 @@ void launch_pass(const Geo &g, const TuneBufs &b, int pass, hipStream_t s) {
 // Mean time of one launch of the pass with its current shape (best of a few repeats).
 template <typename T>
 float time_pass(const Geo &g, const TuneBufs &b, int pass, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-    constexpr int kReps = 3, kLaunches = 2;
+    constexpr int kReps = 5, kLaunches = 2;
     launch_pass<T>(g, b, pass, s);   // warm-up (code object load, caches)
     float best = 1e30f;
     for (int r = 0; r < kReps; ++r) {
@@ -94,7 +108,7 @@ float time_pass(const Geo &g, const TuneBufs &b, int pass, hipStream_t s, hipEve
 template <typename T>
 void tune_precision(Geo &g, const TuneBufs &b, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     const int t = sizeof(T) == 4 ? 1 : 0;
-    for (int pass = 0; pass < 4; ++pass) {
+    for (int pass = 0; pass < DFT_TUNE_PASSES; ++pass) {
         const int nv = variants_of(g, pass);
         g.tune[pass][t] = 0;
         if (nv <= 1) continue;

@@ -37,7 +37,7 @@ def test_every_shape_gives_the_same_residual(precision):
             sol.set_reference(torch.tensor(p.initial_density(), dtype=torch.float64, device="cuda"))
         g0, r0 = sol.residual(rho)
         g0 = g0.clone()
-        nshape = {"y": 5, "z_plain": 5, "z_weights": 6, "z_back": 3}
+        nshape = {"y": 10, "z_plain": 10, "z_weights": 6, "z_back": 3, "y_fwd2": 10, "y_species": 10}
         for ps, nv in nshape.items():
             for v in range(1, nv):
                 for t in (0, 1):
