@@ -240,12 +240,62 @@ __device__ __forceinline__ constexpr int pair_slot(int a, int b) {
     return a * MS - (a * (a - 1)) / 2 + (b - a);
 }
 
+// The species and pair constants of the products in the arithmetic type, read once per block
+// before any store (read at their uses they would be reloaded and converted after every store,
+// which may alias them).  Pair p = pair_slot(a, b), a <= b.
+template <typename T, int MS>
+struct Z1Const {
+    static constexpr int NPR = MS * (MS + 1) / 2;
+    T R[MS], a0[MS], a1[MS], bath[MS];   // R_j, 1 / (4 pi R_j^2), 1 / (4 pi R_j), N rho_b,j
+    T zz[NPR], scR[NPR], c1[NPR], c0[NPR], cm1[NPR];
+    T four_pi_lB;
+    __device__ __forceinline__ explicit Z1Const(const Consts &c) {
+        constexpr bool F32 = std::is_same<T, float>::value;
+        static_for<MS>([&](auto J) __attribute__((always_inline)) {
+            constexpr int j = J;
+            if constexpr (F32) {
+                R[j] = c.f_R[j];
+                a0[j] = c.f_i4piR2[j];
+                a1[j] = c.f_i4piR[j];
+                bath[j] = c.f_bath_N[j];
+            } else {
+                R[j] = c.R[j];
+                a0[j] = c.i4piR2[j];
+                a1[j] = c.i4piR[j];
+                bath[j] = c.bath_N[j];
+            }
+        });
+        static_for<MS>([&](auto IA) __attribute__((always_inline)) {
+            static_for<MS>([&](auto IB) __attribute__((always_inline)) {
+                constexpr int ia = IA, ib = IB;
+                if constexpr (ib >= ia) {
+                    constexpr int q = pair_slot<MS>(ia, ib), ij = ia * DFT_MAX_SPECIES + ib;
+                    if constexpr (F32) {
+                        zz[q] = c.f_zz[ij];
+                        scR[q] = c.f_sc_R[ij];
+                        c1[q] = c.f_sc_c1[ij];
+                        c0[q] = c.f_sc_c0[ij];
+                        cm1[q] = c.f_sc_cm1[ij];
+                    } else {
+                        zz[q] = c.z[ia] * c.z[ib];
+                        scR[q] = c.sc_R[ij];
+                        c1[q] = c.sc_c1[ij];
+                        c0[q] = c.sc_c0[ij];
+                        cm1[q] = c.sc_cm1[ij];
+                    }
+                }
+            });
+        });
+        four_pi_lB = F32 ? c.f_four_pi_lB : c.four_pi_lB;
+    }
+};
+
 // Products of one node with electrostatics (S <= MS): the species values u at the node (k_x
 // column p of the tile, z element e; ti its offset in a spectrum, ok whether it is a real
 // column), the five weighted sums out in acc, and the node's sums over j of K_ij times the
 // species spectra stored at dst + i NC.  Each unordered pair factor is formed once (K_ij = K_ji).
 template <typename T, int MS>
-__device__ __forceinline__ void z1_node(const Consts &c, bool diff, const ZWave<T> &kw, const Poisson<T> &pd,
+__device__ __forceinline__ void z1_node(const Z1Const<T, MS> &k, bool diff, const ZWave<T> &kw, const Poisson<T> &pd,
                                         const double *tab, long long NC, int S, bool es, int kx0, int p, int e,
                                         bool ok, long long ti, const cx<T> (&u)[MS], cx<T> (&acc)[5], cx<T> *dst) {
     constexpr bool TAB = std::is_same<T, double>::value;
@@ -275,8 +325,8 @@ __device__ __forceinline__ void z1_node(const Consts &c, bool diff, const ZWave<
             cs[j] = T(1);
             w2[j] = w3[j] = T(0);
             if (j < S) {
-                sincos_r(km * T(c.R[j]), &sn[j], &cs[j]);
-                weight_w2_w3_sc<T>(km, T(c.R[j]), sn[j], cs[j], w2[j], w3[j]);
+                sincos_r(km * k.R[j], &sn[j], &cs[j]);
+                weight_w2_w3_sc<T>(km, k.R[j], sn[j], cs[j], w2[j], w3[j]);
             }
         });
         static_for<MS>([&](auto IA) __attribute__((always_inline)) {
@@ -289,9 +339,8 @@ __device__ __forceinline__ void z1_node(const Consts &c, bool diff, const ZWave<
                         // launcher sends the cutoff at lambda_a + lambda_b to the run-time-length kernel)
                         const T sp = sn[ia] * cs[ib] + cs[ia] * sn[ib];
                         const T cp = cs[ia] * cs[ib] - sn[ia] * sn[ib];
-                        const int ij = ia * DFT_MAX_SPECIES + ib;
-                        Kv = screening_hat_sc<T>(km, T(c.sc_R[ij]), sp, cp, T(c.sc_c1[ij]), T(c.sc_c0[ij]),
-                                                 T(c.sc_cm1[ij]));
+                        constexpr int q = pair_slot<MS>(ia, ib);
+                        Kv = screening_hat_sc<T>(km, k.scR[q], sp, cp, k.c1[q], k.c0[q], k.cm1[q]);
                     }
                     K[pair_slot<MS>(ia, ib)] = Kv;
                 }
@@ -303,7 +352,7 @@ __device__ __forceinline__ void z1_node(const Consts &c, bool diff, const ZWave<
     static_for<MS>([&](auto J) __attribute__((always_inline)) {
         constexpr int j = J;
         if (j < S) {
-            const T a0 = T(c.i4piR2[j]), a1 = T(c.i4piR[j]);
+            const T a0 = k.a0[j], a1 = k.a1[j];
             const T m0 = w2[j] * a0, m1 = w2[j] * a1, m4 = w3[j] * a1;
             acc[0].x += u[j].x * m0; acc[0].y += u[j].y * m0;
             acc[1].x += u[j].x * m1; acc[1].y += u[j].y * m1;
@@ -317,7 +366,7 @@ __device__ __forceinline__ void z1_node(const Consts &c, bool diff, const ZWave<
     const bool z0 = !diff && kw.zero(p, e);
     T invD = T(0);
     if constexpr (!TAB)
-        if (!kw.zero(p, e)) invD = T(c.four_pi_lB) * rcp_r(pd.denom(kx0 + p, e));
+        if (!kw.zero(p, e)) invD = k.four_pi_lB * rcp_r(pd.denom(kx0 + p, e));
     static_for<MS>([&](auto IS) __attribute__((always_inline)) {
         constexpr int is = IS;
         if (is < S) {
@@ -325,13 +374,14 @@ __device__ __forceinline__ void z1_node(const Consts &c, bool diff, const ZWave<
             static_for<MS>([&](auto J) __attribute__((always_inline)) {
                 constexpr int j = J;
                 if (j < S) {
-                    const T Kij = K[is <= j ? pair_slot<MS>(is, j) : pair_slot<MS>(j, is)];
-                    const T ux = z0 ? u[j].x - T((double)c.N * c.rho_b[j]) : u[j].x;
+                    constexpr int q = is <= j ? pair_slot<MS>(is, j) : pair_slot<MS>(j, is);
+                    const T Kij = K[q];
+                    const T ux = z0 ? u[j].x - k.bath[j] : u[j].x;
                     if constexpr (TAB) {
                         ea.x += Kij * ux;
                         ea.y += Kij * u[j].y;
                     } else {
-                        const T Pz = invD * T(c.z[is] * c.z[j]);
+                        const T Pz = invD * k.zz[q];
                         ea.x += Kij * ux - Pz * u[j].x;
                         ea.y += (Kij - Pz) * u[j].y;
                     }
@@ -461,6 +511,8 @@ __global__ __launch_bounds__(NTB) void k_z1c(Geo g_in, Z1Args a) {
     const cx<T> *tw = twp<T>(g, 2);
     const bool es = MS > 0 && c.es && !a.n3only;
     const ZWave<T> kw(c, kx0, y);
+    // the products' constants, read before the first store
+    [[maybe_unused]] const Z1Const<T, (MS > 0 ? MS : 1)> kc(c);
     const double *tab = TAB ? g.tab64 + off : nullptr;
     cx<T> acc[NO][5];
     cx<T> v[F::V];
@@ -523,7 +575,7 @@ __global__ __launch_bounds__(NTB) void k_z1c(Geo g_in, Z1Args a) {
             cx<T> u[MS];
 #pragma unroll
             for (int j = 0; j < MS; ++j) u[j] = us[j][i];
-            z1_node<T, MS>(c, a.diff != 0, kw, pd, tab, NC, S, es, kx0, p, e, ok, ti, u, acc[i],
+            z1_node<T, MS>(kc, a.diff != 0, kw, pd, tab, NC, S, es, kx0, p, e, ok, ti, u, acc[i],
                            reinterpret_cast<cx<T> *>(a.specA) + off + ti);
         });
     }
@@ -562,6 +614,8 @@ __global__ __launch_bounds__(NTB) void k_z1s(Geo g_in, Z1Args a) {
     const cx<T> *tw = twp<T>(g, 2);
     const bool es = MS > 0 && c.es && !a.n3only;
     const ZWave<T> kw(c, kx0, y);
+    // the products' constants, read before the first store
+    [[maybe_unused]] const Z1Const<T, (MS > 0 ? MS : 1)> kc(c);
     const double *tab = TAB ? g.tab64 + off : nullptr;
     cx<T> acc[NO][5];
     if constexpr (MS == 0) {
@@ -598,7 +652,7 @@ __global__ __launch_bounds__(NTB) void k_z1s(Geo g_in, Z1Args a) {
             cx<T> u[MS];
 #pragma unroll
             for (int j = 0; j < MS; ++j) u[j] = (ok && j < S) ? ct::gld(src + (long long)j * NC) : mk<T>(T(0), T(0));
-            z1_node<T, MS>(c, a.diff != 0, kw, pd, tab, NC, S, es, kx0, p, e, ok, ti, u, acc[i], src);
+            z1_node<T, MS>(kc, a.diff != 0, kw, pd, tab, NC, S, es, kx0, p, e, ok, ti, u, acc[i], src);
         });
     }
     int ph = 0;
@@ -798,10 +852,11 @@ __global__ __launch_bounds__(NTB) void k_z2c(Geo g_in, Z2Args a) {
     // FP32: the electrostatic spectra of species is + 1 fetched while species is transforms
     // (slot is + 1 is written only in the next iteration, after every read of it)
     cx<T> evn[NO];
+    const bool es = c.es != 0;   // read once (a read after the stores below would be repeated)
     auto fetch_es = [&](int is) {
         const cx<T> *esrc = reinterpret_cast<const cx<T> *>(a.specA) + (long long)is * NC + off;
 #pragma unroll
-        for (int i = 0; i < NO; ++i) evn[i] = (c.es && okk[i]) ? ct::gld(esrc + ti[i]) : mk<T>(T(0), T(0));
+        for (int i = 0; i < NO; ++i) evn[i] = (es && okk[i]) ? ct::gld(esrc + ti[i]) : mk<T>(T(0), T(0));
     };
     if constexpr (PF) fetch_es(0);
     for (int is = 0; is < S; ++is) {

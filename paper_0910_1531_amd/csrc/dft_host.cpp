@@ -356,6 +356,22 @@ void fill_consts(const dft_params *p, const dft_bulk_info &b, Consts *c) {
                 c->sc_R[ij] = (p->flags & DFT_FLAG_CUTOFF_LAMBDA) ? li + lj : p->radius[i] + p->radius[j];
             }
     }
+    for (int k = 0; k < S; ++k) {
+        c->bath_N[k] = (double)c->N * c->rho_b[k];
+        c->f_R[k] = (float)c->R[k];
+        c->f_i4piR2[k] = (float)c->i4piR2[k];
+        c->f_i4piR[k] = (float)c->i4piR[k];
+        c->f_bath_N[k] = (float)c->bath_N[k];
+    }
+    for (int ij = 0; ij < DFT_MAX_SPECIES * DFT_MAX_SPECIES; ++ij) {
+        const int i = ij / DFT_MAX_SPECIES, j = ij % DFT_MAX_SPECIES;
+        c->f_zz[ij] = (i < S && j < S) ? (float)(c->z[i] * c->z[j]) : 0.0f;
+        c->f_sc_c1[ij] = (float)c->sc_c1[ij];
+        c->f_sc_c0[ij] = (float)c->sc_c0[ij];
+        c->f_sc_cm1[ij] = (float)c->sc_cm1[ij];
+        c->f_sc_R[ij] = (float)c->sc_R[ij];
+    }
+    c->f_four_pi_lB = (float)c->four_pi_lB;
 }
 
 }  // namespace dft

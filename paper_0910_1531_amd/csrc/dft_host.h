@@ -45,6 +45,14 @@ struct Consts {
     double sc_R[DFT_MAX_SPECIES * DFT_MAX_SPECIES];
     double nfluid;          // fluid nodes summed over species
     double eta_cap;
+    // The species and pair constants of the Z1 products rounded once to FP32 (the FP32 path reads
+    // them as they are instead of converting the FP64 values at every use); bath_N = N rho_b.
+    double bath_N[DFT_MAX_SPECIES];
+    float f_R[DFT_MAX_SPECIES], f_i4piR2[DFT_MAX_SPECIES], f_i4piR[DFT_MAX_SPECIES], f_bath_N[DFT_MAX_SPECIES];
+    float f_zz[DFT_MAX_SPECIES * DFT_MAX_SPECIES];   // z_i z_j
+    float f_sc_c1[DFT_MAX_SPECIES * DFT_MAX_SPECIES], f_sc_c0[DFT_MAX_SPECIES * DFT_MAX_SPECIES];
+    float f_sc_cm1[DFT_MAX_SPECIES * DFT_MAX_SPECIES], f_sc_R[DFT_MAX_SPECIES * DFT_MAX_SPECIES];
+    float f_four_pi_lB;
 };
 
 // Validation shared by every entry point (no HIP calls).
