@@ -74,6 +74,8 @@ __global__ __launch_bounds__(NTB) void k_yc(Geo g_in, YArgs a) {
     const long long ob = zax ? (long long)o * Kx : (long long)o * g.ny * Kx;
     cx<T> *spec = reinterpret_cast<cx<T> *>(a.spec) + ob + kx0;
     const cx<T> *tw = twp<T>(g, zax ? 2 : 1);
+    // grid steps of k_x, k_y read before any store (read later they would be reloaded after each)
+    [[maybe_unused]] const T dkx = T(g.cs->dk[0]), dky = T(g.cs->dk[1]);
     cx<T> v[F::V];
     int ph = 0;
     auto body = [&](auto dirc) {
@@ -98,7 +100,7 @@ __global__ __launch_bounds__(NTB) void k_yc(Geo g_in, YArgs a) {
                 cx<T> u = w[i];
                 if (mx) {
                     const int jx = kx0 + p;
-                    const T kx = (g.nx % 2 == 0 && 2 * jx == g.nx) ? T(0) : T(jx) * T(g.cs->dk[0]);
+                    const T kx = (g.nx % 2 == 0 && 2 * jx == g.nx) ? T(0) : T(jx) * dkx;
                     u = mk<T>(kx * u.y, -kx * u.x);
                 }
                 ct::gst(base + e * rs + p, u);
@@ -106,7 +108,7 @@ __global__ __launch_bounds__(NTB) void k_yc(Geo g_in, YArgs a) {
         };
         // k_y of element e of the pencil (zero on the Nyquist row)
         auto ky = [&](int e) {
-            return (g.ny % 2 == 0 && 2 * e == g.ny) ? T(0) : T(signed_mode(e, g.ny)) * T(g.cs->dk[1]);
+            return (g.ny % 2 == 0 && 2 * e == g.ny) ? T(0) : T(signed_mode(e, g.ny)) * dky;
         };
         if constexpr (VEC == 0) {
             load(f, v);
@@ -1085,6 +1087,7 @@ k_x2c(Geo g_in, X2Args a) {
     }
     const Geo &g = g_in;
     if (gated_off(a.gate)) return;
+    const T dk0 = T(g.cs->dk[0]);   // k_x step, read before any store
     __shared__ cx<T> lds[F::LDS_ELEMS + F::TILE];
     cx<T> *split = lds + F::LDS_ELEMS;
     const long long N = g.N, NC = g.NC;
@@ -1218,7 +1221,7 @@ k_x2c(Geo g_in, X2Args a) {
         }
         F::sync();
         // compact layout: the x components of the vector derivatives leave multiplied by i k_x
-        const T dkx = (g.compact && (f == 4 || f == 7)) ? T(g.cs->dk[0]) : T(0);
+        const T dkx = (g.compact && (f == 4 || f == 7)) ? dk0 : T(0);
         split_rows<T, L, F>(split, reinterpret_cast<cx<T> *>(a.specB) + (long long)f * NC, pair0, Pact, rows, dkx);
     }
 }
@@ -1344,6 +1347,7 @@ k_x2p(Geo g_in, X2Args a) {
     }
     const Geo &g = g_in;
     if (gated_off(a.gate)) return;
+    const T dk0 = T(g.cs->dk[0]);   // k_x step, read before any store
     __shared__ cx<T> lds[F::LDS_ELEMS + F::TILE];
     cx<T> *split = lds + F::LDS_ELEMS;
     const long long N = g.N, NC = g.NC;
@@ -1403,7 +1407,7 @@ k_x2p(Geo g_in, X2Args a) {
         }
         F::sync();
         const int f = x2_half_field(h, j);
-        const T dkx = (g.compact && (f == 4 || f == 7)) ? T(g.cs->dk[0]) : T(0);
+        const T dkx = (g.compact && (f == 4 || f == 7)) ? dk0 : T(0);
         split_rows<T, L, F, true>(split, reinterpret_cast<cx<T> *>(a.specB) + (long long)f * NC, pair0, Pact, rows, dkx);
     }
 }
