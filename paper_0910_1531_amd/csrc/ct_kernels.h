@@ -207,11 +207,11 @@ struct Poisson {
         tz = twp<T>(g, 2);
         ih2x = T(1.0 / (c.h[0] * c.h[0]));
         ih2z = T(1.0 / (c.h[2] * c.h[2]));
-        const cx<T> wy = ct::gld(twp<T>(g, 1) + y);
+        const cx<T> wy = ct::cld(twp<T>(g, 1) + y);
         dy = two_omc<T>(wy.x, wy.y) * T(1.0 / (c.h[1] * c.h[1]));
     }
     __device__ __forceinline__ T denom(int jx, int e) const {
-        const cx<T> wx = ct::gld(tx + jx), wz = ct::gld(tz + e);
+        const cx<T> wx = ct::cld(tx + jx), wz = ct::cld(tz + e);
         return two_omc<T>(wx.x, wx.y) * ih2x + dy + two_omc<T>(wz.x, wz.y) * ih2z;
     }
 };
@@ -307,15 +307,15 @@ __device__ __forceinline__ void z1_node(const Z1Const<T, MS> &k, bool diff, cons
     if constexpr (TAB) {
         static_for<MS>([&](auto J) __attribute__((always_inline)) {
             constexpr int j = J;
-            w2[j] = (ok && j < S) ? ct::gld(tab + (long long)j * NC + ti) : T(0);
-            w3[j] = (ok && j < S) ? ct::gld(tab + (long long)(S + j) * NC + ti) : T(0);
+            w2[j] = (ok && j < S) ? ct::cld(tab + (long long)j * NC + ti) : T(0);
+            w3[j] = (ok && j < S) ? ct::cld(tab + (long long)(S + j) * NC + ti) : T(0);
         });
         static_for<MS>([&](auto IA) __attribute__((always_inline)) {
             static_for<MS>([&](auto IB) __attribute__((always_inline)) {
                 constexpr int ia = IA, ib = IB;
                 if constexpr (ib >= ia)
                     K[pair_slot<MS>(ia, ib)] =
-                        (ok && es && ib < S) ? ct::gld(tab + (long long)pair_row(S, ia, ib) * NC + ti) : T(0);
+                        (ok && es && ib < S) ? ct::cld(tab + (long long)pair_row(S, ia, ib) * NC + ti) : T(0);
             });
         });
     } else {
@@ -400,8 +400,8 @@ __device__ __forceinline__ void z1_species(const Consts &c, const ZWave<T> &kw, 
                                            int jsp, int p, int e, bool ok, long long ti, cx<T> u, cx<T> (&acc)[5]) {
     T w2, w3;
     if constexpr (std::is_same<T, double>::value) {
-        w2 = ok ? ct::gld(tab + (long long)jsp * NC + ti) : T(0);
-        w3 = ok ? ct::gld(tab + (long long)(S + jsp) * NC + ti) : T(0);
+        w2 = ok ? ct::cld(tab + (long long)jsp * NC + ti) : T(0);
+        w3 = ok ? ct::cld(tab + (long long)(S + jsp) * NC + ti) : T(0);
     } else {
         weight_w2_w3<T>(kw.kmag(p, e), T(c.R[jsp]), w2, w3);
     }
@@ -873,8 +873,8 @@ __global__ __launch_bounds__(NTB) void k_z2c(Geo g_in, Z2Args a) {
             T w2, w3;
             if constexpr (TAB) {
                 const double *tab = g.tab64 + off;
-                w2 = ct::gld(tab + (long long)is * NC + ti[i]);
-                w3 = ct::gld(tab + (long long)(S + is) * NC + ti[i]);
+                w2 = ct::cld(tab + (long long)is * NC + ti[i]);
+                w3 = ct::cld(tab + (long long)(S + is) * NC + ti[i]);
             } else {
                 weight_w2_w3<T>(kmag[i], Ri, w2, w3);
             }
@@ -1141,7 +1141,7 @@ k_x2c(Geo g_in, X2Args a) {
             const bool okh = ok && r0 + h < rows;
             const long long idx = (r0 + h) * L + e;
 #pragma unroll
-            for (int f = 0; f < DFT_NALPHA; ++f) dst[h][f] = okh ? ct::gld(a.nref + f * N + idx) : 0.0f;
+            for (int f = 0; f < DFT_NALPHA; ++f) dst[h][f] = okh ? ct::cld(a.nref + f * N + idx) : 0.0f;
         }
     };
     if constexpr (D32) fetch_nref(0, nrc[0]);
@@ -1299,7 +1299,7 @@ __device__ __forceinline__ void x2p_swap_and_nodes(const X2Args &a, long long N,
                 if constexpr (sizeof(T) == 4) {
                     float nr[DFT_NALPHA];
 #pragma unroll
-                    for (int f = 0; f < DFT_NALPHA; ++f) nr[f] = ct::gld(a.nref + f * N + idx);
+                    for (int f = 0; f < DFT_NALPHA; ++f) nr[f] = ct::cld(a.nref + f * N + idx);
                     x2_node_diff(nr, dn, dd, mloc, flag);
                 } else {
                     x2_node<false>(a, N, idx, dn, dd, mloc, flag);
@@ -1457,13 +1457,13 @@ __global__ __launch_bounds__(XTile<L>::NTB) void k_x1c(Geo g_in, XFwdArgs a) {
                 const long long idx = foff + r * L + e;
                 double xv;
                 if (trial) {
-                    const double r0v = ct::gld(a.src + idx);
-                    xv = fma(alpha, ct::gld(a.g0 + idx) - r0v, r0v);
+                    const double r0v = ct::cld(a.src + idx);
+                    xv = fma(alpha, ct::cld(a.g0 + idx) - r0v, r0v);
                     if (a.rho_t) ct::gst(a.rho_t + idx, xv);
                 } else {
-                    xv = ct::gld(a.src + idx);
+                    xv = ct::cld(a.src + idx);
                 }
-                if (a.ref) xv -= ct::gld(a.ref + idx);
+                if (a.ref) xv -= ct::cld(a.ref + idx);
                 x[h] = xv;
             }
         }
@@ -1536,14 +1536,14 @@ __global__ __launch_bounds__(XTile<L>::NTB) void k_x3c(Geo g_in, X3Args a) {
                 ct::gst(a.raw_out + idx, o);
                 continue;
             }
-            const double b = ct::gld(a.base + idx);
+            const double b = ct::cld(a.base + idx);
             const bool fluid = b > -INFINITY;
             const double G = fluid ? rb * exp(b + E) : 0.0;
             if (a.g_out) ct::gst(a.g_out + idx, G);
             if (a.e_out) ct::gst(a.e_out + idx, a.e_phi ? E - zs * ct::gld(a.e_phi + node) : E);
             if (a.lp_out) ct::gst(a.lp_out + idx, fluid ? b + E : -INFINITY);
             if (fluid) {
-                const double dlt = (ct::gld(a.rho_t + idx) - G) * irb;
+                const double dlt = (ct::cld(a.rho_t + idx) - G) * irb;
                 acc += dlt * dlt;
                 if (!isfinite(G)) flag |= 1;
             }

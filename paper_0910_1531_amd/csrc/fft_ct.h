@@ -51,6 +51,19 @@ template <typename T>
 __device__ __forceinline__ void gst(T *p, T v) {
     *(__attribute__((address_space(1))) T *)p = v;
 }
+// Loads of data that no thread writes while the kernel runs (twiddles, spectral tables, the
+// reference fields): through the constant address space, so the compiler knows no store of the
+// kernel changes them and may issue them ahead of earlier stores.
+template <typename T>
+__device__ __forceinline__ cx<T> cld(const cx<T> *p) {
+    typedef __attribute__((address_space(4))) const typename V2<T>::type *CP;
+    const typename V2<T>::type r = *(CP)p;
+    return mk<T>(r.x, r.y);
+}
+template <typename T>
+__device__ __forceinline__ T cld(const T *p) {
+    return *(__attribute__((address_space(4))) const T *)p;
+}
 
 // ---------------------------------------------------------------- radix schedules
 // Radices in the order the forward transform runs them.
@@ -234,7 +247,7 @@ struct Fft {
                 constexpr int ts = L / (NS * R);
 #pragma unroll
                 for (int q = 1; q < R; ++q) {
-                    cx<T> w = gld(tw + q * k * ts);
+                    cx<T> w = cld(tw + q * k * ts);
                     if (DIR > 0) w.y = -w.y;
                     u[q] = mul(u[q], w);
                 }
@@ -258,7 +271,7 @@ struct Fft {
             const int NS = 1 << (2 * s);
             const int k = b % NS, ts = L / (NS * 4);
 #pragma unroll
-            for (int q = 1; q < 4; ++q) t.w[s - 1][q - 1] = gld(tw + q * k * ts);
+            for (int q = 1; q < 4; ++q) t.w[s - 1][q - 1] = cld(tw + q * k * ts);
         }
     }
     template <int DIR, int S>
@@ -297,7 +310,7 @@ struct Fft {
                 const int k = b % NS;   // idle butterflies read an in-range entry they never use
 #pragma unroll
                 for (int q = 1; q < R; ++q) {
-                    cx<T> w = gld(tw + q * k * ts);
+                    cx<T> w = cld(tw + q * k * ts);
                     if (DIR > 0) w.y = -w.y;
                     t.w[o + it * (R - 1) + q - 1] = w;
                 }
