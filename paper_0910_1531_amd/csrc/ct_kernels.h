@@ -67,11 +67,13 @@ __global__ __launch_bounds__(NTB) void k_yc(Geo g_in, YArgs a) {
     const int Kx = g.Kx;
     int bx, o;
     xcd_block(bx, o);
+    // y axis: P columns kx0.. of z plane o; z axis: P consecutive columns of the flattened
+    // (y, kx) plane (as in the other z tiles), kx0 then counting columns of the plane
     const int kx0 = bx * P;
-    const int Pact = min(P, Kx - kx0);
+    const int Pact = min(P, (zax ? g.ny * Kx : Kx) - kx0);
     const int f = (int)blockIdx.z % ntypes;
     const long long rs = zax ? (long long)g.ny * Kx : (long long)Kx;
-    const long long ob = zax ? (long long)o * Kx : (long long)o * g.ny * Kx;
+    const long long ob = zax ? 0 : (long long)o * g.ny * Kx;
     cx<T> *spec = reinterpret_cast<cx<T> *>(a.spec) + ob + kx0;
     const cx<T> *tw = twp<T>(g, zax ? 2 : 1);
     // grid steps of k_x, k_y read before any store (read later they would be reloaded after each)
@@ -163,56 +165,79 @@ __global__ __launch_bounds__(NTB) void k_yc(Geo g_in, YArgs a) {
 }
 
 // ------------------------------------------------------------------ z passes
-// Wavenumbers of the elements of one z tile: columns kx0 + p of the y row `y`, z index e.
+// z tiles run over the plane of columns (y, kx) flattened as y Kx + kx: a tile is P consecutive
+// columns, whatever row they fall in, so a plane of n_y Kx columns needs ceil(n_y Kx / P) tiles
+// (none holding a lone Nyquist column) and, with n_y Kx a multiple of P, every tile's segment of
+// a z plane starts on a P-element boundary.  In these tiles (pencil index fastest over threads,
+// NTB a multiple of P) a thread keeps one column, p = threadIdx.x mod P.
+struct ZTile {
+    long long off;   // first column of the tile (offset of its segment in a z plane)
+    int Pact;        // columns of the tile inside the plane
+    int x, y;        // the thread's column (a valid column also for idle lanes of a ragged tile)
+};
+template <int P>
+__device__ __forceinline__ ZTile z_tile(const Geo &g) {
+    int t, unused;
+    xcd_block(t, unused);
+    const int ncol = g.ny * g.Kx;
+    const int c0 = t * P;
+    ZTile z;
+    z.off = c0;
+    z.Pact = min(P, ncol - c0);
+    const int col = min(c0 + (int)threadIdx.x % P, ncol - 1);
+    z.y = col / g.Kx;
+    z.x = col - z.y * g.Kx;
+    return z;
+}
+
+// Wavenumbers of the elements of one z pencil: column (x, y), z index e.  Only the indices are
+// kept per thread (the grid steps are uniform): the components are formed at each use, which
+// costs a few instructions and no registers across the transforms.
 template <typename T>
 struct ZWave {
-    T dkx, dkz, ky;
-    int jx0, nx, nz;
-    bool yzero, ynyq;
-    __device__ __forceinline__ ZWave(const Consts &c, int kx0, int y) {
+    T dkx, dky, dkz;
+    int x, y, nx, ny, nz;
+    __device__ __forceinline__ ZWave(const Consts &c, int x_, int y_) : x(x_), y(y_) {
         dkx = T(c.dk[0]);
+        dky = T(c.dk[1]);
         dkz = T(c.dk[2]);
-        const int my = signed_mode(y, c.ny);
-        ky = T(my) * T(c.dk[1]);
-        jx0 = kx0;
         nx = c.nx;
+        ny = c.ny;
         nz = c.nz;
-        yzero = y == 0;
-        ynyq = (c.ny % 2 == 0) && (2 * y == c.ny);
     }
-    __device__ __forceinline__ T kx(int p) const { return T(jx0 + p) * dkx; }
+    __device__ __forceinline__ T kx() const { return T(x) * dkx; }
+    __device__ __forceinline__ T ky() const { return T(signed_mode(y, ny)) * dky; }
     __device__ __forceinline__ T kz(int e) const { return T(signed_mode(e, nz)) * dkz; }
-    __device__ __forceinline__ T kmag(int p, int e) const {
-        const T a = kx(p), b = kz(e);
-        return sqrt_r(a * a + ky * ky + b * b);
+    __device__ __forceinline__ T kmag(int e) const {
+        const T a = kx(), b = ky(), d = kz(e);
+        return sqrt_r(a * a + b * b + d * d);
     }
-    __device__ __forceinline__ bool zero(int p, int e) const { return yzero && jx0 + p == 0 && e == 0; }
+    __device__ __forceinline__ bool zero(int e) const { return x == 0 && y == 0 && e == 0; }
     // component d of k, zero on the Nyquist plane of axis d
-    __device__ __forceinline__ T comp(int p, int e, int d) const {
-        if (d == 0) return ((nx % 2 == 0) && 2 * (jx0 + p) == nx) ? T(0) : kx(p);
-        if (d == 1) return ynyq ? T(0) : ky;
+    __device__ __forceinline__ T comp(int e, int d) const {
+        if (d == 0) return ((nx % 2 == 0) && 2 * x == nx) ? T(0) : kx();
+        if (d == 1) return ((ny % 2 == 0) && 2 * y == ny) ? T(0) : ky();
         return ((nz % 2 == 0) && 2 * e == nz) ? T(0) : kz(e);
     }
 };
 
 // Eigenvalue of minus the 7-point Laplacian, sum_d 4 sin^2(k_d h_d / 2) / h_d^2, from the
-// twiddle tables: k_d h_d = 2 pi j_d / n_d, and tw_d[j] = exp(-2 pi i j / n_d).
+// twiddle tables: k_d h_d = 2 pi j_d / n_d, and tw_d[j] = exp(-2 pi i j / n_d).  The x and y
+// terms are those of one column (x, y).
 template <typename T>
 struct Poisson {
-    const cx<T> *tx, *tz;
-    T ih2x, ih2z, dy;
-    __device__ __forceinline__ Poisson() : tx(nullptr), tz(nullptr), ih2x(0), ih2z(0), dy(0) {}
-    __device__ __forceinline__ Poisson(const Geo &g, const Consts &c, int y) {
-        tx = twp<T>(g, 0);
+    const cx<T> *tz;
+    T ih2z, dxy;
+    __device__ __forceinline__ Poisson() : tz(nullptr), ih2z(0), dxy(0) {}
+    __device__ __forceinline__ Poisson(const Geo &g, const Consts &c, int x, int y) {
         tz = twp<T>(g, 2);
-        ih2x = T(1.0 / (c.h[0] * c.h[0]));
         ih2z = T(1.0 / (c.h[2] * c.h[2]));
-        const cx<T> wy = ct::cld(twp<T>(g, 1) + y);
-        dy = two_omc<T>(wy.x, wy.y) * T(1.0 / (c.h[1] * c.h[1]));
+        const cx<T> wx = ct::cld(twp<T>(g, 0) + x), wy = ct::cld(twp<T>(g, 1) + y);
+        dxy = two_omc<T>(wx.x, wx.y) * T(1.0 / (c.h[0] * c.h[0])) + two_omc<T>(wy.x, wy.y) * T(1.0 / (c.h[1] * c.h[1]));
     }
-    __device__ __forceinline__ T denom(int jx, int e) const {
-        const cx<T> wx = ct::cld(tx + jx), wz = ct::cld(tz + e);
-        return two_omc<T>(wx.x, wx.y) * ih2x + dy + two_omc<T>(wz.x, wz.y) * ih2z;
+    __device__ __forceinline__ T denom(int e) const {
+        const cx<T> wz = ct::cld(tz + e);
+        return dxy + two_omc<T>(wz.x, wz.y) * ih2z;
     }
 };
 
@@ -298,8 +323,8 @@ struct Z1Const {
 // species spectra stored at dst + i NC.  Each unordered pair factor is formed once (K_ij = K_ji).
 template <typename T, int MS>
 __device__ __forceinline__ void z1_node(const Z1Const<T, MS> &k, bool diff, const ZWave<T> &kw, const Poisson<T> &pd,
-                                        const double *tab, long long NC, int S, bool es, int kx0, int p, int e,
-                                        bool ok, long long ti, const cx<T> (&u)[MS], cx<T> (&acc)[5], cx<T> *dst) {
+                                        const double *tab, long long NC, int S, bool es, int e, bool ok,
+                                        long long ti, const cx<T> (&u)[MS], cx<T> (&acc)[5], cx<T> *dst) {
     constexpr bool TAB = std::is_same<T, double>::value;
     constexpr int NPR = MS * (MS + 1) / 2;
     T w2[MS], w3[MS], K[NPR];
@@ -319,7 +344,7 @@ __device__ __forceinline__ void z1_node(const Z1Const<T, MS> &k, bool diff, cons
             });
         });
     } else {
-        const T km = kw.kmag(p, e);
+        const T km = kw.kmag(e);
         T sn[MS], cs[MS];
         static_for<MS>([&](auto J) __attribute__((always_inline)) {
             constexpr int j = J;
@@ -365,10 +390,10 @@ __device__ __forceinline__ void z1_node(const Z1Const<T, MS> &k, bool diff, cons
     });
     if (!(es && ok)) return;
     // the bath term enters the k = 0 element of the pair-correlation part only
-    const bool z0 = !diff && kw.zero(p, e);
+    const bool z0 = !diff && kw.zero(e);
     T invD = T(0);
     if constexpr (!TAB)
-        if (!kw.zero(p, e)) invD = k.four_pi_lB * rcp_r(pd.denom(kx0 + p, e));
+        if (!kw.zero(e)) invD = k.four_pi_lB * rcp_r(pd.denom(e));
     static_for<MS>([&](auto IS) __attribute__((always_inline)) {
         constexpr int is = IS;
         if (is < S) {
@@ -397,13 +422,13 @@ __device__ __forceinline__ void z1_node(const Z1Const<T, MS> &k, bool diff, cons
 // Products of one species at one node without electrostatics (species by species).
 template <typename T>
 __device__ __forceinline__ void z1_species(const Consts &c, const ZWave<T> &kw, const double *tab, long long NC, int S,
-                                           int jsp, int p, int e, bool ok, long long ti, cx<T> u, cx<T> (&acc)[5]) {
+                                           int jsp, int e, bool ok, long long ti, cx<T> u, cx<T> (&acc)[5]) {
     T w2, w3;
     if constexpr (std::is_same<T, double>::value) {
         w2 = ok ? ct::cld(tab + (long long)jsp * NC + ti) : T(0);
         w3 = ok ? ct::cld(tab + (long long)(S + jsp) * NC + ti) : T(0);
     } else {
-        weight_w2_w3<T>(kw.kmag(p, e), T(c.R[jsp]), w2, w3);
+        weight_w2_w3<T>(kw.kmag(e), T(c.R[jsp]), w2, w3);
     }
     const T a0 = T(c.i4piR2[jsp]), a1 = T(c.i4piR[jsp]);
     const T m0 = w2 * a0, m1 = w2 * a1, m4 = w3 * a1;
@@ -444,7 +469,7 @@ __device__ __forceinline__ void z1_inverse(const Geo &g, const Z1Args &a, const 
             if (kzm) {
                 int p, e;
                 F::template in_pos<1>(i, p, e);
-                const T kd = kw.comp(p, e, 2);
+                const T kd = kw.comp(e, 2);
                 sm = mk<T>(kd * sm.y, -kd * sm.x);   // -i k_z s
             }
             v[i] = mk<T>(sm.x * invN, sm.y * invN);
@@ -460,7 +485,7 @@ __device__ __forceinline__ void z1_inverse(const Geo &g, const Z1Args &a, const 
                 if (!(ok && p < Pact)) continue;
                 cx<T> w = v[i];
                 if (d >= 0) {
-                    const T kd = kw.comp(p, e, d);
+                    const T kd = kw.comp(e, d);
                     w = mk<T>(kd * w.y, -kd * w.x);
                 }
                 ct::gst(dst + e * rs + p, w);
@@ -504,15 +529,14 @@ __global__ __launch_bounds__(NTB) void k_z1c(Geo g_in, Z1Args a) {
     const Consts &c = *g.cs;
     const int Kx = g.Kx, S = g.S;
     const long long NC = g.NC;
-    int bx, y;
-    xcd_block(bx, y);
-    const int kx0 = bx * P;
-    const int Pact = min(P, Kx - kx0);
+    static_assert(NTB % P == 0, "a thread keeps one column");
+    const ZTile zt = z_tile<P>(g);
+    const int Pact = zt.Pact;
     const long long rs = (long long)g.ny * Kx;
-    const long long off = (long long)y * Kx + kx0;
+    const long long off = zt.off;
     const cx<T> *tw = twp<T>(g, 2);
     const bool es = MS > 0 && c.es && !a.n3only;
-    const ZWave<T> kw(c, kx0, y);
+    const ZWave<T> kw(c, zt.x, zt.y);
     // the products' constants, read before the first store
     [[maybe_unused]] const Z1Const<T, (MS > 0 ? MS : 1)> kc(c);
     const double *tab = TAB ? g.tab64 + off : nullptr;
@@ -548,7 +572,7 @@ __global__ __launch_bounds__(NTB) void k_z1c(Geo g_in, Z1Args a) {
             for (int i = 0; i < NO; ++i) {
                 int p, e;
                 const bool ok = F::template out_pos<-1>(i, p, e) && p < Pact;
-                z1_species<T>(c, kw, tab, NC, S, jsp, p, e, ok, ok ? e * rs + p : 0, v[i], acc[i]);
+                z1_species<T>(c, kw, tab, NC, S, jsp, e, ok, ok ? e * rs + p : 0, v[i], acc[i]);
             }
         }
     } else {
@@ -568,7 +592,7 @@ __global__ __launch_bounds__(NTB) void k_z1c(Geo g_in, Z1Args a) {
             }
         });
         Poisson<T> pd;
-        if constexpr (!TAB) pd = Poisson<T>(g, c, y);
+        if constexpr (!TAB) pd = Poisson<T>(g, c, zt.x, zt.y);
         static_for<NO>([&](auto I) __attribute__((always_inline)) {
             constexpr int i = I;
             int p, e;
@@ -577,7 +601,7 @@ __global__ __launch_bounds__(NTB) void k_z1c(Geo g_in, Z1Args a) {
             cx<T> u[MS];
 #pragma unroll
             for (int j = 0; j < MS; ++j) u[j] = us[j][i];
-            z1_node<T, MS>(kc, a.diff != 0, kw, pd, tab, NC, S, es, kx0, p, e, ok, ti, u, acc[i],
+            z1_node<T, MS>(kc, a.diff != 0, kw, pd, tab, NC, S, es, e, ok, ti, u, acc[i],
                            reinterpret_cast<cx<T> *>(a.specA) + off + ti);
         });
     }
@@ -607,15 +631,14 @@ __global__ __launch_bounds__(NTB) void k_z1s(Geo g_in, Z1Args a) {
     const Consts &c = *g.cs;
     const int Kx = g.Kx, S = g.S;
     const long long NC = g.NC;
-    int bx, y;
-    xcd_block(bx, y);
-    const int kx0 = bx * P;
-    const int Pact = min(P, Kx - kx0);
+    static_assert(NTB % P == 0, "a thread keeps one column");
+    const ZTile zt = z_tile<P>(g);
+    const int Pact = zt.Pact;
     const long long rs = (long long)g.ny * Kx;
-    const long long off = (long long)y * Kx + kx0;
+    const long long off = zt.off;
     const cx<T> *tw = twp<T>(g, 2);
     const bool es = MS > 0 && c.es && !a.n3only;
-    const ZWave<T> kw(c, kx0, y);
+    const ZWave<T> kw(c, zt.x, zt.y);
     // the products' constants, read before the first store
     [[maybe_unused]] const Z1Const<T, (MS > 0 ? MS : 1)> kc(c);
     const double *tab = TAB ? g.tab64 + off : nullptr;
@@ -639,12 +662,12 @@ __global__ __launch_bounds__(NTB) void k_z1s(Geo g_in, Z1Args a) {
             for (int i = 0; i < NO; ++i) {
                 int p, e;
                 const bool ok = F::template in_pos<1>(i, p, e) && p < Pact;
-                z1_species<T>(c, kw, tab, NC, S, jsp, p, e, ok, ok ? e * rs + p : 0, uin[i], acc[i]);
+                z1_species<T>(c, kw, tab, NC, S, jsp, e, ok, ok ? e * rs + p : 0, uin[i], acc[i]);
             }
         }
     } else {
         Poisson<T> pd;
-        if constexpr (!TAB) pd = Poisson<T>(g, c, y);
+        if constexpr (!TAB) pd = Poisson<T>(g, c, zt.x, zt.y);
         static_for<NO>([&](auto I) __attribute__((always_inline)) {
             constexpr int i = I;
             int p, e;
@@ -654,7 +677,7 @@ __global__ __launch_bounds__(NTB) void k_z1s(Geo g_in, Z1Args a) {
             cx<T> u[MS];
 #pragma unroll
             for (int j = 0; j < MS; ++j) u[j] = (ok && j < S) ? ct::gld(src + (long long)j * NC) : mk<T>(T(0), T(0));
-            z1_node<T, MS>(kc, a.diff != 0, kw, pd, tab, NC, S, es, kx0, p, e, ok, ti, u, acc[i], src);
+            z1_node<T, MS>(kc, a.diff != 0, kw, pd, tab, NC, S, es, e, ok, ti, u, acc[i], src);
         });
     }
     int ph = 0;
@@ -684,14 +707,13 @@ __global__ __launch_bounds__(NTB) void k_z2c(Geo g_in, Z2Args a) {
     const Consts &c = *g.cs;
     const int Kx = g.Kx, S = g.S;
     const long long NC = g.NC;
-    int bx, y;
-    xcd_block(bx, y);
-    const int kx0 = bx * P;
-    const int Pact = min(P, Kx - kx0);
+    static_assert(NTB % P == 0, "a thread keeps one column");
+    const ZTile zt = z_tile<P>(g);
+    const int Pact = zt.Pact;
     const long long rs = (long long)g.ny * Kx;
-    const long long off = (long long)y * Kx + kx0;
+    const long long off = zt.off;
     const cx<T> *tw = twp<T>(g, 2);
-    const ZWave<T> kw(c, kx0, y);
+    const ZWave<T> kw(c, zt.x, zt.y);
     int pp[NO], ee[NO];
     bool okk[NO];
     long long ti[NO];
@@ -735,7 +757,7 @@ __global__ __launch_bounds__(NTB) void k_z2c(Geo g_in, Z2Args a) {
         // specA[i] x B(|k| radius) / N -> specB[i]
         double m[NO];
 #pragma unroll
-        for (int i = 0; i < NO; ++i) m[i] = ball_mean<double>((double)kw.kmag(pp[i], ee[i]), a.radius) * c.invN;
+        for (int i = 0; i < NO; ++i) m[i] = ball_mean<double>((double)kw.kmag(ee[i]), a.radius) * c.invN;
         for (int is = 0; is < a.nsrc; ++is) {
             load_fwd(reinterpret_cast<const cx<T> *>(a.specA) + (long long)is * NC + off);
 #pragma unroll
@@ -761,11 +783,11 @@ __global__ __launch_bounds__(NTB) void k_z2c(Geo g_in, Z2Args a) {
                 acc[i][1] += wj * (double)v[i].y;
             }
         }
-        const Poisson<double> pd(g, c, y);
+        const Poisson<double> pd(g, c, zt.x, zt.y);
 #pragma unroll
         for (int i = 0; i < NO; ++i) {
             double m = 0.0;
-            if (!kw.zero(pp[i], ee[i])) m = c.four_pi_lB / pd.denom(kx0 + pp[i], ee[i]) * c.invN;
+            if (!kw.zero(ee[i])) m = c.four_pi_lB / pd.denom(ee[i]) * c.invN;
             v[i] = mk<T>(T(acc[i][0] * m), T(acc[i][1] * m));
         }
         inv_store(reinterpret_cast<cx<T> *>(a.specA) + off);
@@ -825,7 +847,7 @@ __global__ __launch_bounds__(NTB) void k_z2c(Geo g_in, Z2Args a) {
                 cx<T> w = mk<T>(T(0), T(0));
                 if (ok) {
                     const cx<T> fx = ct::gld(sx + e * rs + p), fy = ct::gld(sy + e * rs + p);
-                    const T kx = kw.comp(p, e, 0), ky = kw.comp(p, e, 1);
+                    const T kx = kw.comp(e, 0), ky = kw.comp(e, 1);
                     w = mk<T>(-(kx * fx.y + ky * fy.y), kx * fx.x + ky * fy.x);   // i k_x fx + i k_y fy
                 }
                 v[i] = w;
@@ -836,7 +858,7 @@ __global__ __launch_bounds__(NTB) void k_z2c(Geo g_in, Z2Args a) {
         for (int i = 0; i < NO; ++i) {
             cx<T> w = v[i];
             if (t == 5 || t == 7) {
-                const T kd = kw.comp(pp[i], ee[i], 2);
+                const T kd = kw.comp(ee[i], 2);
                 w = mk<T>(-kd * w.y, kd * w.x);   // + i k_z w
             }
 #pragma unroll
@@ -849,7 +871,7 @@ __global__ __launch_bounds__(NTB) void k_z2c(Geo g_in, Z2Args a) {
     T kmag[NOF];
     if constexpr (!TAB) {
 #pragma unroll
-        for (int i = 0; i < NO; ++i) kmag[i] = kw.kmag(pp[i], ee[i]);
+        for (int i = 0; i < NO; ++i) kmag[i] = kw.kmag(ee[i]);
     }
     // FP32: the electrostatic spectra of species is + 1 fetched while species is transforms
     // (slot is + 1 is written only in the next iteration, after every read of it)

@@ -11,7 +11,7 @@ template <> constexpr int z_width<double>(int v) { return v == 0 ? 4 : v == 1 ? 
 template <typename T, int L, int V>
 static void launch_z1c_var(const Geo &g, const Z1Args &a, int es, hipStream_t s) {
     constexpr int P = z_width<T>(V), NTB = fit_threads(L, P, 4, 512);
-    dim3 grid((unsigned)ct_cdiv(g.Kx, P), (unsigned)g.ny, (unsigned)g.nprob);
+    dim3 grid((unsigned)ct_cdiv(g.ny * g.Kx, P), 1, (unsigned)g.nprob);   // flattened (y, kx) columns
     if (!es) hipLaunchKernelGGL((k_z1c<T, L, P, NTB, 0>), grid, dim3(NTB), 0, s, g, a);
     else {
         // the pair accumulators are sized for the species count: fewer registers for S < 4
@@ -30,7 +30,7 @@ static void launch_z1s_var(const Geo &g, const Z1Args &a, int es, hipStream_t s)
     za.axis = 2;
     launch_y<T>(g, za, s);
     constexpr int P = z_width<T>(V), NTB = fit_threads(L, P, 4, 512);
-    dim3 grid((unsigned)ct_cdiv(g.Kx, P), (unsigned)g.ny, (unsigned)g.nprob);
+    dim3 grid((unsigned)ct_cdiv(g.ny * g.Kx, P), 1, (unsigned)g.nprob);   // flattened (y, kx) columns
     if (!es) hipLaunchKernelGGL((k_z1s<T, L, P, NTB, 0>), grid, dim3(NTB), 0, s, g, a);
     else if (g.S <= 2) hipLaunchKernelGGL((k_z1s<T, L, P, NTB, 2>), grid, dim3(NTB), 0, s, g, a);
     else if (g.S == 3) hipLaunchKernelGGL((k_z1s<T, L, P, NTB, 3>), grid, dim3(NTB), 0, s, g, a);

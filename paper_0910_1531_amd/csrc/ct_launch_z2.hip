@@ -14,8 +14,8 @@ __global__ __launch_bounds__(256) void k_spec_tables(Geo g) {
     const int kx = (int)(i % Kx);
     const long long t = i / Kx;
     const int y = (int)(t % g.ny), e = (int)(t / g.ny);
-    const ZWave<double> kw(c, 0, y);
-    const double kmag = kw.kmag(kx, e);
+    const ZWave<double> kw(c, kx, y);
+    const double kmag = kw.kmag(e);
     double *t64 = const_cast<double *>(g.tab64);
     auto put = [&](int row, double v) { ct::gst(t64 + (long long)row * NC + i, v); };
     for (int s = 0; s < S; ++s) {
@@ -26,9 +26,9 @@ __global__ __launch_bounds__(256) void k_spec_tables(Geo g) {
     }
     if (g.ntab > 2 * S) {
         double invD = 0.0;
-        if (!kw.zero(kx, e)) {
-            const Poisson<double> pd(g, c, y);
-            invD = c.four_pi_lB / pd.denom(kx, e);
+        if (!kw.zero(e)) {
+            const Poisson<double> pd(g, c, kx, y);
+            invD = c.four_pi_lB / pd.denom(e);
         }
         for (int a = 0; a < S; ++a)
             for (int b = a; b < S; ++b) {
@@ -47,7 +47,7 @@ template <> constexpr int z2_width<double>(int v) { return v == 0 ? 4 : v == 1 ?
 template <typename T, int L, int V>
 static void launch_z2c_var(const Geo &g, const Z2Args &a, hipStream_t s) {
     constexpr int P = z2_width<T>(V), NTB = fit_threads(L, P, 4, 512);
-    dim3 grid((unsigned)ct_cdiv(g.Kx, P), (unsigned)g.ny, (unsigned)g.nprob);
+    dim3 grid((unsigned)ct_cdiv(g.ny * g.Kx, P), 1, (unsigned)g.nprob);   // flattened (y, kx) columns
     hipLaunchKernelGGL((k_z2c<T, L, P, NTB>), grid, dim3(NTB), 0, s, g, a);
     ct_check("z2 (compiled length)");
 }
