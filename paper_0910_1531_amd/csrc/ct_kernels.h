@@ -43,8 +43,8 @@ __device__ __forceinline__ void static_for(Fn &&f) {
 #define DFT_CT_LENGTHS(X) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384)
 
 // ------------------------------------------------------------------ y / z plain transforms
-// One block transforms P adjacent columns (kx) of one field along y (one z plane) or z
-// (one y line); the pencils' elements sit rs apart in HBM and P columns are contiguous.
+// One block transforms P adjacent pencils of one field along y or z; the pencils' elements sit
+// rs apart in HBM, and adjacent pencils of one row are adjacent in HBM.
 // VEC = 1, 2: the y passes of the compact vector layout (Geo::compact), where a block of the
 // n3 or nV1-sum slot makes two transforms (inverse: the field and -i k_y times it) and a block
 // of a vector-derivative slot adds i k_y times the transform of the y component (forward).
@@ -65,16 +65,21 @@ __global__ __launch_bounds__(NTB) void k_yc(Geo g_in, YArgs a) {
     __shared__ cx<T> lds[F::LDS_ELEMS];
     const bool zax = a.axis == 2;
     const int Kx = g.Kx;
-    int bx, o;
-    xcd_block(bx, o);
-    // y axis: P columns kx0.. of z plane o; z axis: P consecutive columns of the flattened
-    // (y, kx) plane (as in the other z tiles), kx0 then counting columns of the plane
-    const int kx0 = bx * P;
-    const int Pact = min(P, (zax ? g.ny * Kx : Kx) - kx0);
+    // A tile is P consecutive pencils of the flattened plane of pencils, (y, kx) as y Kx + kx for
+    // the z axis (as in the other z tiles), (z, kx) as z Kx + kx for the y axis, so no tile holds
+    // a lone Nyquist column.  A thread keeps one pencil (p = threadIdx.x mod P) and its offset.
+    static_assert(NTB % P == 0, "a thread keeps one pencil");
+    int bx, unused;
+    xcd_block(bx, unused);
+    const int ncol = (zax ? g.ny : g.nz) * Kx;
+    const int c0 = bx * P;
+    const int Pact = min(P, ncol - c0);
+    const int col = min(c0 + (int)threadIdx.x % P, ncol - 1);
+    const int zc = zax ? 0 : col / Kx;
+    const int jx = col - zc * Kx;   // k_x index of the pencil (y axis)
     const int f = (int)blockIdx.z % ntypes;
     const long long rs = zax ? (long long)g.ny * Kx : (long long)Kx;
-    const long long ob = zax ? 0 : (long long)o * g.ny * Kx;
-    cx<T> *spec = reinterpret_cast<cx<T> *>(a.spec) + ob + kx0;
+    cx<T> *spec = reinterpret_cast<cx<T> *>(a.spec) + (zax ? (long long)col : (long long)zc * g.ny * Kx + jx);
     const cx<T> *tw = twp<T>(g, zax ? 2 : 1);
     // grid steps of k_x, k_y read before any store (read later they would be reloaded after each)
     [[maybe_unused]] const T dkx = T(g.cs->dk[0]), dky = T(g.cs->dk[1]);
@@ -88,7 +93,7 @@ __global__ __launch_bounds__(NTB) void k_yc(Geo g_in, YArgs a) {
             for (int i = 0; i < F::template nin<DIR>(); ++i) {
                 int p, e;
                 const bool ok = F::template in_pos<DIR>(i, p, e);
-                w[i] = (ok && p < Pact) ? ct::gld(base + e * rs + p) : mk<T>(T(0), T(0));
+                w[i] = (ok && p < Pact) ? ct::gld(base + e * rs) : mk<T>(T(0), T(0));
             }
         };
         // store slot, times -i k_x when mx (k_x of the column, zero on the Nyquist column)
@@ -101,11 +106,10 @@ __global__ __launch_bounds__(NTB) void k_yc(Geo g_in, YArgs a) {
                 if (!(ok && p < Pact)) continue;
                 cx<T> u = w[i];
                 if (mx) {
-                    const int jx = kx0 + p;
                     const T kx = (g.nx % 2 == 0 && 2 * jx == g.nx) ? T(0) : T(jx) * dkx;
                     u = mk<T>(kx * u.y, -kx * u.x);
                 }
-                ct::gst(base + e * rs + p, u);
+                ct::gst(base + e * rs, u);
             }
         };
         // k_y of element e of the pencil (zero on the Nyquist row)

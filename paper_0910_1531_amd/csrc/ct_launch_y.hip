@@ -38,9 +38,8 @@ static bool launch_yc_var(const Geo &g, const YArgs &a, hipStream_t s) {
         const bool zax = a.axis == 2;
         const int ntypes = a.vec == 1 ? 7 : (a.vec == 2 ? 8 : a.nfield);
         if (zax && a.vec != 0) return false;   // the compact vector layout has y passes only
-        // z axis: tiles over the flattened (y, kx) plane of columns
-        dim3 grid((unsigned)(zax ? ct_cdiv(g.ny * g.Kx, P) : ct_cdiv(g.Kx, P)), (unsigned)(zax ? 1 : g.nz),
-                  (unsigned)(ntypes * g.nprob));
+        // tiles over the flattened plane of pencils: (y, kx) for the z axis, (z, kx) for the y axis
+        dim3 grid((unsigned)ct_cdiv((zax ? g.ny : g.nz) * g.Kx, P), 1, (unsigned)(ntypes * g.nprob));
         if (a.vec == 1)
             hipLaunchKernelGGL((k_yc<T, L, P, NTB, NB, 1>), grid, dim3(NTB), 0, s, g, a);
         else if (a.vec == 2)

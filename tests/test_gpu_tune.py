@@ -21,6 +21,10 @@ def _say(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# launch shapes of each tunable pass
+NSHAPE = {"y": 10, "z_plain": 10, "z_weights": 6, "z_back": 3, "y_fwd2": 10, "y_species": 10}
+
+
 def _problems():
     yield "pore48", W.charged_pore(n=48, h=0.0625)
     p = W.charged_sphere(n=(64, 32, 96), h=0.05, sigma=(0.3, 0.24), conc=(0.5, 0.5), sphere_radius=0.3)
@@ -37,11 +41,10 @@ def test_every_shape_gives_the_same_residual(precision):
             sol.set_reference(torch.tensor(p.initial_density(), dtype=torch.float64, device="cuda"))
         g0, r0 = sol.residual(rho)
         g0 = g0.clone()
-        nshape = {"y": 10, "z_plain": 10, "z_weights": 6, "z_back": 3, "y_fwd2": 10, "y_species": 10}
-        for ps, nv in nshape.items():
+        for ps, nv in NSHAPE.items():
             for v in range(1, nv):
                 for t in (0, 1):
-                    sched = {k: (0, 0) for k in nshape}
+                    sched = {k: (0, 0) for k in NSHAPE}
                     sched[ps] = (v, 0) if t == 0 else (0, v)
                     sol.set_schedule(sched)
                     g, r = sol.residual(rho)
@@ -61,8 +64,9 @@ def test_tuned_solve_equals_untuned():
         sol = from_problem(p, precision=_abi.DFT_FP32_MIXED, flags=flags)
         sched = sol.schedule()
         _say(f"  flags {flags}: schedule {sched}")
-        for v in sched.values():
-            assert 0 <= v[0] < 6 and 0 <= v[1] < 6
+        assert set(sched) == set(NSHAPE)
+        for ps, v in sched.items():
+            assert 0 <= v[0] < NSHAPE[ps] and 0 <= v[1] < NSHAPE[ps]
         rho = torch.tensor(p.initial_density(), dtype=torch.float64, device="cuda")
         it, r, st = sol.solve(rho, 1e-8, 500)
         assert st == 0
