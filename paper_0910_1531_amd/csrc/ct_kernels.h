@@ -356,7 +356,7 @@ __device__ __forceinline__ void z1_node(const Z1Const<T, MS> &k, bool diff, cons
             cs[j] = T(1);
             w2[j] = w3[j] = T(0);
             if (j < S) {
-                sincos_r(km * k.R[j], &sn[j], &cs[j]);
+                sincos_w(km * k.R[j], &sn[j], &cs[j]);
                 weight_w2_w3_sc<T>(km, k.R[j], sn[j], cs[j], w2[j], w3[j]);
             }
         });
