@@ -63,10 +63,12 @@ def mixture(n, h=(0.09, 0.11, 0.1), S=2, es=True, seed=0):
 
 # Run-time-length kernels (12, 6, 9, 8, 18, 2, 3, 4), compiled lengths (16 .. 256, radix-3
 # schedules with partly idle butterflies among them; x lengths 16, 64 and 256 run wave-private
-# tiles with ragged last blocks), and mixes of both.
+# tiles with ragged last blocks), and mixes of both.  (8, 24, 24): compiled y and z lengths whose
+# planes of pencils (24 x 5) are not a whole number of 16- or 32-pencil tiles, so the last tile of
+# each y and z pass is partial and y tiles cross plane boundaries.
 SHAPES = [((12, 6, 9), 2, True), ((8, 8, 8), 1, False), ((16, 12, 18), 3, True), ((96, 1, 1), 2, True),
           ((1, 8, 12), 2, True), ((2, 3, 4), 2, True), ((32, 32, 32), 2, True), ((24, 16, 48), 2, True),
-          ((96, 64, 48), 3, True), ((256, 6, 3), 2, True), ((64, 12, 9), 3, True)]
+          ((96, 64, 48), 3, True), ((256, 6, 3), 2, True), ((64, 12, 9), 3, True), ((8, 24, 24), 3, True)]
 
 
 @pytest.mark.parametrize("n,S,es", SHAPES)

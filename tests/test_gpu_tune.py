@@ -29,6 +29,9 @@ def _problems():
     yield "pore48", W.charged_pore(n=48, h=0.0625)
     p = W.charged_sphere(n=(64, 32, 96), h=0.05, sigma=(0.3, 0.24), conc=(0.5, 0.5), sphere_radius=0.3)
     yield "sphere64x32x96", p
+    # planes of 24 x 5 pencils: the last y and z tiles of 16 or 32 pencils are partial
+    p = W.charged_sphere(n=(8, 24, 24), h=0.05, sigma=(0.3, 0.24), conc=(0.5, 0.5), sphere_radius=0.2)
+    yield "sphere8x24x24", p
 
 
 @pytest.mark.parametrize("precision", [_abi.DFT_FP64, _abi.DFT_FP32_MIXED])
