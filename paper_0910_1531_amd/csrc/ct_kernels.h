@@ -278,7 +278,7 @@ template <typename T, int MS>
 struct Z1Const {
     static constexpr int NPR = MS * (MS + 1) / 2;
     T R[MS], a0[MS], a1[MS], bath[MS];   // R_j, 1 / (4 pi R_j^2), 1 / (4 pi R_j), N rho_b,j
-    T zz[NPR], scR[NPR], c1[NPR], c0[NPR], cm1[NPR];
+    T zz[NPR], scR[NPR], p1[NPR], p2[NPR], p3[NPR], p4[NPR];   // pair constants (FP32 only)
     T four_pi_lB;
     __device__ __forceinline__ explicit Z1Const(const Consts &c) {
         constexpr bool F32 = std::is_same<T, float>::value;
@@ -304,15 +304,14 @@ struct Z1Const {
                     if constexpr (F32) {
                         zz[q] = c.f_zz[ij];
                         scR[q] = c.f_sc_R[ij];
-                        c1[q] = c.f_sc_c1[ij];
-                        c0[q] = c.f_sc_c0[ij];
-                        cm1[q] = c.f_sc_cm1[ij];
+                        p1[q] = c.f_sc_p1[ij];
+                        p2[q] = c.f_sc_p2[ij];
+                        p3[q] = c.f_sc_p3[ij];
+                        p4[q] = c.f_sc_p4[ij];
                     } else {
+                        // FP64 reads the pair factors from the spectral tables
                         zz[q] = c.z[ia] * c.z[ib];
-                        scR[q] = c.sc_R[ij];
-                        c1[q] = c.sc_c1[ij];
-                        c0[q] = c.sc_c0[ij];
-                        cm1[q] = c.sc_cm1[ij];
+                        scR[q] = p1[q] = p2[q] = p3[q] = p4[q] = T(0);
                     }
                 }
             });
@@ -371,7 +370,7 @@ __device__ __forceinline__ void z1_node(const Z1Const<T, MS> &k, bool diff, cons
                         const T sp = sn[ia] * cs[ib] + cs[ia] * sn[ib];
                         const T cp = cs[ia] * cs[ib] - sn[ia] * sn[ib];
                         constexpr int q = pair_slot<MS>(ia, ib);
-                        Kv = screening_hat_sc<T>(km, k.scR[q], sp, cp, k.c1[q], k.c0[q], k.cm1[q]);
+                        Kv = screening_hat_p<T>(km, k.scR[q], sp, cp, k.p1[q], k.p2[q], k.p3[q], k.p4[q]);
                     }
                     K[pair_slot<MS>(ia, ib)] = Kv;
                 }

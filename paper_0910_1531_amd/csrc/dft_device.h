@@ -301,6 +301,24 @@ __device__ __forceinline__ R screening_hat_sc(R k, R Rc, R s, R c, R c1, R c0, R
     return c1 * F1 + c0 * F0 + cm1 * Fm1;
 }
 
+// The same factor from the regrouped pair constants p1..p4 (a = -p4 / 2, b = p2 + p4, g = p3):
+//   k Rc >= 1:  (p1 c + p2 s / y + (1 - c)(p3 + p4 / y^2)) / y^2,
+//   k Rc < 1:   a S1(y) + b S0(y) + g Sm1(y) with the series of F1, F0, Fm1 over their prefactors.
+template <typename R>
+__device__ __forceinline__ R screening_hat_p(R k, R Rc, R s, R c, R p1, R p2, R p3, R p4) {
+    const R y = k * Rc;
+    if (y < R(1)) {
+        constexpr BallSeries<-1> sm{};
+        constexpr BallSeries<0> s0{};
+        constexpr BallSeries<1> s1{};
+        const R y2 = y * y;
+        return R(-0.5) * p4 * horner_y2<R>(s1, y2) + (p2 + p4) * horner_y2<R>(s0, y2) + p3 * horner_y2<R>(sm, y2);
+    }
+    const R omc = (c > R(0)) ? s * s * rcp_r(R(1) + c) : R(1) - c;   // 1 - cos y without cancellation
+    const R iy = rcp_r(y), iy2 = iy * iy;
+    return iy2 * (p1 * c + p2 * s * iy + omc * (p3 + p4 * iy2));
+}
+
 template <typename R>
 __device__ __forceinline__ R screening_hat(R k, R Rc, R c1, R c0, R cm1) {
     R s = R(0), c = R(1);

@@ -366,10 +366,13 @@ void fill_consts(const dft_params *p, const dft_bulk_info &b, Consts *c) {
     for (int ij = 0; ij < DFT_MAX_SPECIES * DFT_MAX_SPECIES; ++ij) {
         const int i = ij / DFT_MAX_SPECIES, j = ij % DFT_MAX_SPECIES;
         c->f_zz[ij] = (i < S && j < S) ? (float)(c->z[i] * c->z[j]) : 0.0f;
-        c->f_sc_c1[ij] = (float)c->sc_c1[ij];
-        c->f_sc_c0[ij] = (float)c->sc_c0[ij];
-        c->f_sc_cm1[ij] = (float)c->sc_cm1[ij];
-        c->f_sc_R[ij] = (float)c->sc_R[ij];
+        const double Rc = c->sc_R[ij], R2 = Rc * Rc;
+        const double a = 4.0 * M_PI * c->sc_c1[ij] * R2 * R2, bb = 4.0 * M_PI * c->sc_c0[ij] * R2 * Rc;
+        c->f_sc_p1[ij] = (float)(-(a + bb));
+        c->f_sc_p2[ij] = (float)(2.0 * a + bb);
+        c->f_sc_p3[ij] = (float)(4.0 * M_PI * c->sc_cm1[ij] * R2);
+        c->f_sc_p4[ij] = (float)(-2.0 * a);
+        c->f_sc_R[ij] = (float)Rc;
     }
     c->f_four_pi_lB = (float)c->four_pi_lB;
 }

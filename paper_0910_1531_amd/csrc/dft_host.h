@@ -50,8 +50,12 @@ struct Consts {
     double bath_N[DFT_MAX_SPECIES];
     float f_R[DFT_MAX_SPECIES], f_i4piR2[DFT_MAX_SPECIES], f_i4piR[DFT_MAX_SPECIES], f_bath_N[DFT_MAX_SPECIES];
     float f_zz[DFT_MAX_SPECIES * DFT_MAX_SPECIES];   // z_i z_j
-    float f_sc_c1[DFT_MAX_SPECIES * DFT_MAX_SPECIES], f_sc_c0[DFT_MAX_SPECIES * DFT_MAX_SPECIES];
-    float f_sc_cm1[DFT_MAX_SPECIES * DFT_MAX_SPECIES], f_sc_R[DFT_MAX_SPECIES * DFT_MAX_SPECIES];
+    // The screening factor for k Rc >= 1 regrouped by sin, cos and 1 - cos (screening_hat_p):
+    // with a = 4 pi c1 Rc^4, b = 4 pi c0 Rc^3, g = 4 pi cm1 Rc^2 (formed in FP64),
+    // p1 = -(a + b), p2 = 2a + b, p3 = g, p4 = -2a.
+    float f_sc_p1[DFT_MAX_SPECIES * DFT_MAX_SPECIES], f_sc_p2[DFT_MAX_SPECIES * DFT_MAX_SPECIES];
+    float f_sc_p3[DFT_MAX_SPECIES * DFT_MAX_SPECIES], f_sc_p4[DFT_MAX_SPECIES * DFT_MAX_SPECIES];
+    float f_sc_R[DFT_MAX_SPECIES * DFT_MAX_SPECIES];
     float f_four_pi_lB;
 };
 
