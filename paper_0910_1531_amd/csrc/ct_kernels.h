@@ -717,14 +717,22 @@ __global__ __launch_bounds__(NTB) void k_z2c(Geo g_in, Z2Args a) {
     const long long off = zt.off;
     const cx<T> *tw = twp<T>(g, 2);
     const ZWave<T> kw(c, zt.x, zt.y);
-    int pp[NO], ee[NO];
-    bool okk[NO];
-    long long ti[NO];
-#pragma unroll
-    for (int i = 0; i < NO; ++i) {
-        okk[i] = F::template out_pos<-1>(i, pp[i], ee[i]) && pp[i] < Pact;
-        ti[i] = okk[i] ? ee[i] * rs + pp[i] : 0;
-    }
+    // position of output register i of the forward transforms (recomputed at each use: a few
+    // instructions from the thread index instead of registers held through the kernel)
+    auto ee = [&](int i) {
+        int p, e;
+        F::template out_pos<-1>(i, p, e);
+        return e;
+    };
+    auto okk = [&](int i) {
+        int p, e;
+        return F::template out_pos<-1>(i, p, e) && p < Pact;
+    };
+    auto ti = [&](int i) {
+        int p, e;
+        const bool ok = F::template out_pos<-1>(i, p, e) && p < Pact;
+        return ok ? e * rs + p : 0;
+    };
     cx<T> v[F::V];
     int ph = 0;
     // FP32: the forward twiddles in registers, shared by the input transforms (in FP64 the
@@ -760,7 +768,7 @@ __global__ __launch_bounds__(NTB) void k_z2c(Geo g_in, Z2Args a) {
         // specA[i] x B(|k| radius) / N -> specB[i]
         double m[NO];
 #pragma unroll
-        for (int i = 0; i < NO; ++i) m[i] = ball_mean<double>((double)kw.kmag(ee[i]), a.radius) * c.invN;
+        for (int i = 0; i < NO; ++i) m[i] = ball_mean<double>((double)kw.kmag(ee(i)), a.radius) * c.invN;
         for (int is = 0; is < a.nsrc; ++is) {
             load_fwd(reinterpret_cast<const cx<T> *>(a.specA) + (long long)is * NC + off);
 #pragma unroll
@@ -790,7 +798,7 @@ __global__ __launch_bounds__(NTB) void k_z2c(Geo g_in, Z2Args a) {
 #pragma unroll
         for (int i = 0; i < NO; ++i) {
             double m = 0.0;
-            if (!kw.zero(ee[i])) m = c.four_pi_lB / pd.denom(ee[i]) * c.invN;
+            if (!kw.zero(ee(i))) m = c.four_pi_lB / pd.denom(ee(i)) * c.invN;
             v[i] = mk<T>(T(acc[i][0] * m), T(acc[i][1] * m));
         }
         inv_store(reinterpret_cast<cx<T> *>(a.specA) + off);
@@ -810,7 +818,7 @@ __global__ __launch_bounds__(NTB) void k_z2c(Geo g_in, Z2Args a) {
     // compact layout: slots 4 and 7 already hold i k_x dPhi_x + i k_y dPhi_y and all eight inputs
     // are plain spectra; in FP32 tiles of at most four values per thread each is fetched while the
     // previous one transforms (FP64 and wider tiles have no registers to spare for it)
-    constexpr bool PF = std::is_same<T, float>::value && NO <= 4;
+    constexpr bool PF = std::is_same<T, float>::value && NO <= 8;
     constexpr int NIN = F::template nin<-1>();
     cx<T> vin[NIN];
     auto slot_of = [](int t) { return t < 4 ? t : (t == 4 ? 4 : (t == 5 ? 6 : (t == 6 ? 7 : 9))); };
@@ -861,7 +869,7 @@ __global__ __launch_bounds__(NTB) void k_z2c(Geo g_in, Z2Args a) {
         for (int i = 0; i < NO; ++i) {
             cx<T> w = v[i];
             if (t == 5 || t == 7) {
-                const T kd = kw.comp(ee[i], 2);
+                const T kd = kw.comp(ee(i), 2);
                 w = mk<T>(-kd * w.y, kd * w.x);   // + i k_z w
             }
 #pragma unroll
@@ -874,7 +882,7 @@ __global__ __launch_bounds__(NTB) void k_z2c(Geo g_in, Z2Args a) {
     T kmag[NOF];
     if constexpr (!TAB) {
 #pragma unroll
-        for (int i = 0; i < NO; ++i) kmag[i] = kw.kmag(ee[i]);
+        for (int i = 0; i < NO; ++i) kmag[i] = kw.kmag(ee(i));
     }
     // FP32: the electrostatic spectra of species is + 1 fetched while species is transforms
     // (slot is + 1 is written only in the next iteration, after every read of it)
@@ -883,7 +891,7 @@ __global__ __launch_bounds__(NTB) void k_z2c(Geo g_in, Z2Args a) {
     auto fetch_es = [&](int is) {
         const cx<T> *esrc = reinterpret_cast<const cx<T> *>(a.specA) + (long long)is * NC + off;
 #pragma unroll
-        for (int i = 0; i < NO; ++i) evn[i] = (es && okk[i]) ? ct::gld(esrc + ti[i]) : mk<T>(T(0), T(0));
+        for (int i = 0; i < NO; ++i) evn[i] = (es && okk(i)) ? ct::gld(esrc + ti(i)) : mk<T>(T(0), T(0));
     };
     if constexpr (PF) fetch_es(0);
     for (int is = 0; is < S; ++is) {
@@ -898,8 +906,8 @@ __global__ __launch_bounds__(NTB) void k_z2c(Geo g_in, Z2Args a) {
             T w2, w3;
             if constexpr (TAB) {
                 const double *tab = g.tab64 + off;
-                w2 = ct::cld(tab + (long long)is * NC + ti[i]);
-                w3 = ct::cld(tab + (long long)(S + is) * NC + ti[i]);
+                w2 = ct::cld(tab + (long long)is * NC + ti(i));
+                w3 = ct::cld(tab + (long long)(S + is) * NC + ti(i));
             } else {
                 weight_w2_w3<T>(kmag[i], Ri, w2, w3);
             }
