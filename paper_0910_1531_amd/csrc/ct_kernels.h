@@ -816,8 +816,8 @@ __global__ __launch_bounds__(NTB) void k_z2c(Geo g_in, Z2Args a) {
     // are transformed and multiplied by i k_z after.  Transform t: 0..3 the scalars (u0..u3);
     // 4, 6 the combined x, y parts of V1, V2; 5, 7 their z parts.
     // compact layout: slots 4 and 7 already hold i k_x dPhi_x + i k_y dPhi_y and all eight inputs
-    // are plain spectra; in FP32 tiles of at most four values per thread each is fetched while the
-    // previous one transforms (FP64 and wider tiles have no registers to spare for it)
+    // are plain spectra; in FP32 tiles of at most eight values per thread each is fetched while the
+    // previous one transforms (FP64 tiles have no registers to spare for it)
     constexpr bool PF = std::is_same<T, float>::value && NO <= 8;
     constexpr int NIN = F::template nin<-1>();
     cx<T> vin[NIN];
