@@ -50,7 +50,7 @@ __device__ __forceinline__ void static_for(Fn &&f) {
 // of a vector-derivative slot adds i k_y times the transform of the y component (forward).
 template <typename T, int L, int P, int NTB, int NB, int VEC>
 __global__ __launch_bounds__(NTB) void k_yc(Geo g_in, YArgs a) {
-    using F = ct::Fft<T, typename ct::Plan<L>::type, P, NTB, false, NB>;
+    using F = ct::Fft<T, typename ct::PlanT<T, L>::type, P, NTB, false, NB>;
     // blocks per problem: one per field, or per block type of the compact vector layout
     // (VEC = YArgs::vec, a template parameter so that the plain transforms keep their registers)
     const int ntypes = VEC == 1 ? 7 : (VEC == 2 ? 8 : a.nfield);
@@ -516,7 +516,7 @@ __device__ __forceinline__ void z1_inverse(const Geo &g, const Z1Args &a, const 
 
 template <typename T, int L, int P, int NTB, int MS>
 __global__ __launch_bounds__(NTB) void k_z1c(Geo g_in, Z1Args a) {
-    using F = ct::Fft<T, typename ct::Plan<L>::type, P, NTB, false, 2>;
+    using F = ct::Fft<T, typename ct::PlanT<T, L>::type, P, NTB, false, 2>;
     constexpr int NO = F::template nout<-1>();
     static_assert(NO == F::template nin<1>(), "inverse must start where the forward ends");
     constexpr bool TAB = std::is_same<T, double>::value;
@@ -619,7 +619,7 @@ __global__ __launch_bounds__(NTB) void k_z1c(Geo g_in, Z1Args a) {
 // after reading them.
 template <typename T, int L, int P, int NTB, int MS>
 __global__ __launch_bounds__(NTB) void k_z1s(Geo g_in, Z1Args a) {
-    using F = ct::Fft<T, typename ct::Plan<L>::type, P, NTB, false, 2>;
+    using F = ct::Fft<T, typename ct::PlanT<T, L>::type, P, NTB, false, 2>;
     constexpr int NO = F::template nin<1>();
     constexpr bool TAB = std::is_same<T, double>::value;
     const int prob = (int)blockIdx.z;
@@ -694,7 +694,7 @@ __global__ __launch_bounds__(NTB) void k_z1s(Geo g_in, Z1Args a) {
 // Weights: tables in FP64, on the fly in FP32.
 template <typename T, int L, int P, int NTB>
 __global__ __launch_bounds__(NTB) void k_z2c(Geo g_in, Z2Args a) {
-    using F = ct::Fft<T, typename ct::Plan<L>::type, P, NTB, false, 2>;
+    using F = ct::Fft<T, typename ct::PlanT<T, L>::type, P, NTB, false, 2>;
     constexpr int NO = F::template nout<-1>();
     static_assert(NO == F::template nin<1>(), "inverse must start where the forward ends");
     constexpr bool TAB = std::is_same<T, double>::value;
