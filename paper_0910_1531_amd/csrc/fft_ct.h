@@ -433,9 +433,12 @@ template <> struct Plan<192> { using type = Sched<8, 8, 3>; };
 template <> struct Plan<256> { using type = Sched<8, 8, 4>; };
 template <> struct Plan<384> { using type = Sched<8, 4, 4, 3>; };
 // Schedule of the y and z transforms in precision T: FP64 tiles hold four values per thread,
-// so at length 256 the all-radix-4 schedule keeps every thread in every stage (8 x 8 x 4 would
-// leave half of them idle in the radix-8 stages while the other half hold eight values).
+// so at the power-of-two lengths 64, 128 and 256 radix-4 (and one radix-2) stages keep every
+// thread in every stage (a radix-8 stage would leave half of them idle while the other half hold
+// eight values).
 template <typename T, int L> struct PlanT { using type = typename Plan<L>::type; };
+template <> struct PlanT<double, 64> { using type = Sched<4, 4, 4>; };
+template <> struct PlanT<double, 128> { using type = Sched<4, 4, 4, 2>; };
 template <> struct PlanT<double, 256> { using type = Sched<4, 4, 4, 4>; };
 
 // Schedules of the x passes: radices of at most 4, the first (forward) being 4 and the
